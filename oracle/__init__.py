@@ -1,0 +1,29 @@
+"""FP64 CPU oracle of one-shot Parareal topology optimisation for transient heat flow.
+
+TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package. The HIP library never
+calls it and shares no code with it; the only thing both sides consume in
+common are the seeded arrays from ``workloads``.
+
+It is a plain, slow implementation written from the paper: assembled sparse
+Q1 matrices, a sparse direct solve per backward-Euler step, the sequential
+reference method, and the modified / time-reversed Parareal passes step by step
+in the paper's order. Pins against closed forms, invariants and finite
+differences live in ``tests/test_oracle_*.py``.
+
+Every function is pinned; see the tests' docstrings for which property pins
+which part.
+"""
+from .fem import (Discretisation, Problem, dirichlet_mask, element_matrices,
+                  element_nodes, simp, simp_deriv)
+from .parareal import (F_adj, F_pri, G_adj, G_pri, one_cycle, parareal_adjoint,
+                       parareal_forward)
+from .timestepping import (adjoint_sequential, adjoint_source, forward_sequential,
+                           h_adj, h_pri, pnorm_p)
+
+__all__ = [
+    "Discretisation", "Problem", "dirichlet_mask", "element_matrices",
+    "element_nodes", "simp", "simp_deriv", "F_adj", "F_pri", "G_adj", "G_pri",
+    "one_cycle", "parareal_adjoint", "parareal_forward", "adjoint_sequential",
+    "adjoint_source", "forward_sequential", "h_adj", "h_pri", "pnorm_p",
+]
