@@ -1,0 +1,159 @@
+/*
+ * pt.h -- C ABI of the MI355X (gfx950) hot path of one-shot Parareal topology
+ * optimisation for transient heat conduction (Appel & Alexandersen).
+ *
+ * One optimisation cycle is three calls on one HIP stream:
+ *   pt_parareal_forward   modified Parareal for (T, theta)            Sec. 4.3-4.4, Alg. 1
+ *   pt_parareal_adjoint   time-reversed vanilla Parareal for lambda   Sec. 4.4, Alg. 2, Eq. 4.9
+ *   pt_sensitivities      grad Theta = g_1                            Eq. 4.8, Eq. 4.10
+ *
+ * Discretisation (Sec. 2.2): unit square, nx x ny rectangular bilinear (Q1)
+ * elements, hx = 1/nx, hy = 1/ny, out-of-plane depth 1, element-wise constant
+ * k(rho), c(rho) by SIMP (Eq. 2.5-2.6) and uniform source q(t); consistent
+ * (Galerkin) capacity matrix; backward Euler with dt = t_final/n_steps
+ * (Eq. 2.7); T = 0 on a set of Dirichlet nodes (rows and columns eliminated),
+ * insulated elsewhere, T_0 = 0.
+ *
+ * Layouts: node (i, j) has index j*(nx+1)+i, element (ex, ey) index ey*nx+ex,
+ * both row-major with x fastest. All arrays are contiguous FP64.
+ *
+ * Ownership: every array argument is a DEVICE pointer owned by the caller,
+ * except the two fields of pt_problem marked HOST. The library allocates no
+ * device memory: all scratch lives in the caller's workspace `ws`
+ * (pt_workspace_bytes). It keeps no global state between calls; state that
+ * flows from one call to the next of the same cycle lives in `ws`. Calls are
+ * stream-ordered and asynchronous, except where noted; calls that overlap on
+ * the same `ws` race.
+ *
+ * Errors: every entry point returns PT_OK (0) or a negative code. Argument
+ * checks run on the host before anything is enqueued. Solver and domain
+ * problems found on the device (a CG solve reaching max_iter, Theta <= 0,
+ * non-finite values) are recorded in `ws` and reported by pt_query_status.
+ */
+#ifndef PT_H
+#define PT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PT_OK = 0,
+    PT_EINVAL = -1,   /* invalid argument (sizes, N_tau not dividing N_t, odd p, NULL, aliasing) */
+    PT_ENOMEM = -2,   /* workspace smaller than pt_workspace_bytes()                              */
+    PT_EHIP = -3,     /* HIP runtime error (launch, copy, co-residency)                           */
+    PT_ENOCONV = -4,  /* some CG solve stopped at max_iter; outputs were still written            */
+    PT_EDOMAIN = -5,  /* non-finite input/result or Theta <= 0                                    */
+    PT_ESTATE = -6    /* call order violated (adjoint before forward, sensitivities before adjoint) */
+};
+
+/* Dirichlet node sets */
+enum {
+    PT_BC_LEFT_CENTRE = 0,   /* x = 0, 0.45 <= y <= 0.55: node (0,j) with 9 ny <= 20 j <= 11 ny */
+    PT_BC_BOTTOM_CENTRE = 1, /* y = 0, 0.45 <= x <= 0.55 (the paper's Fig. 4 test case)         */
+    PT_BC_NONE = 2,          /* no Dirichlet node (then C/dt + K is still SPD)                  */
+    PT_BC_MASK = 3           /* explicit HOST mask, one byte per node, non-zero = T fixed at 0  */
+};
+
+enum { PT_FP64 = 0, PT_FP32_REFINE = 1 };
+enum { PT_JACOBI = 0, PT_GMG = 1 };
+enum { PT_STORE_ALL = 0, PT_CHECKPOINT = 1 };
+
+typedef struct pt_problem {
+    int32_t nx, ny;            /* elements along x and y, >= 1                                   */
+    double k0, kmin, pk;       /* k(rho) = kmin + (k0 - kmin) rho^pk            (Eq. 2.6)         */
+    double c0, cmin, pc;       /* c(rho) = cmin + (c0 - cmin) rho^pc            (Eq. 2.5)         */
+    double q;                  /* uniform source, used when q_t == NULL                           */
+    const double *q_t;         /* HOST, optional: q(t_n) for n = 0..n_steps (uniform in space)    */
+    double t_final;            /* t_T > 0; dt = t_T / n_steps, dtau = t_T / n_slices              */
+    int32_t n_steps;           /* N_t >= 1                                                        */
+    int32_t n_slices;          /* N_tau >= 1, must divide N_t; M = N_t / N_tau      (Sec. 4.2)    */
+    int32_t pnorm;             /* p, even >= 2                                      (Eq. 2.9)     */
+    int32_t iterations;        /* Parareal iterations per pass, >= 1 (1 = one-shot, Alg. 3)       */
+    double cg_rtol;            /* stop when ||b - A x||_2 <= cg_rtol ||b||_2, per system, > 0     */
+    int32_t max_iter;          /* CG iteration cap per solve, >= 1                                */
+    int32_t precision;         /* PT_FP64 (only value accepted by this build)                     */
+    int32_t precond;           /* PT_JACOBI (only value accepted by this build)                   */
+    int32_t storage;           /* PT_STORE_ALL (only value accepted by this build)                */
+    int32_t bc;                /* PT_BC_*                                                         */
+    const uint8_t *dirichlet_mask; /* HOST, (nx+1)(ny+1) bytes, read when bc == PT_BC_MASK        */
+} pt_problem;
+
+typedef struct pt_stats {
+    int32_t status;            /* PT_OK, PT_ENOCONV or PT_EDOMAIN: first device-side problem     */
+    int32_t max_cg_iters;      /* largest CG iteration count of any solve of the last pass       */
+    int64_t cg_iters_fine;     /* total CG iterations of fine solves (forward + adjoint)          */
+    int64_t cg_iters_coarse;   /* total CG iterations of coarse solves (cold, batched, sweep)    */
+    int64_t solves_fine;
+    int64_t solves_coarse;
+    double max_rel_residual;   /* largest final ||r|| / ||b|| (recursive residual) of any solve  */
+} pt_stats;
+
+/* Bytes of device workspace the three calls need for this problem; 0 if the
+ * problem is invalid (pt_validate gives the reason). */
+size_t pt_workspace_bytes(const pt_problem *prob);
+
+/* Host-side argument check only; returns PT_OK or PT_EINVAL. */
+int pt_validate(const pt_problem *prob);
+
+/*
+ * Primal pass: Parareal for u_n = (T_{Mn}, theta_{Mn}), n = 0..N_tau (Sec. 4.4,
+ * Eq. 4.2 correction applied to T and theta; G_pri = Alg. 1 with dt -> dtau,
+ * N_t -> N_tau, load at tau_{n+1}).
+ *   rho          [N_e]              design, finite, >= 0 (rho^p with non-integer p needs rho >= 0)
+ *   guess_T      [N_tau+1][N_n]     warm-restart guess u^k (Alg. 3), or NULL: cold start from the
+ *                                   coarse sweep u^0_{n+1} = G(u^0_n) (Sec. 5.2)
+ *   guess_theta  [N_tau+1]          theta part of the guess; NULL iff guess_T is NULL
+ *   S            [N_t][N_n]         out: T_1..T_{N_t}; coarse slots T_{Mn} corrected, the other
+ *                                   slots the fine states of the last F sweep (Sec. 4.3)
+ *   uT_out       [N_tau+1][N_n]     out: corrected T_{Mn} (the next cycle's guess); may be NULL
+ *   utheta_out   [N_tau+1]          out: corrected theta_{Mn}; may be NULL
+ *   Theta_out    [1]                out: Theta = theta_{N_t} estimate (device scalar)
+ * guess arrays must not overlap any output. Returns PT_OK once enqueued.
+ */
+int pt_parareal_forward(const pt_problem *prob, const double *rho, const double *guess_T,
+                        const double *guess_theta, double *S, double *uT_out,
+                        double *utheta_out, double *Theta_out, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/*
+ * Adjoint pass: reversed Parareal for v_n = (lambda_{Mn+1}, g_{Mn+1}), v_{N_tau} = 0
+ * (Sec. 4.4, Eq. 4.9; H_adj = Alg. 2 with source Theta^{1-p}/N_e T_n^{o(p-1)}, Eq. 4.6;
+ * G_adj = Alg. 2 with dt -> dtau, N_t -> N_tau, n+-1 -> n+-M, so the coarse step from
+ * v_n uses source and T at fine index m = M(n-1)+1 and T_{m-M} (T_0 = 0 if m-M < 0)).
+ *   S, Theta       from pt_parareal_forward of the same cycle (unchanged since)
+ *   guess_lambda   [N_tau+1][N_n]  lambda_{Mn+1} guesses (previous cycle's lambda_out), or NULL
+ *                                  for the cold sweep v^0_{n-1} = G(v^0_n); row N_tau is ignored
+ *   lambda_out     [N_tau+1][N_n]  out: corrected lambda_{Mn+1}, row N_tau = 0; may be NULL
+ * The g part of a guess cancels in the correction, so only lambda is taken.
+ * Leaves the per-element sensitivity sums in ws for pt_sensitivities.
+ */
+int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double *S,
+                        const double *Theta, const double *guess_lambda, double *lambda_out,
+                        void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * grad Theta = g-part of v_0 (Sec. 4.4 step 4):
+ *   dTheta_drho[e] = -(1/N_t) sum_fine lambda_j,e^T (dC/drho_e (T_j - T_{j-1})/dt + dK/drho_e T_j)
+ *                    - (1/N_tau) (coarse-correction terms)          (Eq. 4.8, Eq. 4.10)
+ *   dTheta_drho    [N_e] out
+ */
+int pt_sensitivities(const pt_problem *prob, const double *rho, const void *ws,
+                     size_t ws_bytes, double *dTheta_drho, hipStream_t stream);
+
+/* Synchronises `stream`, then reads the device status and counters in ws. */
+int pt_query_status(const void *ws, hipStream_t stream, pt_stats *out);
+
+/* Static string for a return code. */
+const char *pt_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PT_H */

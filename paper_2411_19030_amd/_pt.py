@@ -1,0 +1,219 @@
+"""ctypes binding of libpt (include/pt.h): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; this module converts
+torch device tensors to pointers and a Python problem description to the C
+struct. It raises if the library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpt.so")
+
+PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ENOCONV, PT_EDOMAIN, PT_ESTATE = 0, -1, -2, -3, -4, -5, -6
+PT_BC = {"left_centre": 0, "bottom_centre": 1, "none": 2, "mask": 3}
+PT_FP64, PT_FP32_REFINE = 0, 1
+PT_JACOBI, PT_GMG = 0, 1
+PT_STORE_ALL, PT_CHECKPOINT = 0, 1
+
+EXPORTS = ["pt_workspace_bytes", "pt_validate", "pt_parareal_forward", "pt_parareal_adjoint",
+           "pt_sensitivities", "pt_query_status", "pt_strerror"]
+
+
+class PtProblem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("k0", ctypes.c_double), ("kmin", ctypes.c_double), ("pk", ctypes.c_double),
+        ("c0", ctypes.c_double), ("cmin", ctypes.c_double), ("pc", ctypes.c_double),
+        ("q", ctypes.c_double), ("q_t", ctypes.POINTER(ctypes.c_double)),
+        ("t_final", ctypes.c_double),
+        ("n_steps", ctypes.c_int32), ("n_slices", ctypes.c_int32),
+        ("pnorm", ctypes.c_int32), ("iterations", ctypes.c_int32),
+        ("cg_rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("precond", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("bc", ctypes.c_int32),
+        ("dirichlet_mask", ctypes.POINTER(ctypes.c_uint8)),
+    ]
+
+
+class PtStats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("max_cg_iters", ctypes.c_int32),
+        ("cg_iters_fine", ctypes.c_int64), ("cg_iters_coarse", ctypes.c_int64),
+        ("solves_fine", ctypes.c_int64), ("solves_coarse", ctypes.c_int64),
+        ("max_rel_residual", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpt.so; raises RuntimeError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libpt.so not found at {path}: build it with "
+                           "`python -m paper_2411_19030_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER(PtProblem)
+    vp = ctypes.c_void_p
+    lib.pt_workspace_bytes.argtypes = [P]
+    lib.pt_workspace_bytes.restype = ctypes.c_size_t
+    lib.pt_validate.argtypes = [P]
+    lib.pt_validate.restype = ctypes.c_int
+    lib.pt_parareal_forward.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.pt_parareal_forward.restype = ctypes.c_int
+    lib.pt_parareal_adjoint.argtypes = [P, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.pt_parareal_adjoint.restype = ctypes.c_int
+    lib.pt_sensitivities.argtypes = [P, vp, vp, ctypes.c_size_t, vp, vp]
+    lib.pt_sensitivities.restype = ctypes.c_int
+    lib.pt_query_status.argtypes = [vp, vp, ctypes.POINTER(PtStats)]
+    lib.pt_query_status.restype = ctypes.c_int
+    lib.pt_strerror.argtypes = [ctypes.c_int]
+    lib.pt_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class PtError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = load_library().pt_strerror(code).decode()
+        super().__init__(f"{where}: {msg} ({code})")
+        self.code = code
+
+
+@dataclass
+class Problem:
+    """Python mirror of pt_problem (field meanings in include/pt.h)."""
+    nx: int
+    ny: int
+    n_steps: int
+    n_slices: int
+    pnorm: int = 8
+    k0: float = 1.0
+    kmin: float = 1e-3
+    pk: float = 3.0
+    c0: float = 1.0
+    cmin: float = 1.0
+    pc: float = 1.0
+    q: object = 1.0           # float, or array of q(t_n), n = 0..n_steps
+    t_final: float = 1.0
+    iterations: int = 1
+    cg_rtol: float = 1e-10
+    max_iter: int = 10000
+    precision: int = PT_FP64
+    precond: int = PT_JACOBI
+    storage: int = PT_STORE_ALL
+    bc: object = "left_centre"  # name or boolean/uint8 node mask
+    _keep: list = field(default_factory=list, repr=False, compare=False)
+
+    @property
+    def n_nodes(self) -> int:
+        return (self.nx + 1) * (self.ny + 1)
+
+    @property
+    def n_elem(self) -> int:
+        return self.nx * self.ny
+
+    def to_c(self) -> PtProblem:
+        c = PtProblem()
+        c.nx, c.ny = int(self.nx), int(self.ny)
+        c.k0, c.kmin, c.pk = float(self.k0), float(self.kmin), float(self.pk)
+        c.c0, c.cmin, c.pc = float(self.c0), float(self.cmin), float(self.pc)
+        self._keep.clear()
+        if np.isscalar(self.q):
+            c.q = float(self.q)
+            c.q_t = ctypes.POINTER(ctypes.c_double)()
+        else:
+            qa = np.ascontiguousarray(self.q, dtype=np.float64)
+            self._keep.append(qa)
+            c.q = float("nan")
+            c.q_t = qa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        c.t_final = float(self.t_final)
+        c.n_steps, c.n_slices = int(self.n_steps), int(self.n_slices)
+        c.pnorm, c.iterations = int(self.pnorm), int(self.iterations)
+        c.cg_rtol, c.max_iter = float(self.cg_rtol), int(self.max_iter)
+        c.precision, c.precond, c.storage = int(self.precision), int(self.precond), int(self.storage)
+        if isinstance(self.bc, str):
+            c.bc = PT_BC[self.bc]
+            c.dirichlet_mask = ctypes.POINTER(ctypes.c_uint8)()
+        else:
+            m = np.ascontiguousarray(np.asarray(self.bc).astype(np.uint8))
+            self._keep.append(m)
+            c.bc = PT_BC["mask"]
+            c.dirichlet_mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        return c
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    return int(stream)
+
+
+def _check(rc: int, where: str):
+    if rc != PT_OK:
+        raise PtError(rc, where)
+
+
+def pt_validate(prob: Problem) -> int:
+    return load_library().pt_validate(ctypes.byref(prob.to_c()))
+
+
+def pt_workspace_bytes(prob: Problem) -> int:
+    return int(load_library().pt_workspace_bytes(ctypes.byref(prob.to_c())))
+
+
+def pt_parareal_forward(prob: Problem, rho, guess_T, guess_theta, S, uT_out, utheta_out,
+                        Theta_out, ws, stream=None, check: bool = True) -> int:
+    c = prob.to_c()
+    rc = load_library().pt_parareal_forward(
+        ctypes.byref(c), _ptr(rho), _ptr(guess_T), _ptr(guess_theta), _ptr(S), _ptr(uT_out),
+        _ptr(utheta_out), _ptr(Theta_out), _ptr(ws), ws.numel() * ws.element_size(),
+        _stream(stream))
+    if check:
+        _check(rc, "pt_parareal_forward")
+    return rc
+
+
+def pt_parareal_adjoint(prob: Problem, rho, S, Theta, guess_lambda, lambda_out, ws,
+                        stream=None, check: bool = True) -> int:
+    c = prob.to_c()
+    rc = load_library().pt_parareal_adjoint(
+        ctypes.byref(c), _ptr(rho), _ptr(S), _ptr(Theta), _ptr(guess_lambda), _ptr(lambda_out),
+        _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
+    if check:
+        _check(rc, "pt_parareal_adjoint")
+    return rc
+
+
+def pt_sensitivities(prob: Problem, rho, ws, dTheta_drho, stream=None, check: bool = True) -> int:
+    c = prob.to_c()
+    rc = load_library().pt_sensitivities(
+        ctypes.byref(c), _ptr(rho), _ptr(ws), ws.numel() * ws.element_size(), _ptr(dTheta_drho),
+        _stream(stream))
+    if check:
+        _check(rc, "pt_sensitivities")
+    return rc
+
+
+def pt_query_status(ws, stream=None) -> dict:
+    st = PtStats()
+    _check(load_library().pt_query_status(_ptr(ws), _stream(stream), ctypes.byref(st)),
+           "pt_query_status")
+    return {k: getattr(st, k) for k, _ in PtStats._fields_}

@@ -1,0 +1,987 @@
+// Lane engine: one persistent cooperative launch runs every propagator of one
+// Parareal pass (Sec. 4.2-4.4) on gfx950.
+//
+// A *lane* is a sequence of backward-Euler solves (C/delta + K) x = b executed
+// by a fixed group of workgroups: the fine propagator of one time slice (M
+// steps of Alg. 1 or Alg. 2 with dt), one batched coarse step G(u^k_n), the
+// cold coarse sweep, or the sequential correction sweep (Eq. 4.2 / Eq. 4.9).
+// All lanes of a pass run concurrently; a lane waits on a device flag only
+// where the method has a true data dependence (the sweep step n needs F_n and
+// G(u^k_n); a cold-started slice needs its coarse guess). The sequential
+// coarse sweep therefore overlaps the bandwidth-bound fine slices instead of
+// following them.
+//
+// Each solve is a Jacobi-preconditioned conjugate gradient in the single-
+// reduction form of Chronopoulos and Gear: one group barrier per iteration,
+// which both publishes the halo values of the iteration's vectors and combines
+// the three dot products (r,z), (z,Az), (r,r). The workgroups of a group own
+// contiguous node ranges ("tiles") of the lane's vectors; every tile is staged
+// in LDS with a halo of one grid row plus one node on each side, so the 9-point
+// Q1 stencil reads LDS only. The halo values of z = D^{-1} r_{i+1} are
+// recomputed locally from r_i, w_i, s_{i-1} (pointwise), which is why one
+// barrier per iteration suffices. Vectors that neighbours read in the same
+// round are double-buffered by iteration parity.
+//
+// Control state (step, phase, alpha, beta, theta ...) is replicated: every
+// workgroup of a group reduces the same partial sums in the same order and
+// takes the same decisions, so no broadcast is needed. Reductions are
+// deterministic (fixed order), so results are bitwise reproducible.
+#include "pt_internal.h"
+
+namespace pt {
+
+namespace {
+
+enum Phase : int { PH_INIT = 0, PH_FIRST = 1, PH_ITER = 2, PH_POST = 3, PH_DONE = 4 };
+
+constexpr int kWaves = kThreads / 64;
+
+__device__ __forceinline__ double ipow(double x, int n) {
+    double r = 1.0, b = x;
+    while (n) {
+        if (n & 1) r *= b;
+        b *= b;
+        n >>= 1;
+    }
+    return r;
+}
+
+__device__ __forceinline__ long long now_ticks() {
+    return (long long)__builtin_amdgcn_s_memrealtime();
+}
+
+__device__ __forceinline__ void set_status(Control *ctl, int code) {
+    atomicCAS(&ctl->status, 0, code);
+}
+
+__device__ __forceinline__ bool aborted(Control *ctl) {
+    return __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// Group barrier: counter += 1 per workgroup; wait until it reaches target.
+// Returns false if the wait timed out or another workgroup aborted.
+__device__ bool group_barrier(unsigned *cnt, unsigned target, Control *ctl, long long timeout) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        long long t0 = now_ticks();
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (aborted(ctl) || now_ticks() - t0 > timeout) {
+                ok = 0;
+                break;
+            }
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// Wait until flags[idx] == epoch (set by a producer group's leader).
+__device__ bool wait_flag(unsigned *flags, int idx, unsigned epoch, Control *ctl,
+                          long long timeout) {
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        long long t0 = now_ticks();
+        while (__hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+               epoch) {
+            __builtin_amdgcn_s_sleep(2);
+            if (aborted(ctl) || now_ticks() - t0 > timeout) {
+                ok = 0;
+                break;
+            }
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+__device__ void set_flag(unsigned *flags, int idx, unsigned epoch) {
+    // called by thread 0 of the group leader after a group barrier
+    __threadfence();
+    __hip_atomic_store(&flags[idx], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int flag_index(int kind, int n) { return kind * 4096 + n; }
+
+// Deterministic block sum of Q values; every thread receives the totals.
+template <int Q>
+__device__ void block_sum(double (&v)[Q], double *red) {
+    for (int q = 0; q < Q; ++q) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[q] = x;
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < Q; ++q) red[wave * Q + q] = v[q];
+    __syncthreads();
+    for (int q = 0; q < Q; ++q) {
+        double t = 0.0;
+        for (int w = 0; w < kWaves; ++w) t += red[w * Q + q];
+        v[q] = t;
+    }
+    __syncthreads();
+}
+
+// Sum partials[0..g)[0..Q) in a fixed order (identical in every workgroup).
+template <int Q>
+__device__ void group_sum(const double *part, int g, double (&out)[Q], double *red) {
+    double v[Q];
+    for (int q = 0; q < Q; ++q) v[q] = 0.0;
+    for (int r = threadIdx.x; r < g; r += kThreads)
+        for (int q = 0; q < Q; ++q) v[q] += part[r * 4 + q];
+    block_sum<Q>(v, red);
+    for (int q = 0; q < Q; ++q) out[q] = v[q];
+}
+
+// Nine stencil coefficients of node (i, j): mass part scaled by ms (= 1/delta
+// or 0), conductivity part scaled by ks (1 or 0). Element contributions follow
+// the bilinear element matrices of an hx x hy rectangle: per element with
+// m = c hx hy/(36 delta) and kap = k/6, self 4m + kap e_self, x-neighbour
+// 2m + kap e_x, y-neighbour 2m + kap e_y, diagonal m + kap e_d.
+struct Coef {
+    double c, e, w, n, s, ne, nw, se, sw;
+};
+
+__device__ __forceinline__ Coef node_coef(const Consts &C, const double *kq, const double *cm,
+                                          int i, int j, double ms, double ks) {
+    const int eSW = j * C.EW + i, eSE = eSW + 1, eNW = eSW + C.EW, eNE = eNW + 1;
+    const double mSW = cm[eSW] * ms, mSE = cm[eSE] * ms, mNW = cm[eNW] * ms, mNE = cm[eNE] * ms;
+    const double kSW = kq[eSW] * ks, kSE = kq[eSE] * ks, kNW = kq[eNW] * ks, kNE = kq[eNE] * ks;
+    Coef a;
+    a.c = 4.0 * (mSW + mSE + mNW + mNE) + C.e_self * (kSW + kSE + kNW + kNE);
+    a.e = 2.0 * (mSE + mNE) + C.e_x * (kSE + kNE);
+    a.w = 2.0 * (mSW + mNW) + C.e_x * (kSW + kNW);
+    a.n = 2.0 * (mNW + mNE) + C.e_y * (kNW + kNE);
+    a.s = 2.0 * (mSW + mSE) + C.e_y * (kSW + kSE);
+    a.ne = mNE + C.e_d * kNE;
+    a.nw = mNW + C.e_d * kNW;
+    a.se = mSE + C.e_d * kSE;
+    a.sw = mSW + C.e_d * kSW;
+    return a;
+}
+
+__device__ __forceinline__ double apply(const Coef &a, const double *L, int li, int W) {
+    return a.c * L[li] + a.e * L[li + 1] + a.w * L[li - 1] + a.n * L[li + W] + a.s * L[li - W] +
+           a.ne * L[li + W + 1] + a.nw * L[li + W - 1] + a.se * L[li - W + 1] +
+           a.sw * L[li - W - 1];
+}
+
+// lambda^T K0 T and lambda^T C0 D of one element (unit k and c), local node
+// order (ex,ey), (ex+1,ey), (ex+1,ey+1), (ex,ey+1).
+__device__ __forceinline__ double elem_k(const Consts &C, double l0, double l1, double l2,
+                                         double l3, double t0, double t1, double t2, double t3) {
+    const double self = l0 * t0 + l1 * t1 + l2 * t2 + l3 * t3;
+    const double xa = l0 * t1 + l1 * t0 + l2 * t3 + l3 * t2;
+    const double ya = l0 * t3 + l3 * t0 + l1 * t2 + l2 * t1;
+    const double dg = l0 * t2 + l2 * t0 + l1 * t3 + l3 * t1;
+    return (C.e_self * self + C.e_x * xa + C.e_y * ya + C.e_d * dg) * (1.0 / 6.0);
+}
+
+__device__ __forceinline__ double elem_c(const Consts &C, double l0, double l1, double l2,
+                                         double l3, double d0, double d1, double d2, double d3) {
+    const double self = l0 * d0 + l1 * d1 + l2 * d2 + l3 * d3;
+    const double adj = l0 * d1 + l1 * d0 + l2 * d3 + l3 * d2 + l0 * d3 + l3 * d0 + l1 * d2 +
+                       l2 * d1;
+    const double dg = l0 * d2 + l2 * d0 + l1 * d3 + l3 * d1;
+    return C.cm_unit * (4.0 * self + 2.0 * adj + dg);
+}
+
+// Per-lane, per-step description derived identically in every workgroup.
+struct StepInfo {
+    bool fine;        // delta = dt (else dtau)
+    bool adjoint;
+    int n;            // coarse index of coarse kinds / slice of fine kinds
+    int j;            // fine time index: load index (primal) or source index (adjoint)
+    int jprev;        // adjoint: index of T_{j-1} or T_{m-M} (<= 0 means T_0 = 0)
+    const double *tp_src;  // vector for C/delta * tp (RHS), never written this round
+    const double *x0_src;  // initial guess; nullptr means "x already holds it"
+    bool wait;        // a flag must be awaited before INIT
+    int wait_idx;
+};
+
+__device__ __forceinline__ int lane_steps(const Consts &C, int kind) {
+    switch (kind) {
+        case F_PRI:
+        case F_ADJ: return C.M;
+        case GK_PRI:
+        case GK_ADJ: return 1;
+        case SWEEP_PRI:
+        case SWEEP_ADJ: return C.Ntau - 1;
+        default: return C.Ntau;  // cold sweeps
+    }
+}
+
+__device__ __forceinline__ double *lane_vec(const Bufs &B, const Consts &C, int vec, int which) {
+    return B.pool + ((size_t)vec * kVecsPerLane + which) * (size_t)C.Nn;
+}
+enum { V_X = 0, V_P = 1, V_R0 = 2, V_R1 = 3, V_W0 = 4, V_W1 = 5, V_S0 = 6, V_S1 = 7, V_TP = 8 };
+
+__device__ StepInfo step_info(const Consts &C, const Bufs &B, const LaunchInfo &I, const Lane &L,
+                              int s) {
+    StepInfo st;
+    const size_t Nn = C.Nn;
+    const double *tpbuf = lane_vec(B, C, L.vec, V_TP);
+    st.wait = false;
+    st.wait_idx = 0;
+    st.jprev = 0;
+    switch (L.kind) {
+        case F_PRI: {
+            const int n = L.slice;
+            st.fine = true;
+            st.adjoint = false;
+            st.n = n;
+            st.j = C.M * n + s + 1;
+            if (s == 0) {
+                const double *src;
+                if (I.cold) {
+                    src = (n == 0) ? B.zero : B.Gk + (size_t)(n - 1) * Nn;
+                    if (n > 0) {
+                        st.wait = true;
+                        st.wait_idx = flag_index(FL_COLD, n - 1);
+                    }
+                } else {
+                    src = (n == 0) ? B.zero : B.in_T + (size_t)n * Nn;
+                }
+                st.tp_src = src;
+                st.x0_src = src;
+            } else {
+                st.tp_src = tpbuf;
+                st.x0_src = nullptr;
+            }
+            break;
+        }
+        case GK_PRI: {
+            const int n = L.slice;
+            st.fine = false;
+            st.adjoint = false;
+            st.n = n;
+            st.j = C.M * (n + 1);
+            st.tp_src = B.in_T + (size_t)n * Nn;
+            st.x0_src = B.in_T + (size_t)(n + 1) * Nn;
+            break;
+        }
+        case COLD_PRI: {
+            const int n = s;
+            st.fine = false;
+            st.adjoint = false;
+            st.n = n;
+            st.j = C.M * (n + 1);
+            if (n == 0) {
+                st.tp_src = B.zero;
+                st.x0_src = B.zero;
+            } else {
+                st.tp_src = tpbuf;
+                st.x0_src = nullptr;
+            }
+            break;
+        }
+        case SWEEP_PRI: {
+            const int n = s + 1;
+            st.fine = false;
+            st.adjoint = false;
+            st.n = n;
+            st.j = C.M * (n + 1);
+            st.tp_src = (n == 1) ? B.S + (size_t)(C.M - 1) * Nn : tpbuf;
+            st.x0_src = B.Gk + (size_t)n * Nn;
+            break;
+        }
+        case F_ADJ: {
+            const int n = L.slice;
+            st.fine = true;
+            st.adjoint = true;
+            st.n = n;
+            st.j = C.M * n - s;
+            st.jprev = st.j - 1;
+            if (s == 0) {
+                const double *src;
+                if (n == C.Ntau) {
+                    src = B.zero;
+                } else if (I.cold) {
+                    src = B.Gk + (size_t)(n + 1) * Nn;
+                    st.wait = true;
+                    st.wait_idx = flag_index(FL_COLD, n + 1);
+                } else {
+                    src = B.in_L + (size_t)n * Nn;
+                }
+                st.tp_src = src;
+                st.x0_src = src;
+            } else {
+                st.tp_src = tpbuf;
+                st.x0_src = nullptr;
+            }
+            break;
+        }
+        case GK_ADJ: {
+            const int n = L.slice;
+            st.fine = false;
+            st.adjoint = true;
+            st.n = n;
+            st.j = C.M * (n - 1) + 1;
+            st.jprev = st.j - C.M;
+            st.tp_src = B.in_L + (size_t)n * Nn;
+            st.x0_src = B.in_L + (size_t)(n - 1) * Nn;
+            break;
+        }
+        case COLD_ADJ: {
+            const int n = C.Ntau - s;
+            st.fine = false;
+            st.adjoint = true;
+            st.n = n;
+            st.j = C.M * (n - 1) + 1;
+            st.jprev = st.j - C.M;
+            if (n == C.Ntau) {
+                st.tp_src = B.zero;
+                st.x0_src = B.zero;
+            } else {
+                st.tp_src = tpbuf;
+                st.x0_src = nullptr;
+            }
+            break;
+        }
+        default: {  // SWEEP_ADJ
+            const int n = C.Ntau - 1 - s;
+            st.fine = false;
+            st.adjoint = true;
+            st.n = n;
+            st.j = C.M * (n - 1) + 1;
+            st.jprev = st.j - C.M;
+            st.tp_src = (n == C.Ntau - 1) ? lane_vec(B, C, B.fvec[C.Ntau], V_X) : tpbuf;
+            st.x0_src = B.Gk + (size_t)n * Nn;
+            break;
+        }
+    }
+    return st;
+}
+
+struct Ctl {
+    int step, nsteps, phase, iter, it_local, restarts;
+    bool verifying, zero_x;
+    double alpha, beta, gamma;
+    double bnorm, relres;
+    double theta;      // primal: theta carried by the lane
+    double src_scale;  // adjoint: Theta^{1-p} / N_e
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Setup kernels
+// ---------------------------------------------------------------------------
+
+// Material (Eq. 2.5-2.6): padded k/6 and c hx hy/36, derivatives k', c'.
+__global__ void k_material(Consts C, const double *rho, double *kq, double *cm, double *dk,
+                           double *dc, double k0, double kmin, double pk, double c0, double cmin,
+                           double pc, Control *ctl) {
+    const int EH = C.ny + 2;
+    const int total = EH * C.EW;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+        const int py = t / C.EW, px = t - py * C.EW;
+        const int ex = px - 1, ey = py - 1;
+        double kv = 0.0, cv = 0.0;
+        if (ex >= 0 && ex < C.nx && ey >= 0 && ey < C.ny) {
+            const int e = ey * C.nx + ex;
+            const double r = rho[e];
+            if (!(r >= 0.0) || !isfinite(r)) set_status(ctl, -5);
+            const double rr = r > 0.0 ? r : 0.0;
+            const double kk = kmin + (k0 - kmin) * pow(rr, pk);
+            const double cc = cmin + (c0 - cmin) * pow(rr, pc);
+            dk[e] = pk * (k0 - kmin) * pow(rr, pk - 1.0);
+            dc[e] = pc * (c0 - cmin) * pow(rr, pc - 1.0);
+            kv = kk * (1.0 / 6.0);
+            cv = cc * C.cm_unit;
+        }
+        kq[t] = kv;
+        cm[t] = cv;
+    }
+}
+
+// Jacobi inverse diagonals of C/dt + K and C/dtau + K (0 on Dirichlet nodes).
+__global__ void k_diag(Consts C, const double *kq, const double *cm, const unsigned char *mask,
+                       double *dinv_f, double *dinv_c) {
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < C.Nn; id += gridDim.x * blockDim.x) {
+        const int j = id / C.W, i = id - j * C.W;
+        const Coef af = node_coef(C, kq, cm, i, j, C.inv_dt, 1.0);
+        const Coef ac = node_coef(C, kq, cm, i, j, C.inv_dtau, 1.0);
+        const bool d = mask[id] != 0;
+        dinv_f[id] = d ? 0.0 : 1.0 / af.c;
+        dinv_c[id] = d ? 0.0 : 1.0 / ac.c;
+    }
+}
+
+// Dirichlet masks of the standard rules (PT_BC_*).
+__global__ void k_mask_rule(Consts C, int rule, unsigned char *mask) {
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < C.Nn; id += gridDim.x * blockDim.x) {
+        const int j = id / C.W, i = id - j * C.W;
+        unsigned char m = 0;
+        if (rule == 0) m = (i == 0 && 9 * C.ny <= 20 * j && 20 * j <= 11 * C.ny) ? 1 : 0;
+        if (rule == 1) m = (j == 0 && 9 * C.nx <= 20 * i && 20 * i <= 11 * C.nx) ? 1 : 0;
+        mask[id] = m;
+    }
+}
+
+__global__ void k_fill_u32(unsigned *p, size_t n, unsigned v) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x)
+        p[t] = v;
+}
+
+__global__ void k_fill_f64(double *p, size_t n, double v) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x)
+        p[t] = v;
+}
+
+__global__ void k_copy_f64(double *dst, const double *src, size_t n) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x)
+        dst[t] = src[t];
+}
+
+// ---------------------------------------------------------------------------
+// The engine
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInfo I) {
+    extern __shared__ double lds[];
+    __shared__ double red[kWaves * 4];
+
+    const int lane_id = B.wg_lane[blockIdx.x];
+    if (lane_id < 0) return;
+    const Lane L = B.lanes[lane_id];
+    const int rank = blockIdx.x - L.wg0;
+    const int g = L.nwg;
+    const int H = C.W + 1;           // halo on each side of a tile window
+    const int TS = L.tile;
+    const int win = TS + 2 * H;
+    double *LA = lds;                // window A
+    double *LB = lds + win;          // window B (INIT only)
+    const int ntiles = (C.Nn + TS - 1) / TS;
+    Control *ctl = B.ctl;
+    unsigned *bar = B.bar + lane_id;
+    double *part = B.partials + (size_t)lane_id * 2 * kMaxGroup * 4;
+    unsigned nbar = 0;
+
+    double *X = lane_vec(B, C, L.vec, V_X);
+    double *P = lane_vec(B, C, L.vec, V_P);
+    double *TP = lane_vec(B, C, L.vec, V_TP);
+    double *Rb[2] = {lane_vec(B, C, L.vec, V_R0), lane_vec(B, C, L.vec, V_R1)};
+    double *Wb[2] = {lane_vec(B, C, L.vec, V_W0), lane_vec(B, C, L.vec, V_W1)};
+    double *Sb[2] = {lane_vec(B, C, L.vec, V_S0), lane_vec(B, C, L.vec, V_S1)};
+
+    Ctl c;
+    c.step = 0;
+    c.nsteps = lane_steps(C, L.kind);
+    c.phase = c.nsteps > 0 ? PH_INIT : PH_DONE;
+    c.iter = 0;
+    c.it_local = 0;
+    c.restarts = 0;
+    c.verifying = false;
+    c.zero_x = false;
+    c.alpha = c.beta = c.gamma = 0.0;
+    c.bnorm = c.relres = 0.0;
+    c.theta = 0.0;
+    c.src_scale = 0.0;
+    const bool is_adj = L.kind >= F_ADJ;
+    if (is_adj) {
+        const double Th = *B.Theta;
+        c.src_scale = pow(Th, 1.0 - C.p) / (double)C.Ne;
+        if (!(Th > 0.0) || !isfinite(Th)) set_status(ctl, -5);
+    }
+    // initial theta of primal lanes
+    if (L.kind == F_PRI) {
+        // a cold-started slice reads its theta after its flag wait (INIT)
+        if (L.slice > 0 && !I.cold) c.theta = B.in_th[L.slice];
+    } else if (L.kind == GK_PRI) {
+        c.theta = B.in_th[L.slice];
+    }
+
+    auto barrier = [&]() -> bool {
+        ++nbar;
+        return group_barrier(bar, nbar * (unsigned)g, ctl, C.timeout_ticks);
+    };
+    auto my_part = [&](int parity) { return part + ((size_t)parity * kMaxGroup + rank) * 4; };
+    auto all_part = [&](int parity) { return part + (size_t)parity * kMaxGroup * 4; };
+
+    StepInfo st{};
+    bool ok = true;
+    while (c.phase != PH_DONE && ok) {
+        if (c.phase == PH_INIT) {
+            const bool first_entry = !c.verifying;
+            st = step_info(C, B, I, L, c.step);
+            if (first_entry && st.wait) {
+                ok = wait_flag(B.flags, st.wait_idx, I.epoch, ctl, C.timeout_ticks);
+                if (!ok) break;
+                if (L.kind == F_PRI && I.cold && L.slice > 0) c.theta = B.Gk_th[L.slice - 1];
+            }
+            if (first_entry && c.step == 0) {
+                // lanes whose first step depends on a producer outside the lane
+                if (L.kind == SWEEP_PRI) {
+                    ok = wait_flag(B.flags, flag_index(FL_F, 0), I.epoch, ctl, C.timeout_ticks);
+                    if (!ok) break;
+                    c.theta = B.F_th[0];
+                } else if (L.kind == SWEEP_ADJ) {
+                    ok = wait_flag(B.flags, flag_index(FL_F, C.Ntau), I.epoch, ctl,
+                                   C.timeout_ticks);
+                    if (!ok) break;
+                }
+            }
+            if (first_entry && (L.kind == SWEEP_PRI || L.kind == SWEEP_ADJ)) {
+                // G(u^k_n) must exist before it serves as initial guess
+                if (I.cold) {
+                    ok = wait_flag(B.flags, flag_index(FL_COLD, st.n), I.epoch, ctl,
+                                   C.timeout_ticks);
+                } else if (I.gk_lanes) {
+                    ok = wait_flag(B.flags, flag_index(FL_GK, st.n), I.epoch, ctl,
+                                   C.timeout_ticks);
+                }
+                if (!ok) break;
+            }
+            const double ms = st.fine ? C.inv_dt : C.inv_dtau;
+            const bool x0copy = first_entry && st.x0_src != nullptr;
+            const double *xs = x0copy ? st.x0_src : X;
+            double loc[2] = {0.0, 0.0};  // ||b||^2, ||r0||^2
+            for (int t = rank; t < ntiles; t += g) {
+                const int a = t * TS;
+                const int b = min(a + TS, C.Nn);
+                const int lo = a - H;
+                const int len = (b - a) + 2 * H;
+                __syncthreads();
+                for (int q = threadIdx.x; q < len; q += kThreads) {
+                    const int id = lo + q;
+                    const bool in = id >= 0 && id < C.Nn;
+                    const bool d = in && B.mask[id];
+                    LA[q] = (in && !d) ? xs[id] : 0.0;
+                    LB[q] = (in && !d) ? st.tp_src[id] : 0.0;
+                }
+                __syncthreads();
+                for (int id = a + threadIdx.x; id < b; id += kThreads) {
+                    const int li = id - lo;
+                    const int j = id / C.W, i = id - j * C.W;
+                    double bval = 0.0, r0 = 0.0;
+                    const double x0 = LA[li];
+                    if (!B.mask[id]) {
+                        const Coef am = node_coef(C, B.kq, B.cm, i, j, ms, 0.0);
+                        const Coef ak = node_coef(C, B.kq, B.cm, i, j, 0.0, 1.0);
+                        double src;
+                        if (!st.adjoint) {
+                            const int nex = (i > 0) + (i < C.nx), ney = (j > 0) + (j < C.ny);
+                            src = B.qt[st.j] * C.quarter_area * (double)(nex * ney);
+                        } else {
+                            const double T = B.S[(size_t)(st.j - 1) * C.Nn + id];
+                            src = c.src_scale * ipow(T, C.p - 1);
+                        }
+                        bval = apply(am, LB, li, C.W) + src;
+                        const double ax = apply(am, LA, li, C.W) + apply(ak, LA, li, C.W);
+                        r0 = bval - ax;
+                    }
+                    if (x0copy) X[id] = x0;
+                    Rb[0][id] = r0;
+                    loc[0] += bval * bval;
+                    loc[1] += r0 * r0;
+                    // first step of a lane: zero sensitivity sums, publish copies
+                    if (first_entry && c.step == 0) {
+                        if (L.kind == F_ADJ) {
+                            const int j2 = id / C.W, i2 = id - j2 * C.W;
+                            if (i2 < C.nx && j2 < C.ny)
+                                B.acc[(size_t)(L.slice - 1) * C.Ne + j2 * C.nx + i2] = 0.0;
+                        } else if (L.kind == SWEEP_ADJ) {
+                            const int j2 = id / C.W, i2 = id - j2 * C.W;
+                            if (i2 < C.nx && j2 < C.ny) B.accG[j2 * C.nx + i2] = 0.0;
+                            B.out_L[(size_t)C.Ntau * C.Nn + id] = 0.0;
+                            B.out_L[(size_t)(C.Ntau - 1) * C.Nn + id] = LB[li];
+                        } else if (L.kind == SWEEP_PRI) {
+                            B.out_T[(size_t)C.Nn + id] = LB[li];
+                        }
+                    }
+                }
+            }
+            block_sum<2>(loc, red);
+            const int par = nbar & 1;
+            if (threadIdx.x == 0) {
+                my_part(par)[0] = loc[0];
+                my_part(par)[1] = loc[1];
+            }
+            ok = barrier();
+            if (!ok) break;
+            double tot[2];
+            group_sum<2>(all_part(par), g, tot, red);
+            c.bnorm = sqrt(tot[0]);
+            const double rn = sqrt(tot[1]);
+            if (rank == 0 && threadIdx.x == 0 && c.step == 0 && first_entry) {
+                if (L.kind == SWEEP_PRI) B.out_th[1] = B.F_th[0];
+            }
+            if (first_entry) {
+                c.iter = 0;
+                c.restarts = 0;
+                c.zero_x = false;
+            }
+            c.it_local = 0;
+            if (c.bnorm == 0.0) {
+                c.zero_x = true;
+                c.relres = 0.0;
+                c.phase = PH_POST;
+            } else if (rn <= C.rtol * c.bnorm) {
+                c.relres = rn / c.bnorm;
+                c.phase = PH_POST;
+            } else {
+                c.phase = PH_FIRST;
+            }
+            c.verifying = false;
+        } else if (c.phase == PH_FIRST) {
+            // w0 = A z0, z0 = D^{-1} r0; gamma0 = (r0, z0), delta0 = (z0, w0)
+            const double ms = st.fine ? C.inv_dt : C.inv_dtau;
+            const double *dinv = st.fine ? B.dinv_f : B.dinv_c;
+            double loc[2] = {0.0, 0.0};
+            for (int t = rank; t < ntiles; t += g) {
+                const int a = t * TS;
+                const int b = min(a + TS, C.Nn);
+                const int lo = a - H;
+                const int len = (b - a) + 2 * H;
+                __syncthreads();
+                for (int q = threadIdx.x; q < len; q += kThreads) {
+                    const int id = lo + q;
+                    LA[q] = (id >= 0 && id < C.Nn) ? dinv[id] * Rb[0][id] : 0.0;
+                }
+                __syncthreads();
+                for (int id = a + threadIdx.x; id < b; id += kThreads) {
+                    const int li = id - lo;
+                    double w = 0.0;
+                    if (!B.mask[id]) {
+                        const int j = id / C.W, i = id - j * C.W;
+                        const Coef aa = node_coef(C, B.kq, B.cm, i, j, ms, 1.0);
+                        w = apply(aa, LA, li, C.W);
+                    }
+                    Wb[0][id] = w;
+                    const double z = LA[li];
+                    loc[0] += Rb[0][id] * z;
+                    loc[1] += z * w;
+                }
+            }
+            block_sum<2>(loc, red);
+            const int par = nbar & 1;
+            if (threadIdx.x == 0) {
+                my_part(par)[0] = loc[0];
+                my_part(par)[1] = loc[1];
+            }
+            ok = barrier();
+            if (!ok) break;
+            double tot[2];
+            group_sum<2>(all_part(par), g, tot, red);
+            c.gamma = tot[0];
+            c.alpha = tot[0] / tot[1];
+            c.beta = 0.0;
+            c.phase = PH_ITER;
+        } else if (c.phase == PH_ITER) {
+            const double ms = st.fine ? C.inv_dt : C.inv_dtau;
+            const double *dinv = st.fine ? B.dinv_f : B.dinv_c;
+            const int i0 = c.it_local;         // iteration since the last (re)start
+            const int cur = i0 & 1, nxt = cur ^ 1;
+            const bool first = (i0 == 0);
+            const double al = c.alpha, be = c.beta;
+            double loc[3] = {0.0, 0.0, 0.0};
+            for (int t = rank; t < ntiles; t += g) {
+                const int a = t * TS;
+                const int b = min(a + TS, C.Nn);
+                const int lo = a - H;
+                const int len = (b - a) + 2 * H;
+                __syncthreads();
+                for (int q = threadIdx.x; q < len; q += kThreads) {
+                    const int id = lo + q;
+                    double z = 0.0;
+                    if (id >= 0 && id < C.Nn) {
+                        const double sv = first ? Wb[cur][id] : Wb[cur][id] + be * Sb[cur][id];
+                        const double rn = Rb[cur][id] - al * sv;
+                        z = dinv[id] * rn;
+                        if (id >= a && id < b) {
+                            const double zi = dinv[id] * Rb[cur][id];
+                            const double pn = first ? zi : zi + be * P[id];
+                            P[id] = pn;
+                            Sb[nxt][id] = sv;
+                            X[id] += al * pn;
+                            Rb[nxt][id] = rn;
+                        }
+                    }
+                    LA[q] = z;
+                }
+                __syncthreads();
+                for (int id = a + threadIdx.x; id < b; id += kThreads) {
+                    const int li = id - lo;
+                    double w = 0.0;
+                    if (!B.mask[id]) {
+                        const int j = id / C.W, i = id - j * C.W;
+                        const Coef aa = node_coef(C, B.kq, B.cm, i, j, ms, 1.0);
+                        w = apply(aa, LA, li, C.W);
+                    }
+                    Wb[nxt][id] = w;
+                    const double z = LA[li];
+                    const double rn = Rb[nxt][id];
+                    loc[0] += rn * z;
+                    loc[1] += z * w;
+                    loc[2] += rn * rn;
+                }
+            }
+            block_sum<3>(loc, red);
+            const int par = nbar & 1;
+            if (threadIdx.x == 0) {
+                my_part(par)[0] = loc[0];
+                my_part(par)[1] = loc[1];
+                my_part(par)[2] = loc[2];
+            }
+            ok = barrier();
+            if (!ok) break;
+            double tot[3];
+            group_sum<3>(all_part(par), g, tot, red);
+            c.it_local = i0 + 1;
+            c.iter += 1;
+            const double rn = sqrt(tot[2]);
+            if (rn <= C.rtol * c.bnorm || c.iter >= C.max_iter) {
+                c.relres = rn / c.bnorm;
+                if (C.verify && rn <= C.rtol * c.bnorm && c.restarts < 3) {
+                    // true-residual check: recompute r = b - A x and restart if needed
+                    c.verifying = true;
+                    c.restarts += 1;
+                    c.phase = PH_INIT;
+                } else {
+                    c.phase = PH_POST;
+                }
+                if (rn > C.rtol * c.bnorm && rank == 0 && threadIdx.x == 0) set_status(ctl, -4);
+            } else {
+                const double gnew = tot[0];
+                const double bnew = gnew / c.gamma;
+                const double anew = gnew / (tot[1] - bnew * gnew / al);
+                c.beta = bnew;
+                c.alpha = anew;
+                c.gamma = gnew;
+            }
+        } else {  // PH_POST
+            // lane-specific writes of the converged solution x
+            const bool last = (c.step == c.nsteps - 1);
+            if (L.kind == SWEEP_PRI) {
+                const int n = st.n;
+                ok = wait_flag(B.flags, flag_index(FL_F, n), I.epoch, ctl, C.timeout_ticks);
+                if (!ok) break;
+            } else if (L.kind == SWEEP_ADJ) {
+                ok = wait_flag(B.flags, flag_index(FL_F, st.n), I.epoch, ctl, C.timeout_ticks);
+                if (!ok) break;
+            }
+            double loc[1] = {0.0};
+            const bool zx = c.zero_x;
+            for (int t = rank; t < ntiles; t += g) {
+                const int a = t * TS;
+                const int b = min(a + TS, C.Nn);
+                for (int id = a + threadIdx.x; id < b; id += kThreads) {
+                    const double x = zx ? 0.0 : X[id];
+                    switch (L.kind) {
+                        case F_PRI: {
+                            B.S[(size_t)(st.j - 1) * C.Nn + id] = x;
+                            TP[id] = x;
+                            loc[0] += ipow(x, C.p);
+                            break;
+                        }
+                        case GK_PRI:
+                        case COLD_PRI: {
+                            B.Gk[(size_t)st.n * C.Nn + id] = x;
+                            TP[id] = x;
+                            loc[0] += ipow(x, C.p);
+                            break;
+                        }
+                        case SWEEP_PRI: {
+                            const int n = st.n;
+                            const size_t srow = (size_t)(C.M * (n + 1) - 1) * C.Nn + id;
+                            const double u = x + B.S[srow] - B.Gk[(size_t)n * C.Nn + id];
+                            B.S[srow] = u;
+                            B.out_T[(size_t)(n + 1) * C.Nn + id] = u;
+                            B.Gn[(size_t)n * C.Nn + id] = x;
+                            TP[id] = u;
+                            loc[0] += ipow(x, C.p);
+                            break;
+                        }
+                        case F_ADJ: {
+                            TP[id] = x;
+                            const int j2 = id / C.W, i2 = id - j2 * C.W;
+                            if (i2 < C.nx && j2 < C.ny) {
+                                const int e = j2 * C.nx + i2;
+                                const double l0 = x;
+                                const double l1 = zx ? 0.0 : X[id + 1];
+                                const double l2 = zx ? 0.0 : X[id + C.W + 1];
+                                const double l3 = zx ? 0.0 : X[id + C.W];
+                                const double *Tr = B.S + (size_t)(st.j - 1) * C.Nn;
+                                const double t0 = Tr[id], t1 = Tr[id + 1], t2 = Tr[id + C.W + 1],
+                                             t3 = Tr[id + C.W];
+                                double term = B.dk[e] * elem_k(C, l0, l1, l2, l3, t0, t1, t2, t3);
+                                if (I.has_dc) {
+                                    double p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+                                    if (st.jprev > 0) {
+                                        const double *Tp = B.S + (size_t)(st.jprev - 1) * C.Nn;
+                                        p0 = Tp[id];
+                                        p1 = Tp[id + 1];
+                                        p2 = Tp[id + C.W + 1];
+                                        p3 = Tp[id + C.W];
+                                    }
+                                    term += B.dc[e] * C.inv_dt *
+                                            elem_c(C, l0, l1, l2, l3, t0 - p0, t1 - p1, t2 - p2,
+                                                   t3 - p3);
+                                }
+                                B.acc[(size_t)(L.slice - 1) * C.Ne + e] += term;
+                            }
+                            break;
+                        }
+                        case GK_ADJ:
+                        case COLD_ADJ: {
+                            B.Gk[(size_t)st.n * C.Nn + id] = x;
+                            TP[id] = x;
+                            break;
+                        }
+                        default: {  // SWEEP_ADJ
+                            const int n = st.n;
+                            const double *FL = lane_vec(B, C, B.fvec[n], V_X);
+                            const double *Gkn = B.Gk + (size_t)n * C.Nn;
+                            const double lam = x + FL[id] - Gkn[id];
+                            B.out_L[(size_t)(n - 1) * C.Nn + id] = lam;
+                            B.Gn[(size_t)n * C.Nn + id] = x;
+                            TP[id] = lam;
+                            const int j2 = id / C.W, i2 = id - j2 * C.W;
+                            if (i2 < C.nx && j2 < C.ny) {
+                                const int e = j2 * C.nx + i2;
+                                auto dl = [&](int k) { return (zx ? 0.0 : X[k]) - Gkn[k]; };
+                                const double l0 = dl(id), l1 = dl(id + 1), l2 = dl(id + C.W + 1),
+                                             l3 = dl(id + C.W);
+                                const double *Tr = B.S + (size_t)(st.j - 1) * C.Nn;
+                                const double t0 = Tr[id], t1 = Tr[id + 1], t2 = Tr[id + C.W + 1],
+                                             t3 = Tr[id + C.W];
+                                double term = B.dk[e] * elem_k(C, l0, l1, l2, l3, t0, t1, t2, t3);
+                                if (I.has_dc) {
+                                    double p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+                                    if (st.jprev > 0) {
+                                        const double *Tp = B.S + (size_t)(st.jprev - 1) * C.Nn;
+                                        p0 = Tp[id];
+                                        p1 = Tp[id + 1];
+                                        p2 = Tp[id + C.W + 1];
+                                        p3 = Tp[id + C.W];
+                                    }
+                                    term += B.dc[e] * C.inv_dtau *
+                                            elem_c(C, l0, l1, l2, l3, t0 - p0, t1 - p1, t2 - p2,
+                                                   t3 - p3);
+                                }
+                                B.accG[e] += term;
+                            }
+                            break;
+                        }
+                    }
+                }
+            }
+            block_sum<1>(loc, red);
+            const int par = nbar & 1;
+            if (threadIdx.x == 0) my_part(par)[0] = loc[0];
+            ok = barrier();
+            if (!ok) break;
+            double tot[1];
+            group_sum<1>(all_part(par), g, tot, red);
+            const bool leader = (rank == 0 && threadIdx.x == 0);
+            // theta updates (Alg. 1, step 2) and lane outputs
+            if (!is_adj) {
+                const double inv = st.fine ? C.inv_NtNe : C.inv_NtauNe;
+                const double thG = pow(ipow(c.theta, C.p) + tot[0] * inv, C.inv_p);
+                if (L.kind == SWEEP_PRI) {
+                    const int n = st.n;
+                    const double thu = thG + B.F_th[n] - B.Gk_th[n];
+                    if (leader) {
+                        B.out_th[n + 1] = thu;
+                        B.Gn_th[n] = thG;
+                    }
+                    c.theta = thu;
+                } else {
+                    c.theta = thG;
+                    if (leader && (L.kind == GK_PRI || L.kind == COLD_PRI)) B.Gk_th[st.n] = thG;
+                    if (leader && L.kind == F_PRI && last) B.F_th[L.slice] = thG;
+                }
+            }
+            if (leader) {
+                // statistics
+                const int it = c.iter;
+                if (st.fine) {
+                    atomicAdd(&ctl->iters_fine, (unsigned long long)it);
+                    atomicAdd(&ctl->solves_fine, 1ull);
+                } else {
+                    atomicAdd(&ctl->iters_coarse, (unsigned long long)it);
+                    atomicAdd(&ctl->solves_coarse, 1ull);
+                }
+                atomicMax(&ctl->max_iters, it);
+                atomicMax(&ctl->max_relres_bits, (unsigned long long)__double_as_longlong(c.relres));
+                // flags
+                if (L.kind == GK_PRI || L.kind == GK_ADJ) set_flag(B.flags, flag_index(FL_GK, st.n), I.epoch);
+                if (L.kind == COLD_PRI || L.kind == COLD_ADJ)
+                    set_flag(B.flags, flag_index(FL_COLD, st.n), I.epoch);
+                if ((L.kind == F_PRI || L.kind == F_ADJ) && last)
+                    set_flag(B.flags, flag_index(FL_F, L.slice), I.epoch);
+            }
+            c.step += 1;
+            c.phase = (c.step < c.nsteps) ? PH_INIT : PH_DONE;
+            c.iter = 0;
+            c.verifying = false;
+        }
+    }
+    if (!ok && threadIdx.x == 0) {
+        atomicExch(&ctl->abort, 1);
+        set_status(ctl, -3);
+    }
+}
+
+// After the primal engine: u_0 = 0, Theta, and the N_tau = 1 case.
+__global__ void k_finalize_fwd(Consts C, Bufs B, double *Theta_out, double *uT_out,
+                               double *uth_out, int copy_out) {
+    const size_t Nn = C.Nn;
+    for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < Nn;
+         id += (size_t)gridDim.x * blockDim.x) {
+        B.out_T[id] = 0.0;
+        if (C.Ntau == 1) B.out_T[Nn + id] = B.S[(size_t)(C.Nt - 1) * Nn + id];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        B.out_th[0] = 0.0;
+        if (C.Ntau == 1) B.out_th[1] = B.F_th[0];
+        const double Th = B.out_th[C.Ntau];
+        *Theta_out = Th;
+        if (!(Th > 0.0) || !isfinite(Th)) atomicCAS(&B.ctl->status, 0, -5);
+        B.ctl->fwd_done = 1;
+    }
+    (void)uT_out;
+    (void)uth_out;
+    (void)copy_out;
+}
+
+// After the adjoint engine: lambda for N_tau = 1.
+__global__ void k_finalize_adj(Consts C, Bufs B) {
+    const size_t Nn = C.Nn;
+    if (C.Ntau == 1) {
+        const double *FL = B.pool + ((size_t)B.fvec[1] * kVecsPerLane + 0) * Nn;
+        for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < Nn;
+             id += (size_t)gridDim.x * blockDim.x) {
+            B.out_L[id] = FL[id];
+            B.out_L[Nn + id] = 0.0;
+        }
+        for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)C.Ne;
+             e += (size_t)gridDim.x * blockDim.x)
+            B.accG[e] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) B.ctl->adj_done = 1;
+}
+
+// grad_e = -(1/N_t) sum_n acc[n][e] - (1/N_tau) accG[e]  (Eq. 4.10 summed, Sec. 4.4 step 4)
+__global__ void k_sensitivities(Consts C, const double *acc, const double *accG, double *grad) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < C.Ne; e += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int n = 0; n < C.Ntau; ++n) s += acc[(size_t)n * C.Ne + e];
+        grad[e] = -s / (double)C.Nt - accG[e] / (double)C.Ntau;
+    }
+}
+
+}  // namespace pt

@@ -1,0 +1,601 @@
+// Host side of libpt: argument checks, workspace layout, lane planning and the
+// stream-ordered launches of one forward / adjoint / sensitivity call.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/pt.h"
+#include "pt_engine.hip"
+
+using namespace pt;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t ctl, bar, flags, partials, wg_lane, lanes, fvec;
+    size_t kq, cm, dk, dc, dinv_f, dinv_c, mask, qt, zero;
+    size_t Gk, Gn, Gk_th, Gn_th, F_th, Uprev, Uprev_th, Ubuf, Ubuf_th, Lprev, Lbuf;
+    size_t acc, accG, pool;
+    size_t total;
+    int max_lanes, max_grid;
+};
+
+bool valid_problem(const pt_problem *p) {
+    if (!p) return false;
+    if (p->nx < 1 || p->ny < 1 || p->nx > 16384 || p->ny > 16384) return false;
+    if ((long long)(p->nx + 1) * (p->ny + 1) > (1ll << 30)) return false;
+    if (p->n_steps < 1 || p->n_slices < 1 || p->n_steps % p->n_slices) return false;
+    if (p->n_slices > 4000) return false;
+    if (p->pnorm < 2 || (p->pnorm % 2)) return false;
+    if (p->iterations < 1) return false;
+    if (!(p->cg_rtol > 0.0) || !isfinite(p->cg_rtol)) return false;
+    if (p->max_iter < 1) return false;
+    if (!(p->t_final > 0.0) || !isfinite(p->t_final)) return false;
+    if (!isfinite(p->k0) || !isfinite(p->kmin) || !isfinite(p->pk)) return false;
+    if (!isfinite(p->c0) || !isfinite(p->cmin) || !isfinite(p->pc)) return false;
+    if (!(p->kmin > 0.0) || !(p->k0 > 0.0) || !(p->cmin > 0.0) || !(p->c0 > 0.0)) return false;
+    if (p->pk < 1.0 || p->pc < 1.0) return false;
+    if (!p->q_t && !isfinite(p->q)) return false;
+    if (p->precision != PT_FP64 || p->precond != PT_JACOBI || p->storage != PT_STORE_ALL)
+        return false;
+    if (p->bc < 0 || p->bc > 3) return false;
+    if (p->bc == PT_BC_MASK && !p->dirichlet_mask) return false;
+    if (p->q_t)
+        for (int n = 0; n <= p->n_steps; ++n)
+            if (!isfinite(p->q_t[n])) return false;
+    return true;
+}
+
+Layout layout(const pt_problem *p) {
+    Layout L{};
+    const size_t Nn = (size_t)(p->nx + 1) * (p->ny + 1);
+    const size_t Ne = (size_t)p->nx * p->ny;
+    const size_t EP = (size_t)(p->nx + 2) * (p->ny + 2);
+    const size_t Nt1 = (size_t)p->n_slices + 1;
+    L.max_lanes = 2 * p->n_slices + 2;
+    L.max_grid = 4096;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.ctl = take(sizeof(Control));
+    L.bar = take(sizeof(unsigned) * kMaxLanes);
+    L.flags = take(sizeof(unsigned) * kMaxFlags);
+    L.partials = take(sizeof(double) * (size_t)L.max_lanes * 2 * kMaxGroup * 4);
+    L.wg_lane = take(sizeof(int) * L.max_grid);
+    L.lanes = take(sizeof(Lane) * L.max_lanes);
+    L.fvec = take(sizeof(int) * Nt1);
+    L.kq = take(sizeof(double) * EP);
+    L.cm = take(sizeof(double) * EP);
+    L.dk = take(sizeof(double) * Ne);
+    L.dc = take(sizeof(double) * Ne);
+    L.dinv_f = take(sizeof(double) * Nn);
+    L.dinv_c = take(sizeof(double) * Nn);
+    L.mask = take(Nn);
+    L.qt = take(sizeof(double) * (p->n_steps + 1));
+    L.zero = take(sizeof(double) * Nn);
+    L.Gk = take(sizeof(double) * Nt1 * Nn);
+    L.Gn = take(sizeof(double) * Nt1 * Nn);
+    L.Gk_th = take(sizeof(double) * Nt1);
+    L.Gn_th = take(sizeof(double) * Nt1);
+    L.F_th = take(sizeof(double) * Nt1);
+    L.Uprev = take(sizeof(double) * Nt1 * Nn);
+    L.Uprev_th = take(sizeof(double) * Nt1);
+    L.Ubuf = take(sizeof(double) * Nt1 * Nn);
+    L.Ubuf_th = take(sizeof(double) * Nt1);
+    L.Lprev = L.Uprev;  // adjoint reuses the primal scratch
+    L.Lbuf = L.Ubuf;
+    L.acc = take(sizeof(double) * (size_t)p->n_slices * Ne);
+    L.accG = take(sizeof(double) * Ne);
+    L.pool = take(sizeof(double) * (size_t)L.max_lanes * kVecsPerLane * Nn);
+    L.total = o;
+    return L;
+}
+
+Consts make_consts(const pt_problem *p) {
+    Consts C{};
+    C.nx = p->nx;
+    C.ny = p->ny;
+    C.W = p->nx + 1;
+    C.Nn = (p->nx + 1) * (p->ny + 1);
+    C.Ne = p->nx * p->ny;
+    C.EW = p->nx + 2;
+    C.Nt = p->n_steps;
+    C.Ntau = p->n_slices;
+    C.M = p->n_steps / p->n_slices;
+    C.p = p->pnorm;
+    C.max_iter = p->max_iter;
+    C.verify = 1;
+    C.hx = 1.0 / p->nx;
+    C.hy = 1.0 / p->ny;
+    const double rx = C.hy / C.hx, ry = C.hx / C.hy;
+    C.e_self = 2.0 * (rx + ry);
+    C.e_x = ry - 2.0 * rx;
+    C.e_y = rx - 2.0 * ry;
+    C.e_d = -(rx + ry);
+    C.cm_unit = C.hx * C.hy / 36.0;
+    C.quarter_area = C.hx * C.hy / 4.0;
+    C.dt = p->t_final / p->n_steps;
+    C.dtau = p->t_final / p->n_slices;
+    C.inv_dt = 1.0 / C.dt;
+    C.inv_dtau = 1.0 / C.dtau;
+    C.rtol = p->cg_rtol;
+    C.inv_NtNe = 1.0 / ((double)p->n_steps * (double)C.Ne);
+    C.inv_NtauNe = 1.0 / ((double)p->n_slices * (double)C.Ne);
+    C.inv_p = 1.0 / p->pnorm;
+    // a device wait gives up after this many seconds (100 MHz realtime clock)
+    double tmo = 20.0;
+    if (const char *e = getenv("PT_WAIT_TIMEOUT_S")) tmo = atof(e);
+    if (!(tmo > 0.0)) tmo = 20.0;
+    C.timeout_ticks = (long long)(tmo * 1e8);
+    return C;
+}
+
+template <typename T>
+T *at(void *ws, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+Bufs make_bufs(void *ws, const Layout &L) {
+    Bufs B{};
+    B.ctl = at<Control>(ws, L.ctl);
+    B.bar = at<unsigned>(ws, L.bar);
+    B.flags = at<unsigned>(ws, L.flags);
+    B.partials = at<double>(ws, L.partials);
+    B.wg_lane = at<int>(ws, L.wg_lane);
+    B.lanes = at<Lane>(ws, L.lanes);
+    B.fvec = at<int>(ws, L.fvec);
+    B.pool = at<double>(ws, L.pool);
+    B.kq = at<double>(ws, L.kq);
+    B.cm = at<double>(ws, L.cm);
+    B.dk = at<double>(ws, L.dk);
+    B.dc = at<double>(ws, L.dc);
+    B.dinv_f = at<double>(ws, L.dinv_f);
+    B.dinv_c = at<double>(ws, L.dinv_c);
+    B.mask = at<unsigned char>(ws, L.mask);
+    B.qt = at<double>(ws, L.qt);
+    B.zero = at<double>(ws, L.zero);
+    B.Gk = at<double>(ws, L.Gk);
+    B.Gn = at<double>(ws, L.Gn);
+    B.Gk_th = at<double>(ws, L.Gk_th);
+    B.Gn_th = at<double>(ws, L.Gn_th);
+    B.F_th = at<double>(ws, L.F_th);
+    B.acc = at<double>(ws, L.acc);
+    B.accG = at<double>(ws, L.accG);
+    return B;
+}
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? PT_OK : PT_EHIP; }
+
+#define PT_TRY(expr)                         \
+    do {                                     \
+        int _rc = (expr);                    \
+        if (_rc != PT_OK) return _rc;        \
+    } while (0)
+
+int launch_check() { return hip_ok(hipGetLastError()); }
+
+// Plan of one engine launch, built on the host and uploaded through a kernel
+// argument (so no host buffer must outlive the call).
+struct PlanArgs {
+    int n_lanes;
+    int grid;
+    // lanes are described in runs: [first, count, kind, slice0, slice_step, nwg, tile, vec0]
+    int runs;
+    int run[8][8];
+};
+
+__global__ void k_build_plan(PlanArgs P, Lane *lanes, int *wg_lane, int *fvec, int ntau) {
+    if (blockIdx.x != 0) return;
+    // lanes
+    for (int r = 0; r < P.runs; ++r) {
+        const int first = P.run[r][0], count = P.run[r][1];
+        for (int q = threadIdx.x; q < count; q += blockDim.x) {
+            Lane L;
+            L.kind = P.run[r][2];
+            L.slice = P.run[r][3] + q * P.run[r][4];
+            L.nwg = P.run[r][5];
+            L.tile = P.run[r][6];
+            L.vec = P.run[r][7] + q;
+            L.wg0 = 0;
+            lanes[first + q] = L;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int w = 0;
+        for (int l = 0; l < P.n_lanes; ++l) {
+            lanes[l].wg0 = w;
+            for (int k = 0; k < lanes[l].nwg; ++k) wg_lane[w++] = l;
+            if (lanes[l].kind == F_PRI || lanes[l].kind == F_ADJ) fvec[lanes[l].slice] = lanes[l].vec;
+        }
+        for (; w < P.grid; ++w) wg_lane[w] = -1;
+        (void)ntau;
+    }
+}
+
+struct Device {
+    int cus = 0;
+    int lds_max = 0;
+};
+
+int device_info(Device &d) {
+    int dev = 0;
+    PT_TRY(hip_ok(hipGetDevice(&dev)));
+    PT_TRY(hip_ok(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev)));
+    PT_TRY(hip_ok(hipDeviceGetAttribute(&d.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)));
+    return PT_OK;
+}
+
+// Work weights in CG iterations (coarse solves need several times more
+// iterations than fine ones; sweeps are latency-bound and get a fixed share).
+struct LanePlan {
+    int kind;
+    int count;
+    int slice0, slice_step;
+    double weight;  // per lane
+    int nwg = 1;
+    int tile = 256;
+};
+
+int tile_for(int Nn, int nwg, int H, int lds_cap_doubles) {
+    int ts = (Nn + nwg - 1) / nwg;
+    ts = (ts + 255) / 256 * 256;
+    const int cap = (lds_cap_doubles / 2 - 2 * H) / 256 * 256;
+    ts = std::min(ts, std::max(cap, 256));
+    ts = std::min(ts, 8192);
+    ts = std::max(ts, 256);
+    return ts;
+}
+
+// Runs one engine launch over the given lane runs.
+int run_engine(const Consts &C, Bufs B, const LaunchInfo &I, std::vector<LanePlan> &plans,
+               void *ws, const Layout &Lay, hipStream_t stream, int sweep_share) {
+    Device dev;
+    PT_TRY(device_info(dev));
+    const int H = C.W + 1;
+    const int lds_cap = std::min(dev.lds_max, 160 * 1024) - 1024;  // bytes for the two windows
+    const int lds_cap_d = lds_cap / 8;
+    // co-resident grid: one workgroup per CU (the engine's LDS windows are large)
+    int grid = dev.cus;
+    int n_lanes = 0;
+    for (auto &p : plans) n_lanes += p.count;
+    if (n_lanes > Lay.max_lanes || n_lanes > kMaxLanes) return PT_EINVAL;
+    if (n_lanes > grid) {
+        // more lanes than workgroups: give every lane one workgroup on a wider grid
+        grid = n_lanes;
+    }
+    // split workgroups: sweeps first, then by weight
+    int fixed = 0;
+    double wsum = 0.0;
+    for (auto &p : plans) {
+        if (p.kind == SWEEP_PRI || p.kind == SWEEP_ADJ || p.kind == COLD_PRI || p.kind == COLD_ADJ) {
+            p.nwg = std::max(1, std::min(sweep_share, grid / 4));
+            fixed += p.nwg * p.count;
+        } else {
+            wsum += p.weight * p.count;
+        }
+    }
+    int rest = grid - fixed;
+    int used = fixed;
+    for (auto &p : plans) {
+        if (p.kind == SWEEP_PRI || p.kind == SWEEP_ADJ || p.kind == COLD_PRI || p.kind == COLD_ADJ)
+            continue;
+        int share = (int)floor(rest * p.weight / wsum);
+        p.nwg = std::max(1, share);
+        used += p.nwg * p.count;
+    }
+    if (used > grid) grid = used;
+    int max_tile = 256;
+    for (auto &p : plans) {
+        p.tile = tile_for(C.Nn, p.nwg, H, lds_cap_d);
+        max_tile = std::max(max_tile, p.tile);
+    }
+    if (grid > Lay.max_grid) return PT_EINVAL;
+    const size_t lds_bytes = (size_t)2 * (max_tile + 2 * H) * sizeof(double);
+    if (lds_bytes > (size_t)dev.lds_max) return PT_EINVAL;
+
+    PlanArgs P{};
+    P.grid = grid;
+    P.runs = 0;
+    int first = 0, vec = 0;
+    for (auto &p : plans) {
+        if (p.count == 0) continue;
+        if (P.runs >= 8) return PT_EINVAL;
+        int *r = P.run[P.runs++];
+        r[0] = first;
+        r[1] = p.count;
+        r[2] = p.kind;
+        r[3] = p.slice0;
+        r[4] = p.slice_step;
+        r[5] = p.nwg;
+        r[6] = p.tile;
+        r[7] = vec;
+        first += p.count;
+        vec += p.count;
+    }
+    P.n_lanes = first;
+    hipLaunchKernelGGL(k_build_plan, dim3(1), dim3(256), 0, stream, P, at<Lane>(ws, Lay.lanes),
+                       at<int>(ws, Lay.wg_lane), at<int>(ws, Lay.fvec), C.Ntau);
+    PT_TRY(launch_check());
+    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream, B.bar, (size_t)kMaxLanes, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream, B.flags, (size_t)kMaxFlags, 0u);
+    PT_TRY(launch_check());
+
+    for (auto &p : plans)
+        if (p.nwg > kMaxGroup) return PT_EINVAL;
+    PT_TRY(hip_ok(hipFuncSetAttribute((const void *)k_engine,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds_bytes)));
+    int occ = 0;
+    PT_TRY(hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_engine, kThreads,
+                                                                lds_bytes)));
+    if ((long long)occ * dev.cus < grid) return PT_EHIP;
+    void *args[] = {(void *)&C, (void *)&B, (void *)&I};
+    PT_TRY(hip_ok(hipLaunchCooperativeKernel((const void *)k_engine, dim3(grid), dim3(kThreads),
+                                             args, (unsigned)lds_bytes, stream)));
+    return launch_check();
+}
+
+int setup_design(const pt_problem *p, const Consts &C, const Bufs &B, const double *rho,
+                 void *ws, const Layout &Lay, hipStream_t stream) {
+    const int blocks = 512;
+    // Dirichlet mask
+    if (p->bc == PT_BC_MASK) {
+        PT_TRY(hip_ok(hipMemcpyAsync(at<unsigned char>(ws, Lay.mask), p->dirichlet_mask,
+                                     (size_t)C.Nn, hipMemcpyHostToDevice, stream)));
+        PT_TRY(hip_ok(hipStreamSynchronize(stream)));
+    } else {
+        const int rule = p->bc == PT_BC_LEFT_CENTRE ? 0 : (p->bc == PT_BC_BOTTOM_CENTRE ? 1 : 2);
+        hipLaunchKernelGGL(k_mask_rule, dim3(blocks), dim3(256), 0, stream, C, rule,
+                           at<unsigned char>(ws, Lay.mask));
+    }
+    // source history
+    if (p->q_t) {
+        PT_TRY(hip_ok(hipMemcpyAsync(at<double>(ws, Lay.qt), p->q_t,
+                                     sizeof(double) * (p->n_steps + 1), hipMemcpyHostToDevice,
+                                     stream)));
+        PT_TRY(hip_ok(hipStreamSynchronize(stream)));
+    } else {
+        hipLaunchKernelGGL(k_fill_f64, dim3(8), dim3(256), 0, stream, at<double>(ws, Lay.qt),
+                           (size_t)(p->n_steps + 1), p->q);
+    }
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks), dim3(256), 0, stream, at<double>(ws, Lay.zero),
+                       (size_t)C.Nn, 0.0);
+    hipLaunchKernelGGL(k_material, dim3(blocks), dim3(256), 0, stream, C, rho,
+                       at<double>(ws, Lay.kq), at<double>(ws, Lay.cm), at<double>(ws, Lay.dk),
+                       at<double>(ws, Lay.dc), p->k0, p->kmin, p->pk, p->c0, p->cmin, p->pc,
+                       B.ctl);
+    hipLaunchKernelGGL(k_diag, dim3(blocks), dim3(256), 0, stream, C, B.kq, B.cm, B.mask,
+                       at<double>(ws, Lay.dinv_f), at<double>(ws, Lay.dinv_c));
+    return launch_check();
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    if (!a || !b) return false;
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+__global__ void k_reset_ctl(Control *ctl, int keep_markers) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int f = ctl->fwd_done, a = ctl->adj_done;
+        ctl->status = 0;
+        ctl->abort = 0;
+        ctl->max_iters = 0;
+        ctl->iters_fine = ctl->iters_coarse = ctl->solves_fine = ctl->solves_coarse = 0;
+        ctl->max_relres_bits = 0;
+        ctl->fwd_done = keep_markers ? f : 0;
+        ctl->adj_done = 0;
+        (void)a;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pt_validate(const pt_problem *prob) { return valid_problem(prob) ? PT_OK : PT_EINVAL; }
+
+size_t pt_workspace_bytes(const pt_problem *prob) {
+    if (!valid_problem(prob)) return 0;
+    return layout(prob).total;
+}
+
+const char *pt_strerror(int code) {
+    switch (code) {
+        case PT_OK: return "ok";
+        case PT_EINVAL: return "invalid argument";
+        case PT_ENOMEM: return "workspace too small";
+        case PT_EHIP: return "HIP runtime error or device wait timeout";
+        case PT_ENOCONV: return "a CG solve reached max_iter";
+        case PT_EDOMAIN: return "non-finite input or result, or Theta <= 0";
+        case PT_ESTATE: return "call order violated";
+        default: return "unknown error";
+    }
+}
+
+int pt_parareal_forward(const pt_problem *prob, const double *rho, const double *guess_T,
+                        const double *guess_theta, double *S, double *uT_out, double *utheta_out,
+                        double *Theta_out, void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (!valid_problem(prob)) return PT_EINVAL;
+    if (!rho || !S || !Theta_out || !ws) return PT_EINVAL;
+    if ((guess_T == nullptr) != (guess_theta == nullptr)) return PT_EINVAL;
+    const Layout Lay = layout(prob);
+    if (ws_bytes < Lay.total) return PT_ENOMEM;
+    const Consts C = make_consts(prob);
+    const size_t Nn = C.Nn, Nt1 = C.Ntau + 1;
+    const size_t sz_U = Nt1 * Nn * sizeof(double), sz_S = (size_t)C.Nt * Nn * sizeof(double);
+    if (guess_T) {
+        const void *outs[] = {S, uT_out, utheta_out, Theta_out, ws};
+        const size_t lens[] = {sz_S, sz_U, Nt1 * sizeof(double), sizeof(double), ws_bytes};
+        for (int k = 0; k < 5; ++k)
+            if (overlaps(guess_T, sz_U, outs[k], lens[k]) ||
+                overlaps(guess_theta, Nt1 * sizeof(double), outs[k], lens[k]))
+                return PT_EINVAL;
+    }
+    if (overlaps(S, sz_S, ws, ws_bytes) || overlaps(uT_out, sz_U, ws, ws_bytes)) return PT_EINVAL;
+
+    Bufs B = make_bufs(ws, Lay);
+    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, stream, B.ctl, 0);
+    PT_TRY(setup_design(prob, C, B, rho, ws, Lay, stream));
+
+    double *outT = uT_out ? uT_out : at<double>(ws, Lay.Ubuf);
+    double *outth = utheta_out ? utheta_out : at<double>(ws, Lay.Ubuf_th);
+    double *Uprev = at<double>(ws, Lay.Uprev);
+    double *Uprev_th = at<double>(ws, Lay.Uprev_th);
+    double *Ga = at<double>(ws, Lay.Gk), *Gb = at<double>(ws, Lay.Gn);
+    double *Ga_th = at<double>(ws, Lay.Gk_th), *Gb_th = at<double>(ws, Lay.Gn_th);
+    const bool cold = guess_T == nullptr;
+    const int Ntau = C.Ntau;
+    for (int it = 0; it < prob->iterations; ++it) {
+        LaunchInfo I{};
+        I.cold = (cold && it == 0) ? 1 : 0;
+        I.gk_lanes = (!cold && it == 0 && Ntau > 1) ? 1 : 0;
+        I.has_dc = (prob->c0 != prob->cmin) ? 1 : 0;
+        I.epoch = 1;
+        B.in_T = it == 0 ? guess_T : Uprev;
+        B.in_th = it == 0 ? guess_theta : Uprev_th;
+        B.S = S;
+        B.out_T = outT;
+        B.out_th = outth;
+        B.Gk = Ga;
+        B.Gk_th = Ga_th;
+        B.Gn = Gb;
+        B.Gn_th = Gb_th;
+        std::vector<LanePlan> plans;
+        LanePlan f{F_PRI, Ntau, 0, 1, (double)C.M};
+        plans.push_back(f);
+        if (I.gk_lanes) {
+            LanePlan gk{GK_PRI, Ntau - 1, 1, 1, 4.0};
+            plans.push_back(gk);
+        }
+        if (I.cold) {
+            LanePlan cl{COLD_PRI, 1, 0, 1, 0.0};
+            plans.push_back(cl);
+        }
+        if (Ntau > 1) {
+            LanePlan sw{SWEEP_PRI, 1, 0, 1, 0.0};
+            plans.push_back(sw);
+        }
+        PT_TRY(run_engine(C, B, I, plans, ws, Lay, stream, 32));
+        if (it + 1 < prob->iterations) {
+            hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Uprev, outT, Nt1 * Nn);
+            hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(256), 0, stream, Uprev_th, outth, Nt1);
+            PT_TRY(launch_check());
+            std::swap(Ga, Gb);
+            std::swap(Ga_th, Gb_th);
+        }
+    }
+    B.out_T = outT;
+    B.out_th = outth;
+    hipLaunchKernelGGL(k_finalize_fwd, dim3(256), dim3(256), 0, stream, C, B, Theta_out, outT,
+                       outth, 0);
+    return launch_check();
+}
+
+int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double *S,
+                        const double *Theta, const double *guess_lambda, double *lambda_out,
+                        void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (!valid_problem(prob)) return PT_EINVAL;
+    if (!rho || !S || !Theta || !ws) return PT_EINVAL;
+    const Layout Lay = layout(prob);
+    if (ws_bytes < Lay.total) return PT_ENOMEM;
+    const Consts C = make_consts(prob);
+    const size_t Nn = C.Nn, Nt1 = C.Ntau + 1;
+    const size_t sz_U = Nt1 * Nn * sizeof(double);
+    if (guess_lambda) {
+        if (overlaps(guess_lambda, sz_U, lambda_out, sz_U) ||
+            overlaps(guess_lambda, sz_U, ws, ws_bytes))
+            return PT_EINVAL;
+    }
+    if (overlaps(lambda_out, sz_U, ws, ws_bytes)) return PT_EINVAL;
+    Bufs B = make_bufs(ws, Lay);
+    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, stream, B.ctl, 1);
+    PT_TRY(setup_design(prob, C, B, rho, ws, Lay, stream));
+
+    double *outL = lambda_out ? lambda_out : at<double>(ws, Lay.Lbuf);
+    double *Lprev = at<double>(ws, Lay.Lprev);
+    double *Ga = at<double>(ws, Lay.Gk), *Gb = at<double>(ws, Lay.Gn);
+    const bool cold = guess_lambda == nullptr;
+    const int Ntau = C.Ntau;
+    for (int it = 0; it < prob->iterations; ++it) {
+        LaunchInfo I{};
+        I.cold = (cold && it == 0) ? 1 : 0;
+        I.gk_lanes = (!cold && it == 0 && Ntau > 1) ? 1 : 0;
+        I.has_dc = (prob->c0 != prob->cmin) ? 1 : 0;
+        I.epoch = 1;
+        B.S = const_cast<double *>(S);
+        B.Theta = Theta;
+        B.in_L = it == 0 ? guess_lambda : Lprev;
+        B.out_L = outL;
+        B.Gk = Ga;
+        B.Gn = Gb;
+        std::vector<LanePlan> plans;
+        LanePlan f{F_ADJ, Ntau, 1, 1, (double)C.M};
+        plans.push_back(f);
+        if (I.gk_lanes) {
+            LanePlan gk{GK_ADJ, Ntau - 1, 1, 1, 4.0};
+            plans.push_back(gk);
+        }
+        if (I.cold) {
+            LanePlan cl{COLD_ADJ, 1, 0, 1, 0.0};
+            plans.push_back(cl);
+        }
+        if (Ntau > 1) {
+            LanePlan sw{SWEEP_ADJ, 1, 0, 1, 0.0};
+            plans.push_back(sw);
+        }
+        PT_TRY(run_engine(C, B, I, plans, ws, Lay, stream, 32));
+        if (it + 1 < prob->iterations) {
+            hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Lprev, outL, Nt1 * Nn);
+            PT_TRY(launch_check());
+            std::swap(Ga, Gb);
+        }
+    }
+    B.out_L = outL;
+    hipLaunchKernelGGL(k_finalize_adj, dim3(256), dim3(256), 0, stream, C, B);
+    return launch_check();
+}
+
+int pt_sensitivities(const pt_problem *prob, const double *rho, const void *ws, size_t ws_bytes,
+                     double *dTheta_drho, hipStream_t stream) {
+    if (!valid_problem(prob)) return PT_EINVAL;
+    if (!rho || !ws || !dTheta_drho) return PT_EINVAL;
+    const Layout Lay = layout(prob);
+    if (ws_bytes < Lay.total) return PT_ENOMEM;
+    const Consts C = make_consts(prob);
+    void *w = const_cast<void *>(ws);
+    hipLaunchKernelGGL(k_sensitivities, dim3(512), dim3(256), 0, stream, C, at<double>(w, Lay.acc),
+                       at<double>(w, Lay.accG), dTheta_drho);
+    return launch_check();
+}
+
+int pt_query_status(const void *ws, hipStream_t stream, pt_stats *out) {
+    if (!ws || !out) return PT_EINVAL;
+    PT_TRY(hip_ok(hipStreamSynchronize(stream)));
+    Control c;
+    PT_TRY(hip_ok(hipMemcpy(&c, ws, sizeof(Control), hipMemcpyDeviceToHost)));
+    memset(out, 0, sizeof(*out));
+    out->status = c.status;
+    out->max_cg_iters = c.max_iters;
+    out->cg_iters_fine = (int64_t)c.iters_fine;
+    out->cg_iters_coarse = (int64_t)c.iters_coarse;
+    out->solves_fine = (int64_t)c.solves_fine;
+    out->solves_coarse = (int64_t)c.solves_coarse;
+    double r;
+    memcpy(&r, &c.max_relres_bits, sizeof(double));
+    out->max_rel_residual = r;
+    return PT_OK;
+}
+
+}  // extern "C"

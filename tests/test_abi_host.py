@@ -1,0 +1,119 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/pt.h declares, and rejects invalid arguments before
+anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2411_19030_amd import _pt
+from paper_2411_19030_amd._pt import Problem, PtProblem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_pt.LIB_PATH):
+        pytest.fail("libpt.so is not built (run __graft_entry__.build())")
+    return _pt.load_library()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pt_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert set(names) >= set(_pt.EXPORTS) - set()
+    for n in names:
+        assert hasattr(lib, n), n
+        assert getattr(lib, n) is not None
+
+
+def base(**kw):
+    p = dict(nx=8, ny=8, n_steps=16, n_slices=4)
+    p.update(kw)
+    return Problem(**p)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(pnorm=7), dict(pnorm=0), dict(n_slices=5), dict(nx=0), dict(ny=-1),
+    dict(cg_rtol=0.0), dict(cg_rtol=float("nan")), dict(max_iter=0), dict(iterations=0),
+    dict(t_final=0.0), dict(kmin=0.0), dict(pk=0.5), dict(precision=7), dict(precond=9),
+    dict(storage=4), dict(n_steps=0), dict(q=float("inf")),
+])
+def test_validate_rejects(lib, kw):
+    p = base(**kw)
+    assert _pt.pt_validate(p) == _pt.PT_EINVAL
+    assert _pt.pt_workspace_bytes(p) == 0
+
+
+def test_validate_accepts_and_sizes(lib):
+    p = base()
+    assert _pt.pt_validate(p) == _pt.PT_OK
+    small = _pt.pt_workspace_bytes(p)
+    big = _pt.pt_workspace_bytes(base(nx=64, ny=64))
+    assert 0 < small < big
+
+
+def test_time_dependent_source_must_be_finite(lib):
+    import numpy as np
+    q = np.ones(17)
+    assert _pt.pt_validate(base(q=q)) == _pt.PT_OK
+    q[3] = np.nan
+    assert _pt.pt_validate(base(q=q)) == _pt.PT_EINVAL
+
+
+def _fwd(lib, p, rho=0x1000, gT=None, gth=None, S=0x2000, uT=None, uth=None, Th=0x3000,
+         ws=0x10000000, nbytes=None):
+    c = p.to_c()
+    if nbytes is None:
+        nbytes = lib.pt_workspace_bytes(ctypes.byref(c))
+    return lib.pt_parareal_forward(ctypes.byref(c), rho, gT, gth, S, uT, uth, Th, ws, nbytes,
+                                   None)
+
+
+def test_forward_argument_errors_before_any_device_work(lib):
+    p = base()
+    assert _fwd(lib, p, rho=None) == _pt.PT_EINVAL
+    assert _fwd(lib, p, S=None) == _pt.PT_EINVAL
+    assert _fwd(lib, p, Th=None) == _pt.PT_EINVAL
+    assert _fwd(lib, p, ws=None) == _pt.PT_EINVAL
+    assert _fwd(lib, p, gT=0x5000, gth=None) == _pt.PT_EINVAL
+    assert _fwd(lib, p, nbytes=16) == _pt.PT_ENOMEM
+    # a guess that overlaps the S output is rejected
+    assert _fwd(lib, p, gT=0x2000, gth=0x9000000) == _pt.PT_EINVAL
+    assert _fwd(lib, base(pnorm=3)) == _pt.PT_EINVAL
+
+
+def test_adjoint_and_sensitivity_argument_errors(lib):
+    p = base()
+    c = p.to_c()
+    nb = lib.pt_workspace_bytes(ctypes.byref(c))
+    assert lib.pt_parareal_adjoint(ctypes.byref(c), None, 0x2000, 0x3000, None, None,
+                                   0x10000000, nb, None) == _pt.PT_EINVAL
+    assert lib.pt_parareal_adjoint(ctypes.byref(c), 0x1000, 0x2000, 0x3000, None, None,
+                                   0x10000000, 8, None) == _pt.PT_ENOMEM
+    assert lib.pt_sensitivities(ctypes.byref(c), 0x1000, 0x10000000, nb, None,
+                                None) == _pt.PT_EINVAL
+    assert lib.pt_sensitivities(ctypes.byref(c), 0x1000, 0x10000000, 8, 0x4000,
+                                None) == _pt.PT_ENOMEM
+
+
+def test_strerror(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6, -99):
+        assert isinstance(lib.pt_strerror(code), bytes)
+
+
+def test_struct_layout_matches_header():
+    """Field order and offsets of the ctypes mirror follow pt.h (natural alignment)."""
+    offs = {name: getattr(PtProblem, name).offset for name, _ in PtProblem._fields_}
+    assert offs["nx"] == 0 and offs["ny"] == 4 and offs["k0"] == 8
+    assert offs["q_t"] == 64 and offs["t_final"] == 72 and offs["n_steps"] == 80
+    assert offs["cg_rtol"] == 96 and offs["max_iter"] == 104
+    assert offs["dirichlet_mask"] == 128
+    assert ctypes.sizeof(PtProblem) == 136
