@@ -1,0 +1,187 @@
+"""Benchmark: fine-step cell-updates/s of one optimisation cycle on one MI355X.
+
+A step is one warm one-shot cycle (Alg. 3 lines 9-12): pt_parareal_forward
+(modified Parareal primal pass), pt_parareal_adjoint (reversed Parareal adjoint
+pass) and pt_sensitivities, one Parareal iteration, with the previous cycle's
+solution as the guess. The workload is the 256 x 256 FP64 problem (512
+backward-Euler steps in 32 slices, SIMP k(rho) = 1e-3 + rho^3 (1 - 1e-3),
+seeded rho = 0.3 + U(-0.1, 0.1), q = 1, Jacobi-PCG to relative residual
+1e-10); the guess for the timed cycles comes from one untimed cold cycle on
+the same design. Work per cycle = N_e * N_t cell updates.
+
+Prints one JSON line. `roofline` reports the lane engine (the kernel that runs
+each whole pass) against HBM peak with the algorithmic byte model:
+per node and CG iteration 12 words, plus 4 words per node and fine step in the
+primal pass and 7 in the adjoint pass (FP64). `cpu_baseline` times the FP64
+oracle (one thread) on a cold cycle of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "plain_fp64_256"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
+    return ap.parse_args()
+
+
+def cpu_sample() -> dict:
+    """Oracle cold cycle on the benchmark workload (runs in a 1-thread child)."""
+    import numpy as np  # noqa: F401
+
+    import oracle as O
+    from workloads import workload, workload_density
+    w = workload(WORKLOAD)
+    P = O.Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
+                  p=w["p"], k0=w["k0"], kmin=w["kmin"], pk=w["pk"], c0=w["c0"],
+                  cmin=w["cmin"], pc=w["pc"], q=w["q"], t_final=w["t_final"], bc=w["bc"])
+    rho = workload_density(WORKLOAD)
+    t0 = time.perf_counter()
+    d = O.Discretisation(P, rho)
+    fw = O.parareal_forward(d, 1)
+    ad = O.parareal_adjoint(d, fw["S"], fw["Theta"], 1)
+    t = time.perf_counter() - t0
+    cells = w["nx"] * w["ny"] * w["n_steps"]
+    return dict(seconds=t, cells=cells, Theta=fw["Theta"], grad_norm=float(
+        np.linalg.norm(ad["grad"])))
+
+
+def cpu_baseline() -> dict:
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample-only"],
+                         capture_output=True, text=True, env=env, timeout=900)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    return {"value": r["cells"] / r["seconds"], "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"one cold one-iteration cycle (forward + adjoint + sensitivities) of "
+                       f"the {WORKLOAD} workload by the FP64 oracle, sparse LU per step, one "
+                       f"thread: {r['seconds']:.1f} s for {r['cells']} cell updates")}
+
+
+def main():
+    args = parse()
+    if args.cpu_sample_only:
+        print(json.dumps(cpu_sample()))
+        return
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the pass would shard by time slices across GPUs, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2411_19030_amd import Problem, load_library
+    from paper_2411_19030_amd.cycle import Cycle
+    from workloads import workload, workload_density
+
+    load_library()
+    w = workload(WORKLOAD)
+    prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
+                   pnorm=w["p"], k0=w["k0"], kmin=w["kmin"], pk=w["pk"], c0=w["c0"],
+                   cmin=w["cmin"], pc=w["pc"], q=w["q"], t_final=w["t_final"], bc=w["bc"],
+                   iterations=1, cg_rtol=w["rtol"], max_iter=20000)
+    dev = torch.device("cuda:0")
+    cyc = Cycle(prob, dev)
+    rho = torch.tensor(workload_density(WORKLOAD), dtype=torch.float64, device=dev)
+    # cold cycle: the guess of the timed warm cycles
+    cyc.run(rho)
+    torch.cuda.synchronize()
+    gT, gth, gl = cyc.uT.clone(), cyc.utheta.clone(), cyc.lam.clone()
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        if events:
+            events[0].record(stream)
+        cyc.forward(rho, gT, gth)
+        if events:
+            events[1].record(stream)
+        cyc.adjoint(rho, gl)
+        if events:
+            events[2].record(stream)
+        cyc.sensitivities(rho)
+        if events:
+            events[3].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # per-pass CG iteration counts (identical every cycle: same design and guess)
+    cyc.forward(rho, gT, gth)
+    st_f = cyc.status()
+    cyc.adjoint(rho, gl)
+    st_a = cyc.status()
+    cyc.sensitivities(rho)
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_fwd = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    t_adj = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    t_sen = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
+    ms = wall * 1e3 / args.steps
+    st = cyc.status()
+
+    Nn, Ne, Nt = prob.n_nodes, prob.n_elem, prob.n_steps
+    cells = Ne * Nt
+    it_f = st_f["cg_iters_fine"] + st_f["cg_iters_coarse"]
+    it_a = st_a["cg_iters_fine"] + st_a["cg_iters_coarse"]
+    bytes_f = 8.0 * Nn * (12 * it_f + 4 * Nt)
+    bytes_a = 8.0 * Nn * (12 * it_a + 7 * Nt)
+    achieved = (bytes_f + bytes_a) / ((t_fwd + t_adj) * 1e-3) / 1e9
+    out = {
+        "metric": "fine-step cell-updates/s (fwd+adjoint+sens per cycle), % HBM peak, vs FP64",
+        "value": cells / (ms * 1e-3),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "nx": prob.nx, "ny": prob.ny, "n_steps": Nt,
+                   "n_slices": prob.n_slices, "pnorm": prob.pnorm, "cg_rtol": prob.cg_rtol,
+                   "parareal_iterations": 1, "guess": "previous (cold) cycle",
+                   "precision": "fp64", "preconditioner": "jacobi"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
+        "phase_ms": {"forward": t_fwd, "adjoint": t_adj, "sensitivities": t_sen},
+        "cg_iterations": {"forward": it_f, "adjoint": it_a},
+        "status": st["status"],
+        "Theta": float(cyc.Theta),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

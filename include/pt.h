@@ -146,6 +146,19 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
 int pt_sensitivities(const pt_problem *prob, const double *rho, const void *ws,
                      size_t ws_bytes, double *dTheta_drho, hipStream_t stream);
 
+/*
+ * Lane trace of the last engine launch (profiling aid). Synchronises `stream`
+ * and copies up to out_words 64-bit words: n_lanes records of `stride` words,
+ * each [kind, slice, workgroups, tile, group barriers, CG iterations,
+ * start tick, ticks working, ticks in barriers, ticks reducing, ticks waiting
+ * on other lanes, unused, end tick of step 0, 1, ...], ticks of the device's
+ * 100 MHz real-time clock; unused records are zero. Lane kinds: 0 fine primal,
+ * 1 batched coarse primal, 2 primal sweep, 3 cold primal sweep, 4-7 the adjoint
+ * counterparts.
+ */
+int pt_query_trace(const pt_problem *prob, const void *ws, hipStream_t stream,
+                   unsigned long long *out, size_t out_words, int *n_lanes, int *stride);
+
 /* Synchronises `stream`, then reads the device status and counters in ws. */
 int pt_query_status(const void *ws, hipStream_t stream, pt_stats *out);
 

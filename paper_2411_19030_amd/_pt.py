@@ -23,7 +23,7 @@ PT_JACOBI, PT_GMG = 0, 1
 PT_STORE_ALL, PT_CHECKPOINT = 0, 1
 
 EXPORTS = ["pt_workspace_bytes", "pt_validate", "pt_parareal_forward", "pt_parareal_adjoint",
-           "pt_sensitivities", "pt_query_status", "pt_strerror"]
+           "pt_sensitivities", "pt_query_status", "pt_query_trace", "pt_strerror"]
 
 
 class PtProblem(ctypes.Structure):
@@ -77,6 +77,9 @@ def load_library(path: str = LIB_PATH):
     lib.pt_sensitivities.restype = ctypes.c_int
     lib.pt_query_status.argtypes = [vp, vp, ctypes.POINTER(PtStats)]
     lib.pt_query_status.restype = ctypes.c_int
+    lib.pt_query_trace.argtypes = [P, vp, vp, ctypes.POINTER(ctypes.c_ulonglong), ctypes.c_size_t,
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.pt_query_trace.restype = ctypes.c_int
     lib.pt_strerror.argtypes = [ctypes.c_int]
     lib.pt_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -210,6 +213,38 @@ def pt_sensitivities(prob: Problem, rho, ws, dTheta_drho, stream=None, check: bo
     if check:
         _check(rc, "pt_sensitivities")
     return rc
+
+
+LANE_KINDS = ["F_PRI", "GK_PRI", "SWEEP_PRI", "COLD_PRI", "F_ADJ", "GK_ADJ", "SWEEP_ADJ",
+              "COLD_ADJ"]
+
+
+def pt_query_trace(prob: Problem, ws, stream=None) -> list:
+    """Per-lane records of the last engine launch: dicts with kind, slice,
+    nwg, tile, rounds, iters and step end times in microseconds from the
+    earliest lane start."""
+    c = prob.to_c()
+    words = 1 << 22
+    buf = (ctypes.c_ulonglong * words)()
+    nl, st = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().pt_query_trace(ctypes.byref(c), _ptr(ws), _stream(stream), buf, words,
+                                         ctypes.byref(nl), ctypes.byref(st)), "pt_query_trace")
+    arr = np.frombuffer(buf, dtype=np.uint64, count=nl.value * st.value).reshape(nl.value,
+                                                                                 st.value)
+    recs = [r for r in arr if r[6] != 0]
+    hdr = 12
+    if not recs:
+        return []
+    t0 = min(int(r[6]) for r in recs)
+    out = []
+    for r in recs:
+        steps = [(int(x) - t0) / 100.0 for x in r[hdr:] if x != 0]
+        out.append(dict(kind=LANE_KINDS[int(r[0])], slice=int(r[1]), nwg=int(r[2]),
+                        tile=int(r[3]), rounds=int(r[4]), iters=int(r[5]),
+                        start_us=(int(r[6]) - t0) / 100.0, step_end_us=steps,
+                        work_us=int(r[7]) / 100.0, barrier_us=int(r[8]) / 100.0,
+                        reduce_us=int(r[9]) / 100.0, flag_us=int(r[10]) / 100.0))
+    return out
 
 
 def pt_query_status(ws, stream=None) -> dict:

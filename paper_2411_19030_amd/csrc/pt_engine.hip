@@ -1,31 +1,38 @@
 // Lane engine: one persistent cooperative launch runs every propagator of one
 // Parareal pass (Sec. 4.2-4.4) on gfx950.
 //
-// A *lane* is a sequence of backward-Euler solves (C/delta + K) x = b executed
-// by a fixed group of workgroups: the fine propagator of one time slice (M
-// steps of Alg. 1 or Alg. 2 with dt), one batched coarse step G(u^k_n), the
-// cold coarse sweep, or the sequential correction sweep (Eq. 4.2 / Eq. 4.9).
-// All lanes of a pass run concurrently; a lane waits on a device flag only
-// where the method has a true data dependence (the sweep step n needs F_n and
-// G(u^k_n); a cold-started slice needs its coarse guess). The sequential
-// coarse sweep therefore overlaps the bandwidth-bound fine slices instead of
-// following them.
+// A *lane* is a sequence of backward-Euler solves (C/delta + K) x = b: the
+// fine propagator of one time slice (M steps of Alg. 1 or Alg. 2 with dt), one
+// batched coarse step G(u^k_n), the cold coarse sweep, or the sequential
+// correction sweep (Eq. 4.2 / Eq. 4.9). A *group* of workgroups runs a queue of
+// lanes one after another. All groups of a pass run concurrently; a lane waits
+// on a device flag only where the method has a true data dependence (the
+// sweep step n needs F_n and G(u^k_n); a cold-started slice needs its coarse
+// guess). Fine slices are queued in the order the sweep consumes them, so the
+// latency-bound sequential sweep overlaps the bandwidth-bound fine slices.
 //
 // Each solve is a Jacobi-preconditioned conjugate gradient in the single-
 // reduction form of Chronopoulos and Gear: one group barrier per iteration,
 // which both publishes the halo values of the iteration's vectors and combines
-// the three dot products (r,z), (z,Az), (r,r). The workgroups of a group own
-// contiguous node ranges ("tiles") of the lane's vectors; every tile is staged
-// in LDS with a halo of one grid row plus one node on each side, so the 9-point
-// Q1 stencil reads LDS only. The halo values of z = D^{-1} r_{i+1} are
-// recomputed locally from r_i, w_i, s_{i-1} (pointwise), which is why one
-// barrier per iteration suffices. Vectors that neighbours read in the same
-// round are double-buffered by iteration parity.
+// the dot products (r,z), (z,Az), (r,r). The workgroups of a group own
+// contiguous node ranges ("tiles"); every tile is staged in LDS with a halo of
+// one grid row plus one node on each side, so the 9-point Q1 stencil reads LDS
+// only. The halo values of z = D^{-1} r_{i+1} are recomputed locally from
+// r_i, w_i, s_{i-1} (pointwise), which is why one barrier per iteration
+// suffices; vectors that neighbours read in the same round are double-buffered
+// by iteration parity.
+//
+// Round data shared between workgroups (lane vectors, partial sums) is moved
+// with device-coherent (agent-scope) loads and stores, and a barrier drains
+// the workgroup's memory counters before its relaxed arrival increment; this
+// avoids the cache-wide write-back / invalidate of agent-scope fences, which
+// dominate a round on a multi-XCD part. Full release/acquire fences are kept
+// where a lane hands results to another lane (flags) and where a lane's plain
+// stores must become visible to other groups.
 //
 // Control state (step, phase, alpha, beta, theta ...) is replicated: every
 // workgroup of a group reduces the same partial sums in the same order and
-// takes the same decisions, so no broadcast is needed. Reductions are
-// deterministic (fixed order), so results are bitwise reproducible.
+// takes the same decisions. Reductions are deterministic (fixed order).
 #include "pt_internal.h"
 
 namespace pt {
@@ -35,6 +42,7 @@ namespace {
 enum Phase : int { PH_INIT = 0, PH_FIRST = 1, PH_ITER = 2, PH_POST = 3, PH_DONE = 4 };
 
 constexpr int kWaves = kThreads / 64;
+constexpr int kU = 4;  // independent loads in flight per thread in streaming loops
 
 __device__ __forceinline__ double ipow(double x, int n) {
     double r = 1.0, b = x;
@@ -50,6 +58,14 @@ __device__ __forceinline__ long long now_ticks() {
     return (long long)__builtin_amdgcn_s_memrealtime();
 }
 
+// device-coherent accesses for data exchanged between workgroups within a launch
+__device__ __forceinline__ double ldc(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stc(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void set_status(Control *ctl, int code) {
     atomicCAS(&ctl->status, 0, code);
 }
@@ -58,14 +74,34 @@ __device__ __forceinline__ bool aborted(Control *ctl) {
     return __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-// Group barrier: counter += 1 per workgroup; wait until it reaches target.
-// Returns false if the wait timed out or another workgroup aborted.
-__device__ bool group_barrier(unsigned *cnt, unsigned target, Control *ctl, long long timeout) {
+// Workgroup barrier for LDS only: waits for this wave's LDS operations and
+// synchronises the waves, but leaves global loads and stores in flight
+// (__syncthreads also drains the vector memory counter, which would expose a
+// memory round trip at every intra-workgroup sync). Global data is never
+// exchanged between threads of a workgroup within a round.
+__device__ __forceinline__ void lds_sync() {
+    asm volatile("" ::: "memory");
+    // lgkmcnt(0); vmcnt and expcnt left at their maxima (no wait)
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Group barrier. Every wave first waits for its own memory operations (the
+// device-coherent stores of this round) to complete; thread 0 then increments
+// the group counter and spins until all g workgroups have arrived. With
+// `release`, thread 0 also issues an agent-scope release fence first, which
+// publishes this workgroup's plain stores to other XCDs. Returns false on
+// timeout or when another workgroup aborted.
+__device__ bool group_barrier(unsigned *cnt, unsigned target, Control *ctl, long long timeout,
+                              bool release) {
     __shared__ int s_ok;
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (release) __threadfence();
+        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
         long long t0 = now_ticks();
         while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -75,14 +111,15 @@ __device__ bool group_barrier(unsigned *cnt, unsigned target, Control *ctl, long
                 break;
             }
         }
-        __threadfence();
         s_ok = ok;
     }
     __syncthreads();
+    asm volatile("" ::: "memory");
     return s_ok != 0;
 }
 
-// Wait until flags[idx] == epoch (set by a producer group's leader).
+// Wait until flags[idx] == epoch (set by a producer group's leader), then
+// acquire at agent scope so the producer's plain stores are visible.
 __device__ bool wait_flag(unsigned *flags, int idx, unsigned epoch, Control *ctl,
                           long long timeout) {
     __shared__ int s_ok;
@@ -104,8 +141,8 @@ __device__ bool wait_flag(unsigned *flags, int idx, unsigned epoch, Control *ctl
     return s_ok != 0;
 }
 
+// Called by thread 0 of the group leader after a release barrier.
 __device__ void set_flag(unsigned *flags, int idx, unsigned epoch) {
-    // called by thread 0 of the group leader after a group barrier
     __threadfence();
     __hip_atomic_store(&flags[idx], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -123,13 +160,13 @@ __device__ void block_sum(double (&v)[Q], double *red) {
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0)
         for (int q = 0; q < Q; ++q) red[wave * Q + q] = v[q];
-    __syncthreads();
+    lds_sync();
     for (int q = 0; q < Q; ++q) {
         double t = 0.0;
         for (int w = 0; w < kWaves; ++w) t += red[w * Q + q];
         v[q] = t;
     }
-    __syncthreads();
+    lds_sync();
 }
 
 // Sum partials[0..g)[0..Q) in a fixed order (identical in every workgroup).
@@ -138,7 +175,7 @@ __device__ void group_sum(const double *part, int g, double (&out)[Q], double *r
     double v[Q];
     for (int q = 0; q < Q; ++q) v[q] = 0.0;
     for (int r = threadIdx.x; r < g; r += kThreads)
-        for (int q = 0; q < Q; ++q) v[q] += part[r * 4 + q];
+        for (int q = 0; q < Q; ++q) v[q] += ldc(part + r * 4 + q);
     block_sum<Q>(v, red);
     for (int q = 0; q < Q; ++q) out[q] = v[q];
 }
@@ -168,6 +205,55 @@ __device__ __forceinline__ Coef node_coef(const Consts &C, const double *kq, con
     a.se = mSE + C.e_d * kSE;
     a.sw = mSW + C.e_d * kSW;
     return a;
+}
+
+// Same, with k/6 and c hx hy/36 read from LDS element windows that start at
+// padded element index ea.
+__device__ __forceinline__ Coef node_coef_l(const Consts &C, const double *LK, const double *LC,
+                                            int ea, int i, int j, double ms, double ks) {
+    const int eSW = j * C.EW + i - ea, eSE = eSW + 1, eNW = eSW + C.EW, eNE = eNW + 1;
+    const double mSW = LC[eSW] * ms, mSE = LC[eSE] * ms, mNW = LC[eNW] * ms, mNE = LC[eNE] * ms;
+    const double kSW = LK[eSW] * ks, kSE = LK[eSE] * ks, kNW = LK[eNW] * ks, kNE = LK[eNE] * ks;
+    Coef a;
+    a.c = 4.0 * (mSW + mSE + mNW + mNE) + C.e_self * (kSW + kSE + kNW + kNE);
+    a.e = 2.0 * (mSE + mNE) + C.e_x * (kSE + kNE);
+    a.w = 2.0 * (mSW + mNW) + C.e_x * (kSW + kNW);
+    a.n = 2.0 * (mNW + mNE) + C.e_y * (kNW + kNE);
+    a.s = 2.0 * (mSW + mSE) + C.e_y * (kSW + kSE);
+    a.ne = mNE + C.e_d * kNE;
+    a.nw = mNW + C.e_d * kNW;
+    a.se = mSE + C.e_d * kSE;
+    a.sw = mSW + C.e_d * kSW;
+    return a;
+}
+
+// Element rows a node tile [a, b) touches: padded rows a/W .. (b-1)/W + 1.
+__device__ __forceinline__ void elem_window(const Consts &C, int a, int b, int &ea, int &elen) {
+    const int ja = a / C.W, jb = (b - 1) / C.W;
+    ea = ja * C.EW;
+    elen = (jb - ja + 2) * C.EW;
+}
+
+// Stage kq, cm of the element window into LDS (coalesced, several loads in flight).
+__device__ __forceinline__ void stage_elems(const Bufs &B, int ea, int elen, double *LK,
+                                            double *LC) {
+    for (int q0 = threadIdx.x; q0 < elen; q0 += kThreads * 4) {
+        double kv[4], cv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u * kThreads;
+            kv[u] = q < elen ? B.kq[ea + q] : 0.0;
+            cv[u] = q < elen ? B.cm[ea + q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u * kThreads;
+            if (q < elen) {
+                LK[q] = kv[u];
+                LC[q] = cv[u];
+            }
+        }
+    }
 }
 
 __device__ __forceinline__ double apply(const Coef &a, const double *L, int li, int W) {
@@ -203,10 +289,11 @@ struct StepInfo {
     int n;            // coarse index of coarse kinds / slice of fine kinds
     int j;            // fine time index: load index (primal) or source index (adjoint)
     int jprev;        // adjoint: index of T_{j-1} or T_{m-M} (<= 0 means T_0 = 0)
-    const double *tp_src;  // vector for C/delta * tp (RHS), never written this round
+    const double *tp_src;  // vector for C/delta * tp (RHS); coherent loads
     const double *x0_src;  // initial guess; nullptr means "x already holds it"
     bool wait;        // a flag must be awaited before INIT
     int wait_idx;
+    bool extrap;      // x0 = 2 x - tq (two previous states of a fine lane)
 };
 
 __device__ __forceinline__ int lane_steps(const Consts &C, int kind) {
@@ -221,19 +308,20 @@ __device__ __forceinline__ int lane_steps(const Consts &C, int kind) {
     }
 }
 
-__device__ __forceinline__ double *lane_vec(const Bufs &B, const Consts &C, int vec, int which) {
+enum { V_X = 0, V_P = 1, V_R0 = 2, V_R1 = 3, V_W0 = 4, V_W1 = 5, V_S0 = 6, V_S1 = 7, V_TP = 8, V_TQ = 9 };
+
+__device__ __forceinline__ double *group_vec(const Bufs &B, const Consts &C, int vec, int which) {
     return B.pool + ((size_t)vec * kVecsPerLane + which) * (size_t)C.Nn;
 }
-enum { V_X = 0, V_P = 1, V_R0 = 2, V_R1 = 3, V_W0 = 4, V_W1 = 5, V_S0 = 6, V_S1 = 7, V_TP = 8 };
 
 __device__ StepInfo step_info(const Consts &C, const Bufs &B, const LaunchInfo &I, const Lane &L,
-                              int s) {
+                              int s, const double *tpbuf) {
     StepInfo st;
     const size_t Nn = C.Nn;
-    const double *tpbuf = lane_vec(B, C, L.vec, V_TP);
     st.wait = false;
     st.wait_idx = 0;
     st.jprev = 0;
+    st.extrap = C.extrap && (L.kind == F_PRI || L.kind == F_ADJ) && s >= 2;
     switch (L.kind) {
         case F_PRI: {
             const int n = L.slice;
@@ -355,7 +443,7 @@ __device__ StepInfo step_info(const Consts &C, const Bufs &B, const LaunchInfo &
             st.n = n;
             st.j = C.M * (n - 1) + 1;
             st.jprev = st.j - C.M;
-            st.tp_src = (n == C.Ntau - 1) ? lane_vec(B, C, B.fvec[C.Ntau], V_X) : tpbuf;
+            st.tp_src = (n == C.Ntau - 1) ? B.FL + (size_t)C.Ntau * Nn : tpbuf;
             st.x0_src = B.Gk + (size_t)n * Nn;
             break;
         }
@@ -371,6 +459,28 @@ struct Ctl {
     double theta;      // primal: theta carried by the lane
     double src_scale;  // adjoint: Theta^{1-p} / N_e
 };
+
+// Per-element sensitivity term lambda^T (dk K0 T + dc C0 (T - Tp)/delta) of the
+// element whose lower-left node is id (Eq. 4.8 summand for one element).
+__device__ __forceinline__ double sens_term(const Consts &C, const Bufs &B, const LaunchInfo &I,
+                                            int id, int e, double l0, double l1, double l2,
+                                            double l3, const double *Tr, const double *Tp,
+                                            double inv_delta) {
+    const double t0 = Tr[id], t1 = Tr[id + 1], t2 = Tr[id + C.W + 1], t3 = Tr[id + C.W];
+    double term = B.dk[e] * elem_k(C, l0, l1, l2, l3, t0, t1, t2, t3);
+    if (I.has_dc) {
+        double p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+        if (Tp) {
+            p0 = Tp[id];
+            p1 = Tp[id + 1];
+            p2 = Tp[id + C.W + 1];
+            p3 = Tp[id + C.W];
+        }
+        term += B.dc[e] * inv_delta *
+                elem_c(C, l0, l1, l2, l3, t0 - p0, t1 - p1, t2 - p2, t3 - p3);
+    }
+    return term;
+}
 
 }  // namespace
 
@@ -450,484 +560,756 @@ __global__ void k_copy_f64(double *dst, const double *src, size_t n) {
 // ---------------------------------------------------------------------------
 // The engine
 // ---------------------------------------------------------------------------
+template <int NPT>
 __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInfo I) {
     extern __shared__ double lds[];
     __shared__ double red[kWaves * 4];
 
-    const int lane_id = B.wg_lane[blockIdx.x];
-    if (lane_id < 0) return;
-    const Lane L = B.lanes[lane_id];
-    const int rank = blockIdx.x - L.wg0;
-    const int g = L.nwg;
-    const int H = C.W + 1;           // halo on each side of a tile window
-    const int TS = L.tile;
+    const int gid = B.wg_group[blockIdx.x];
+    if (gid < 0) return;
+    const Group G = B.groups[gid];
+    const int rank = blockIdx.x - G.wg0;
+    const int g = G.nwg;
+    const int H = C.W + 1;  // halo on each side of a tile window
+    const int TS = G.tile;
     const int win = TS + 2 * H;
-    double *LA = lds;                // window A
-    double *LB = lds + win;          // window B (INIT only)
+    const int ewin = ((TS - 1) / C.W + 3) * C.EW;  // element window bound
+    double *LA = lds;        // window A (halo'd)
+    double *LB = lds + win;  // window B (INIT) / own residuals (ITER)
+    double *LK = lds + 2 * win;          // k/6 of the tile's elements
+    double *LC = lds + 2 * win + ewin;   // c hx hy/36 of the tile's elements
     const int ntiles = (C.Nn + TS - 1) / TS;
     Control *ctl = B.ctl;
-    unsigned *bar = B.bar + lane_id;
-    double *part = B.partials + (size_t)lane_id * 2 * kMaxGroup * 4;
+    unsigned *bar = B.bar + gid;
+    double *part = B.partials + (size_t)gid * 2 * kMaxGroup * 4;
     unsigned nbar = 0;
+    const long long tmo = C.timeout_ticks;
 
-    double *X = lane_vec(B, C, L.vec, V_X);
-    double *P = lane_vec(B, C, L.vec, V_P);
-    double *TP = lane_vec(B, C, L.vec, V_TP);
-    double *Rb[2] = {lane_vec(B, C, L.vec, V_R0), lane_vec(B, C, L.vec, V_R1)};
-    double *Wb[2] = {lane_vec(B, C, L.vec, V_W0), lane_vec(B, C, L.vec, V_W1)};
-    double *Sb[2] = {lane_vec(B, C, L.vec, V_S0), lane_vec(B, C, L.vec, V_S1)};
+    double *X = group_vec(B, C, G.vec, V_X);
+    double *P = group_vec(B, C, G.vec, V_P);
+    double *TP = group_vec(B, C, G.vec, V_TP);
+    double *TQ = group_vec(B, C, G.vec, V_TQ);
+    double *Rb[2] = {group_vec(B, C, G.vec, V_R0), group_vec(B, C, G.vec, V_R1)};
+    double *Wb[2] = {group_vec(B, C, G.vec, V_W0), group_vec(B, C, G.vec, V_W1)};
+    double *Sb[2] = {group_vec(B, C, G.vec, V_S0), group_vec(B, C, G.vec, V_S1)};
 
-    Ctl c;
-    c.step = 0;
-    c.nsteps = lane_steps(C, L.kind);
-    c.phase = c.nsteps > 0 ? PH_INIT : PH_DONE;
-    c.iter = 0;
-    c.it_local = 0;
-    c.restarts = 0;
-    c.verifying = false;
-    c.zero_x = false;
-    c.alpha = c.beta = c.gamma = 0.0;
-    c.bnorm = c.relres = 0.0;
-    c.theta = 0.0;
-    c.src_scale = 0.0;
-    const bool is_adj = L.kind >= F_ADJ;
-    if (is_adj) {
-        const double Th = *B.Theta;
-        c.src_scale = pow(Th, 1.0 - C.p) / (double)C.Ne;
-        if (!(Th > 0.0) || !isfinite(Th)) set_status(ctl, -5);
+    // resident mode (NPT > 0): this workgroup's tile values of p, r, w, s live
+    // in registers across rounds, D^{-1} of the tile in LDS, x in global memory
+    // (updated in place each round); the tile's element window is staged once.
+    constexpr int NR = NPT > 0 ? NPT : 1;
+    double rp[NR], rr[NR], rw[NR], rs[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) rp[k] = rr[k] = rw[k] = rs[k] = 0.0;
+    double *LD = LB;  // resident: D^{-1} of the tile (LB is free after FIRST)
+    int ea_res = 0;
+    if constexpr (NPT > 0) {
+        const int a = min(rank * TS, C.Nn);
+        const int b = min(a + TS, C.Nn);
+        int elen = 0;
+        if (a < b) {
+            elem_window(C, a, b, ea_res, elen);
+            stage_elems(B, ea_res, elen, LK, LC);
+        }
+        lds_sync();
     }
-    // initial theta of primal lanes
-    if (L.kind == F_PRI) {
-        // a cold-started slice reads its theta after its flag wait (INIT)
-        if (L.slice > 0 && !I.cold) c.theta = B.in_th[L.slice];
-    } else if (L.kind == GK_PRI) {
-        c.theta = B.in_th[L.slice];
-    }
+    // boundary values of r, w, s for the neighbours' halos: the first H nodes
+    // of the tile go to side 0 (read by rank-1), the last H to side 1 (rank+1)
+    auto publish = [&](int id, int a, int b, double r, double w, double sv, int par) {
+        const int off = id - a;
+        if (off < H && rank > 0) {
+            double *base = B.xch + (((size_t)blockIdx.x * 2 + par) * 2 + 0) * 3 * H;
+            stc(base + off, r);
+            stc(base + H + off, w);
+            stc(base + 2 * H + off, sv);
+        }
+        const int o2 = off - ((b - a) - H);
+        if (o2 >= 0 && rank < g - 1) {
+            double *base = B.xch + (((size_t)blockIdx.x * 2 + par) * 2 + 1) * 3 * H;
+            stc(base + o2, r);
+            stc(base + H + o2, w);
+            stc(base + 2 * H + o2, sv);
+        }
+    };
+    (void)publish;
 
-    auto barrier = [&]() -> bool {
+    // phase timers of this lane (kept by thread 0 of rank 0, written to the trace)
+    unsigned long long t_work = 0, t_bar = 0, t_red = 0, t_flag = 0;
+    long long t_mark = now_ticks();
+    const bool timer = (rank == 0 && threadIdx.x == 0);
+    auto barrier = [&](bool release) -> bool {
         ++nbar;
-        return group_barrier(bar, nbar * (unsigned)g, ctl, C.timeout_ticks);
+        const long long t0 = now_ticks();
+        const bool r = group_barrier(bar, nbar * (unsigned)g, ctl, tmo, release);
+        const long long t1 = now_ticks();
+        if (timer) {
+            t_work += t0 - t_mark;
+            t_bar += t1 - t0;
+            t_mark = t1;
+        }
+        return r;
+    };
+    auto mark_red = [&]() {
+        const long long t = now_ticks();
+        if (timer) {
+            t_red += t - t_mark;
+            t_mark = t;
+        }
+    };
+    auto waitf = [&](int idx) -> bool {
+        const long long t0 = now_ticks();
+        const bool r = wait_flag(B.flags, idx, I.epoch, ctl, tmo);
+        const long long t1 = now_ticks();
+        if (timer) {
+            t_work += t0 - t_mark;
+            t_flag += t1 - t0;
+            t_mark = t1;
+        }
+        return r;
     };
     auto my_part = [&](int parity) { return part + ((size_t)parity * kMaxGroup + rank) * 4; };
     auto all_part = [&](int parity) { return part + (size_t)parity * kMaxGroup * 4; };
 
-    StepInfo st{};
     bool ok = true;
-    while (c.phase != PH_DONE && ok) {
-        if (c.phase == PH_INIT) {
-            const bool first_entry = !c.verifying;
-            st = step_info(C, B, I, L, c.step);
-            if (first_entry && st.wait) {
-                ok = wait_flag(B.flags, st.wait_idx, I.epoch, ctl, C.timeout_ticks);
-                if (!ok) break;
-                if (L.kind == F_PRI && I.cold && L.slice > 0) c.theta = B.Gk_th[L.slice - 1];
-            }
-            if (first_entry && c.step == 0) {
-                // lanes whose first step depends on a producer outside the lane
-                if (L.kind == SWEEP_PRI) {
-                    ok = wait_flag(B.flags, flag_index(FL_F, 0), I.epoch, ctl, C.timeout_ticks);
+    for (int li = 0; li < G.nlanes && ok; ++li) {
+        const int lane_id = G.lane0 + li;
+        const Lane L = B.lanes[lane_id];
+        const bool is_adj = L.kind >= F_ADJ;
+        const bool tracer = (rank == 0 && threadIdx.x == 0);
+        unsigned long long *trec = B.trace + (size_t)lane_id * B.trace_stride;
+        unsigned long long iters_all = 0;
+        const unsigned nbar0 = nbar;
+        if (tracer) {
+            trec[TR_KIND] = L.kind;
+            trec[TR_SLICE] = L.slice;
+            trec[TR_NWG] = g;
+            trec[TR_TILE] = TS;
+            trec[TR_START] = (unsigned long long)now_ticks();
+        }
+
+        Ctl c;
+        c.step = 0;
+        c.nsteps = lane_steps(C, L.kind);
+        c.phase = c.nsteps > 0 ? PH_INIT : PH_DONE;
+        c.iter = 0;
+        c.it_local = 0;
+        c.restarts = 0;
+        c.verifying = false;
+        c.zero_x = false;
+        c.alpha = c.beta = c.gamma = 0.0;
+        c.bnorm = c.relres = 0.0;
+        c.theta = 0.0;
+        c.src_scale = 0.0;
+        if (is_adj) {
+            const double Th = *B.Theta;
+            c.src_scale = pow(Th, 1.0 - C.p) / (double)C.Ne;
+            if (!(Th > 0.0) || !isfinite(Th)) set_status(ctl, -5);
+        }
+        if (L.kind == F_PRI) {
+            // a cold-started slice reads its theta after its flag wait (INIT)
+            if (L.slice > 0 && !I.cold) c.theta = B.in_th[L.slice];
+        } else if (L.kind == GK_PRI) {
+            c.theta = B.in_th[L.slice];
+        }
+
+        StepInfo st{};
+        while (c.phase != PH_DONE && ok) {
+            if (c.phase == PH_INIT) {
+                const bool first_entry = !c.verifying;
+                st = step_info(C, B, I, L, c.step, TP);
+                if (first_entry && st.wait) {
+                    ok = waitf(st.wait_idx);
                     if (!ok) break;
-                    c.theta = B.F_th[0];
-                } else if (L.kind == SWEEP_ADJ) {
-                    ok = wait_flag(B.flags, flag_index(FL_F, C.Ntau), I.epoch, ctl,
-                                   C.timeout_ticks);
+                    if (L.kind == F_PRI && I.cold && L.slice > 0) c.theta = B.Gk_th[L.slice - 1];
+                }
+                if (first_entry && c.step == 0) {
+                    if (L.kind == SWEEP_PRI) {
+                        ok = waitf(flag_index(FL_F, 0));
+                        if (!ok) break;
+                        c.theta = B.F_th[0];
+                    } else if (L.kind == SWEEP_ADJ) {
+                        ok = waitf(flag_index(FL_F, C.Ntau));
+                        if (!ok) break;
+                    }
+                }
+                if (first_entry && (L.kind == SWEEP_PRI || L.kind == SWEEP_ADJ)) {
+                    // G(u^k_n) must exist before it serves as the initial guess
+                    if (I.cold) {
+                        ok = waitf(flag_index(FL_COLD, st.n));
+                    } else if (I.gk_lanes) {
+                        ok = waitf(flag_index(FL_GK, st.n));
+                    }
                     if (!ok) break;
                 }
-            }
-            if (first_entry && (L.kind == SWEEP_PRI || L.kind == SWEEP_ADJ)) {
-                // G(u^k_n) must exist before it serves as initial guess
-                if (I.cold) {
-                    ok = wait_flag(B.flags, flag_index(FL_COLD, st.n), I.epoch, ctl,
-                                   C.timeout_ticks);
-                } else if (I.gk_lanes) {
-                    ok = wait_flag(B.flags, flag_index(FL_GK, st.n), I.epoch, ctl,
-                                   C.timeout_ticks);
+                const double ms = st.fine ? C.inv_dt : C.inv_dtau;
+                const bool ext = first_entry && st.extrap;
+                const bool x0copy = first_entry && (st.x0_src != nullptr || ext);
+                const double *xs = (first_entry && st.x0_src != nullptr) ? st.x0_src : X;
+                const double *ts = st.tp_src;
+                double loc[2] = {0.0, 0.0};  // ||b||^2, ||r0||^2
+                for (int t = rank; t < ntiles; t += g) {
+                    const int a = t * TS;
+                    const int b = min(a + TS, C.Nn);
+                    const int lo = a - H;
+                    const int len = (b - a) + 2 * H;
+                    int ea, elen;
+                    elem_window(C, a, b, ea, elen);
+                    lds_sync();
+                    stage_elems(B, ea, elen, LK, LC);
+                    for (int q0 = threadIdx.x; q0 < len; q0 += kThreads * kU) {
+                        double va[kU], vb[kU], vq[kU];
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int q = q0 + u * kThreads;
+                            const int id = lo + q;
+                            const bool in = q < len && id >= 0 && id < C.Nn;
+                            va[u] = in ? ldc(xs + id) : 0.0;
+                            vb[u] = in ? ldc(ts + id) : 0.0;
+                            vq[u] = (in && ext) ? ldc(TQ + id) : 0.0;
+                        }
+                        if (ext) {
+#pragma unroll
+                            for (int u = 0; u < kU; ++u) va[u] = 2.0 * va[u] - vq[u];
+                        }
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int q = q0 + u * kThreads;
+                            const int id = lo + q;
+                            if (q < len) {
+                                const bool d = id >= 0 && id < C.Nn && B.mask[id];
+                                LA[q] = d ? 0.0 : va[u];
+                                LB[q] = d ? 0.0 : vb[u];
+                            }
+                        }
+                    }
+                    lds_sync();
+                    for (int id = a + threadIdx.x; id < b; id += kThreads) {
+                        const int li2 = id - lo;
+                        const int j = id / C.W, i = id - j * C.W;
+                        double bval = 0.0, r0 = 0.0;
+                        const double x0 = LA[li2];
+                        if (!B.mask[id]) {
+                            const Coef am = node_coef_l(C, LK, LC, ea, i, j, ms, 0.0);
+                            const Coef ak = node_coef_l(C, LK, LC, ea, i, j, 0.0, 1.0);
+                            double src;
+                            if (!st.adjoint) {
+                                const int nex = (i > 0) + (i < C.nx), ney = (j > 0) + (j < C.ny);
+                                src = B.qt[st.j] * C.quarter_area * (double)(nex * ney);
+                            } else {
+                                const double T = B.S[(size_t)(st.j - 1) * C.Nn + id];
+                                src = c.src_scale * ipow(T, C.p - 1);
+                            }
+                            bval = apply(am, LB, li2, C.W) + src;
+                            const double ax = apply(am, LA, li2, C.W) + apply(ak, LA, li2, C.W);
+                            r0 = bval - ax;
+                        }
+                        if (x0copy) stc(X + id, x0);
+                        stc(Rb[0] + id, r0);
+                        loc[0] += bval * bval;
+                        loc[1] += r0 * r0;
+                        // first step of a lane: zero sensitivity sums, publish copies
+                        if (first_entry && c.step == 0) {
+                            if (L.kind == F_ADJ) {
+                                if (i < C.nx && j < C.ny)
+                                    B.acc[(size_t)(L.slice - 1) * C.Ne + j * C.nx + i] = 0.0;
+                            } else if (L.kind == SWEEP_ADJ) {
+                                if (i < C.nx && j < C.ny) B.accG[j * C.nx + i] = 0.0;
+                                B.out_L[(size_t)C.Ntau * C.Nn + id] = 0.0;
+                                B.out_L[(size_t)(C.Ntau - 1) * C.Nn + id] = LB[li2];
+                            } else if (L.kind == SWEEP_PRI) {
+                                B.out_T[(size_t)C.Nn + id] = LB[li2];
+                            }
+                        }
+                    }
                 }
+                block_sum<2>(loc, red);
+                const int par = nbar & 1;
+                if (threadIdx.x == 0) {
+                    stc(my_part(par) + 0, loc[0]);
+                    stc(my_part(par) + 1, loc[1]);
+                }
+                ok = barrier(false);
                 if (!ok) break;
-            }
-            const double ms = st.fine ? C.inv_dt : C.inv_dtau;
-            const bool x0copy = first_entry && st.x0_src != nullptr;
-            const double *xs = x0copy ? st.x0_src : X;
-            double loc[2] = {0.0, 0.0};  // ||b||^2, ||r0||^2
-            for (int t = rank; t < ntiles; t += g) {
-                const int a = t * TS;
-                const int b = min(a + TS, C.Nn);
-                const int lo = a - H;
-                const int len = (b - a) + 2 * H;
-                __syncthreads();
-                for (int q = threadIdx.x; q < len; q += kThreads) {
-                    const int id = lo + q;
-                    const bool in = id >= 0 && id < C.Nn;
-                    const bool d = in && B.mask[id];
-                    LA[q] = (in && !d) ? xs[id] : 0.0;
-                    LB[q] = (in && !d) ? st.tp_src[id] : 0.0;
+                double tot[2];
+                group_sum<2>(all_part(par), g, tot, red);
+                mark_red();
+                c.bnorm = sqrt(tot[0]);
+                const double rn = sqrt(tot[1]);
+                if (rank == 0 && threadIdx.x == 0 && c.step == 0 && first_entry) {
+                    if (L.kind == SWEEP_PRI) B.out_th[1] = B.F_th[0];
                 }
-                __syncthreads();
-                for (int id = a + threadIdx.x; id < b; id += kThreads) {
-                    const int li = id - lo;
-                    const int j = id / C.W, i = id - j * C.W;
-                    double bval = 0.0, r0 = 0.0;
-                    const double x0 = LA[li];
-                    if (!B.mask[id]) {
-                        const Coef am = node_coef(C, B.kq, B.cm, i, j, ms, 0.0);
-                        const Coef ak = node_coef(C, B.kq, B.cm, i, j, 0.0, 1.0);
-                        double src;
-                        if (!st.adjoint) {
-                            const int nex = (i > 0) + (i < C.nx), ney = (j > 0) + (j < C.ny);
-                            src = B.qt[st.j] * C.quarter_area * (double)(nex * ney);
-                        } else {
-                            const double T = B.S[(size_t)(st.j - 1) * C.Nn + id];
-                            src = c.src_scale * ipow(T, C.p - 1);
-                        }
-                        bval = apply(am, LB, li, C.W) + src;
-                        const double ax = apply(am, LA, li, C.W) + apply(ak, LA, li, C.W);
-                        r0 = bval - ax;
-                    }
-                    if (x0copy) X[id] = x0;
-                    Rb[0][id] = r0;
-                    loc[0] += bval * bval;
-                    loc[1] += r0 * r0;
-                    // first step of a lane: zero sensitivity sums, publish copies
-                    if (first_entry && c.step == 0) {
-                        if (L.kind == F_ADJ) {
-                            const int j2 = id / C.W, i2 = id - j2 * C.W;
-                            if (i2 < C.nx && j2 < C.ny)
-                                B.acc[(size_t)(L.slice - 1) * C.Ne + j2 * C.nx + i2] = 0.0;
-                        } else if (L.kind == SWEEP_ADJ) {
-                            const int j2 = id / C.W, i2 = id - j2 * C.W;
-                            if (i2 < C.nx && j2 < C.ny) B.accG[j2 * C.nx + i2] = 0.0;
-                            B.out_L[(size_t)C.Ntau * C.Nn + id] = 0.0;
-                            B.out_L[(size_t)(C.Ntau - 1) * C.Nn + id] = LB[li];
-                        } else if (L.kind == SWEEP_PRI) {
-                            B.out_T[(size_t)C.Nn + id] = LB[li];
-                        }
-                    }
+                if (first_entry) {
+                    c.iter = 0;
+                    c.restarts = 0;
+                    c.zero_x = false;
                 }
-            }
-            block_sum<2>(loc, red);
-            const int par = nbar & 1;
-            if (threadIdx.x == 0) {
-                my_part(par)[0] = loc[0];
-                my_part(par)[1] = loc[1];
-            }
-            ok = barrier();
-            if (!ok) break;
-            double tot[2];
-            group_sum<2>(all_part(par), g, tot, red);
-            c.bnorm = sqrt(tot[0]);
-            const double rn = sqrt(tot[1]);
-            if (rank == 0 && threadIdx.x == 0 && c.step == 0 && first_entry) {
-                if (L.kind == SWEEP_PRI) B.out_th[1] = B.F_th[0];
-            }
-            if (first_entry) {
-                c.iter = 0;
-                c.restarts = 0;
-                c.zero_x = false;
-            }
-            c.it_local = 0;
-            if (c.bnorm == 0.0) {
-                c.zero_x = true;
-                c.relres = 0.0;
-                c.phase = PH_POST;
-            } else if (rn <= C.rtol * c.bnorm) {
-                c.relres = rn / c.bnorm;
-                c.phase = PH_POST;
-            } else {
-                c.phase = PH_FIRST;
-            }
-            c.verifying = false;
-        } else if (c.phase == PH_FIRST) {
-            // w0 = A z0, z0 = D^{-1} r0; gamma0 = (r0, z0), delta0 = (z0, w0)
-            const double ms = st.fine ? C.inv_dt : C.inv_dtau;
-            const double *dinv = st.fine ? B.dinv_f : B.dinv_c;
-            double loc[2] = {0.0, 0.0};
-            for (int t = rank; t < ntiles; t += g) {
-                const int a = t * TS;
-                const int b = min(a + TS, C.Nn);
-                const int lo = a - H;
-                const int len = (b - a) + 2 * H;
-                __syncthreads();
-                for (int q = threadIdx.x; q < len; q += kThreads) {
-                    const int id = lo + q;
-                    LA[q] = (id >= 0 && id < C.Nn) ? dinv[id] * Rb[0][id] : 0.0;
-                }
-                __syncthreads();
-                for (int id = a + threadIdx.x; id < b; id += kThreads) {
-                    const int li = id - lo;
-                    double w = 0.0;
-                    if (!B.mask[id]) {
-                        const int j = id / C.W, i = id - j * C.W;
-                        const Coef aa = node_coef(C, B.kq, B.cm, i, j, ms, 1.0);
-                        w = apply(aa, LA, li, C.W);
-                    }
-                    Wb[0][id] = w;
-                    const double z = LA[li];
-                    loc[0] += Rb[0][id] * z;
-                    loc[1] += z * w;
-                }
-            }
-            block_sum<2>(loc, red);
-            const int par = nbar & 1;
-            if (threadIdx.x == 0) {
-                my_part(par)[0] = loc[0];
-                my_part(par)[1] = loc[1];
-            }
-            ok = barrier();
-            if (!ok) break;
-            double tot[2];
-            group_sum<2>(all_part(par), g, tot, red);
-            c.gamma = tot[0];
-            c.alpha = tot[0] / tot[1];
-            c.beta = 0.0;
-            c.phase = PH_ITER;
-        } else if (c.phase == PH_ITER) {
-            const double ms = st.fine ? C.inv_dt : C.inv_dtau;
-            const double *dinv = st.fine ? B.dinv_f : B.dinv_c;
-            const int i0 = c.it_local;         // iteration since the last (re)start
-            const int cur = i0 & 1, nxt = cur ^ 1;
-            const bool first = (i0 == 0);
-            const double al = c.alpha, be = c.beta;
-            double loc[3] = {0.0, 0.0, 0.0};
-            for (int t = rank; t < ntiles; t += g) {
-                const int a = t * TS;
-                const int b = min(a + TS, C.Nn);
-                const int lo = a - H;
-                const int len = (b - a) + 2 * H;
-                __syncthreads();
-                for (int q = threadIdx.x; q < len; q += kThreads) {
-                    const int id = lo + q;
-                    double z = 0.0;
-                    if (id >= 0 && id < C.Nn) {
-                        const double sv = first ? Wb[cur][id] : Wb[cur][id] + be * Sb[cur][id];
-                        const double rn = Rb[cur][id] - al * sv;
-                        z = dinv[id] * rn;
-                        if (id >= a && id < b) {
-                            const double zi = dinv[id] * Rb[cur][id];
-                            const double pn = first ? zi : zi + be * P[id];
-                            P[id] = pn;
-                            Sb[nxt][id] = sv;
-                            X[id] += al * pn;
-                            Rb[nxt][id] = rn;
-                        }
-                    }
-                    LA[q] = z;
-                }
-                __syncthreads();
-                for (int id = a + threadIdx.x; id < b; id += kThreads) {
-                    const int li = id - lo;
-                    double w = 0.0;
-                    if (!B.mask[id]) {
-                        const int j = id / C.W, i = id - j * C.W;
-                        const Coef aa = node_coef(C, B.kq, B.cm, i, j, ms, 1.0);
-                        w = apply(aa, LA, li, C.W);
-                    }
-                    Wb[nxt][id] = w;
-                    const double z = LA[li];
-                    const double rn = Rb[nxt][id];
-                    loc[0] += rn * z;
-                    loc[1] += z * w;
-                    loc[2] += rn * rn;
-                }
-            }
-            block_sum<3>(loc, red);
-            const int par = nbar & 1;
-            if (threadIdx.x == 0) {
-                my_part(par)[0] = loc[0];
-                my_part(par)[1] = loc[1];
-                my_part(par)[2] = loc[2];
-            }
-            ok = barrier();
-            if (!ok) break;
-            double tot[3];
-            group_sum<3>(all_part(par), g, tot, red);
-            c.it_local = i0 + 1;
-            c.iter += 1;
-            const double rn = sqrt(tot[2]);
-            if (rn <= C.rtol * c.bnorm || c.iter >= C.max_iter) {
-                c.relres = rn / c.bnorm;
-                if (C.verify && rn <= C.rtol * c.bnorm && c.restarts < 3) {
-                    // true-residual check: recompute r = b - A x and restart if needed
-                    c.verifying = true;
-                    c.restarts += 1;
-                    c.phase = PH_INIT;
-                } else {
+                c.it_local = 0;
+                if (c.bnorm == 0.0) {
+                    c.zero_x = true;
+                    c.relres = 0.0;
                     c.phase = PH_POST;
+                } else if (rn <= C.rtol * c.bnorm) {
+                    c.relres = rn / c.bnorm;
+                    c.phase = PH_POST;
+                } else {
+                    c.phase = PH_FIRST;
                 }
-                if (rn > C.rtol * c.bnorm && rank == 0 && threadIdx.x == 0) set_status(ctl, -4);
-            } else {
-                const double gnew = tot[0];
-                const double bnew = gnew / c.gamma;
-                const double anew = gnew / (tot[1] - bnew * gnew / al);
-                c.beta = bnew;
-                c.alpha = anew;
-                c.gamma = gnew;
-            }
-        } else {  // PH_POST
-            // lane-specific writes of the converged solution x
-            const bool last = (c.step == c.nsteps - 1);
-            if (L.kind == SWEEP_PRI) {
-                const int n = st.n;
-                ok = wait_flag(B.flags, flag_index(FL_F, n), I.epoch, ctl, C.timeout_ticks);
-                if (!ok) break;
-            } else if (L.kind == SWEEP_ADJ) {
-                ok = wait_flag(B.flags, flag_index(FL_F, st.n), I.epoch, ctl, C.timeout_ticks);
-                if (!ok) break;
-            }
-            double loc[1] = {0.0};
-            const bool zx = c.zero_x;
-            for (int t = rank; t < ntiles; t += g) {
-                const int a = t * TS;
-                const int b = min(a + TS, C.Nn);
-                for (int id = a + threadIdx.x; id < b; id += kThreads) {
-                    const double x = zx ? 0.0 : X[id];
-                    switch (L.kind) {
-                        case F_PRI: {
-                            B.S[(size_t)(st.j - 1) * C.Nn + id] = x;
-                            TP[id] = x;
-                            loc[0] += ipow(x, C.p);
-                            break;
+                c.verifying = false;
+            } else if (c.phase == PH_FIRST) {
+                // w0 = A z0, z0 = D^{-1} r0; gamma0 = (r0, z0), delta0 = (z0, w0)
+                const double ms = st.fine ? C.inv_dt : C.inv_dtau;
+                const double *dinv = st.fine ? B.dinv_f : B.dinv_c;
+                double loc[2] = {0.0, 0.0};
+                if constexpr (NPT > 0) {
+                // resident: one tile per workgroup; r0, w0, x, dinv stay in registers
+                {
+                    const int a = min(rank * TS, C.Nn);
+                    const int b = min(a + TS, C.Nn);
+                    const int lo = a - H;
+                    const int len = (b - a) + 2 * H;
+                    lds_sync();
+                    for (int q0 = threadIdx.x; q0 < len; q0 += kThreads * kU) {
+                        double rv[kU], dv[kU];
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int q = q0 + u * kThreads;
+                            const int id = lo + q;
+                            const bool in = q < len && id >= 0 && id < C.Nn;
+                            rv[u] = in ? ldc(Rb[0] + id) : 0.0;
+                            dv[u] = in ? dinv[id] : 0.0;
                         }
-                        case GK_PRI:
-                        case COLD_PRI: {
-                            B.Gk[(size_t)st.n * C.Nn + id] = x;
-                            TP[id] = x;
-                            loc[0] += ipow(x, C.p);
-                            break;
-                        }
-                        case SWEEP_PRI: {
-                            const int n = st.n;
-                            const size_t srow = (size_t)(C.M * (n + 1) - 1) * C.Nn + id;
-                            const double u = x + B.S[srow] - B.Gk[(size_t)n * C.Nn + id];
-                            B.S[srow] = u;
-                            B.out_T[(size_t)(n + 1) * C.Nn + id] = u;
-                            B.Gn[(size_t)n * C.Nn + id] = x;
-                            TP[id] = u;
-                            loc[0] += ipow(x, C.p);
-                            break;
-                        }
-                        case F_ADJ: {
-                            TP[id] = x;
-                            const int j2 = id / C.W, i2 = id - j2 * C.W;
-                            if (i2 < C.nx && j2 < C.ny) {
-                                const int e = j2 * C.nx + i2;
-                                const double l0 = x;
-                                const double l1 = zx ? 0.0 : X[id + 1];
-                                const double l2 = zx ? 0.0 : X[id + C.W + 1];
-                                const double l3 = zx ? 0.0 : X[id + C.W];
-                                const double *Tr = B.S + (size_t)(st.j - 1) * C.Nn;
-                                const double t0 = Tr[id], t1 = Tr[id + 1], t2 = Tr[id + C.W + 1],
-                                             t3 = Tr[id + C.W];
-                                double term = B.dk[e] * elem_k(C, l0, l1, l2, l3, t0, t1, t2, t3);
-                                if (I.has_dc) {
-                                    double p0 = 0, p1 = 0, p2 = 0, p3 = 0;
-                                    if (st.jprev > 0) {
-                                        const double *Tp = B.S + (size_t)(st.jprev - 1) * C.Nn;
-                                        p0 = Tp[id];
-                                        p1 = Tp[id + 1];
-                                        p2 = Tp[id + C.W + 1];
-                                        p3 = Tp[id + C.W];
-                                    }
-                                    term += B.dc[e] * C.inv_dt *
-                                            elem_c(C, l0, l1, l2, l3, t0 - p0, t1 - p1, t2 - p2,
-                                                   t3 - p3);
-                                }
-                                B.acc[(size_t)(L.slice - 1) * C.Ne + e] += term;
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int q = q0 + u * kThreads;
+                            const int id = lo + q;
+                            if (q < len) {
+                                LA[q] = dv[u] * rv[u];
+                                if (id >= a && id < b) LB[id - a] = rv[u];
                             }
-                            break;
                         }
-                        case GK_ADJ:
-                        case COLD_ADJ: {
-                            B.Gk[(size_t)st.n * C.Nn + id] = x;
-                            TP[id] = x;
-                            break;
-                        }
-                        default: {  // SWEEP_ADJ
-                            const int n = st.n;
-                            const double *FL = lane_vec(B, C, B.fvec[n], V_X);
-                            const double *Gkn = B.Gk + (size_t)n * C.Nn;
-                            const double lam = x + FL[id] - Gkn[id];
-                            B.out_L[(size_t)(n - 1) * C.Nn + id] = lam;
-                            B.Gn[(size_t)n * C.Nn + id] = x;
-                            TP[id] = lam;
-                            const int j2 = id / C.W, i2 = id - j2 * C.W;
-                            if (i2 < C.nx && j2 < C.ny) {
-                                const int e = j2 * C.nx + i2;
-                                auto dl = [&](int k) { return (zx ? 0.0 : X[k]) - Gkn[k]; };
-                                const double l0 = dl(id), l1 = dl(id + 1), l2 = dl(id + C.W + 1),
-                                             l3 = dl(id + C.W);
-                                const double *Tr = B.S + (size_t)(st.j - 1) * C.Nn;
-                                const double t0 = Tr[id], t1 = Tr[id + 1], t2 = Tr[id + C.W + 1],
-                                             t3 = Tr[id + C.W];
-                                double term = B.dk[e] * elem_k(C, l0, l1, l2, l3, t0, t1, t2, t3);
-                                if (I.has_dc) {
-                                    double p0 = 0, p1 = 0, p2 = 0, p3 = 0;
-                                    if (st.jprev > 0) {
-                                        const double *Tp = B.S + (size_t)(st.jprev - 1) * C.Nn;
-                                        p0 = Tp[id];
-                                        p1 = Tp[id + 1];
-                                        p2 = Tp[id + C.W + 1];
-                                        p3 = Tp[id + C.W];
-                                    }
-                                    term += B.dc[e] * C.inv_dtau *
-                                            elem_c(C, l0, l1, l2, l3, t0 - p0, t1 - p1, t2 - p2,
-                                                   t3 - p3);
-                                }
-                                B.accG[e] += term;
+                    }
+                    lds_sync();
+                    const int par = nbar & 1;
+                    int tid = threadIdx.x;
+                    asm volatile("" : "+v"(tid));  // per-round index math (not hoisted)
+#pragma unroll
+                    for (int k = 0; k < NPT; ++k) {
+                        const int id = a + tid + k * kThreads;
+                        rp[k] = rs[k] = 0.0;
+                        if (id < b) {
+                            const int li2 = id - lo;
+                            double w = 0.0;
+                            if (!B.mask[id]) {
+                                const int j = id / C.W, i = id - j * C.W;
+                                const Coef aa = node_coef_l(C, LK, LC, ea_res, i, j, ms, 1.0);
+                                w = apply(aa, LA, li2, C.W);
                             }
-                            break;
+                            rr[k] = LB[id - a];
+                            LD[id - a] = dinv[id];
+                            rw[k] = w;
+                            const double z = LA[li2];
+                            loc[0] += rr[k] * z;
+                            loc[1] += z * w;
+                            publish(id, a, b, rr[k], rw[k], 0.0, par);
+                        } else {
+                            rr[k] = rw[k] = 0.0;
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+                } else {
+                for (int t = rank; t < ntiles; t += g) {
+                    const int a = t * TS;
+                    const int b = min(a + TS, C.Nn);
+                    const int lo = a - H;
+                    const int len = (b - a) + 2 * H;
+                    int ea, elen;
+                    elem_window(C, a, b, ea, elen);
+                    lds_sync();
+                    stage_elems(B, ea, elen, LK, LC);
+                    for (int q0 = threadIdx.x; q0 < len; q0 += kThreads * kU) {
+                        double rv[kU], dv[kU];
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int q = q0 + u * kThreads;
+                            const int id = lo + q;
+                            const bool in = q < len && id >= 0 && id < C.Nn;
+                            rv[u] = in ? ldc(Rb[0] + id) : 0.0;
+                            dv[u] = in ? dinv[id] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int q = q0 + u * kThreads;
+                            const int id = lo + q;
+                            if (q < len) {
+                                LA[q] = dv[u] * rv[u];
+                                if (id >= a && id < b) LB[id - a] = rv[u];
+                            }
+                        }
+                    }
+                    lds_sync();
+                    for (int id = a + threadIdx.x; id < b; id += kThreads) {
+                        const int li2 = id - lo;
+                        double w = 0.0;
+                        const double z = LA[li2];
+                        if (!B.mask[id]) {
+                            const int j = id / C.W, i = id - j * C.W;
+                            const Coef aa = node_coef_l(C, LK, LC, ea, i, j, ms, 1.0);
+                            w = apply(aa, LA, li2, C.W);
+                        }
+                        stc(Wb[0] + id, w);
+                        loc[0] += LB[id - a] * z;
+                        loc[1] += z * w;
+                    }
+                }
+                }
+                block_sum<2>(loc, red);
+                const int par = nbar & 1;
+                if (threadIdx.x == 0) {
+                    stc(my_part(par) + 0, loc[0]);
+                    stc(my_part(par) + 1, loc[1]);
+                }
+                ok = barrier(false);
+                if (!ok) break;
+                double tot[2];
+                group_sum<2>(all_part(par), g, tot, red);
+                mark_red();
+                c.gamma = tot[0];
+                c.alpha = tot[0] / tot[1];
+                c.beta = 0.0;
+                c.phase = PH_ITER;
+            } else if (c.phase == PH_ITER) {
+                const double ms = st.fine ? C.inv_dt : C.inv_dtau;
+                const double *dinv = st.fine ? B.dinv_f : B.dinv_c;
+                const int i0 = c.it_local;  // iteration since the last (re)start
+                const bool first = (i0 == 0);
+                const double al = c.alpha, be = c.beta;
+                double loc[3] = {0.0, 0.0, 0.0};
+                if constexpr (NPT > 0) {
+                // resident: halo of z_{i+1} rebuilt from the neighbours' published
+                // r_i, w_i, s_{i-1}; own values updated in registers
+                {
+                    const int a = min(rank * TS, C.Nn);
+                    const int b = min(a + TS, C.Nn);
+                    const int lo = a - H;
+                    const int ppar = (nbar - 1) & 1;  // parity of the previous round
+                    int tid = threadIdx.x;
+                    asm volatile("" : "+v"(tid));  // per-round index math (not hoisted)
+                    double xo[NR];
+#pragma unroll
+                    for (int k = 0; k < NPT; ++k) {
+                        const int id = a + tid + k * kThreads;
+                        xo[k] = id < b ? ldc(X + id) : 0.0;
+                    }
+                    lds_sync();
+                    for (int q = threadIdx.x; q < 2 * H; q += kThreads) {
+                        const bool left = q < H;
+                        const int id = left ? a - H + q : b + (q - H);
+                        double z = 0.0;
+                        if (id >= 0 && id < C.Nn) {
+                            const int nb = left ? blockIdx.x - 1 : blockIdx.x + 1;
+                            const int k = left ? q : q - H;
+                            const double *base =
+                                B.xch + (((size_t)nb * 2 + ppar) * 2 + (left ? 1 : 0)) * 3 * H;
+                            const double rh = ldc(base + k);
+                            const double wh = ldc(base + H + k);
+                            const double sh = first ? 0.0 : ldc(base + 2 * H + k);
+                            const double sv = first ? wh : wh + be * sh;
+                            z = dinv[id] * (rh - al * sv);
+                        }
+                        LA[left ? q : (b - lo) + (q - H)] = z;
+                    }
+#pragma unroll
+                    for (int k = 0; k < NPT; ++k) {
+                        const int id = a + tid + k * kThreads;
+                        if (id < b) {
+                            const double dk = LD[id - a];
+                            const double zi = dk * rr[k];
+                            const double pn = first ? zi : zi + be * rp[k];
+                            const double sn = first ? rw[k] : rw[k] + be * rs[k];
+                            stc(X + id, xo[k] + al * pn);
+                            rr[k] -= al * sn;
+                            rp[k] = pn;
+                            rs[k] = sn;
+                            LA[id - lo] = dk * rr[k];
+                        }
+                    }
+                    lds_sync();
+                    const int par = nbar & 1;
+#pragma unroll
+                    for (int k = 0; k < NPT; ++k) {
+                        const int id = a + tid + k * kThreads;
+                        if (id < b) {
+                            const int li2 = id - lo;
+                            double w = 0.0;
+                            if (!B.mask[id]) {
+                                const int j = id / C.W, i = id - j * C.W;
+                                const Coef aa = node_coef_l(C, LK, LC, ea_res, i, j, ms, 1.0);
+                                w = apply(aa, LA, li2, C.W);
+                            }
+                            rw[k] = w;
+                            const double z = LA[li2];
+                            loc[0] += rr[k] * z;
+                            loc[1] += z * w;
+                            loc[2] += rr[k] * rr[k];
+                            publish(id, a, b, rr[k], rw[k], rs[k], par);
+                        }
+                        // keep the unrolled node iterations from being interleaved
+                        // (register pressure)
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+                } else {
+                const int cur = i0 & 1, nxt = cur ^ 1;
+                double *Rc = Rb[cur], *Rn = Rb[nxt], *Wc = Wb[cur], *Wn = Wb[nxt];
+                double *Sc = Sb[cur], *Sn = Sb[nxt];
+                for (int t = rank; t < ntiles; t += g) {
+                    const int a = t * TS;
+                    const int b = min(a + TS, C.Nn);
+                    const int lo = a - H;
+                    const int len = (b - a) + 2 * H;
+                    int ea, elen;
+                    elem_window(C, a, b, ea, elen);
+                    lds_sync();
+                    stage_elems(B, ea, elen, LK, LC);
+                    for (int q0 = threadIdx.x; q0 < len; q0 += kThreads * kU) {
+                        double rv[kU], wv[kU], sv[kU], dv[kU], pv[kU], xv[kU];
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int q = q0 + u * kThreads;
+                            const int id = lo + q;
+                            const bool in = q < len && id >= 0 && id < C.Nn;
+                            const bool own = in && id >= a && id < b;
+                            rv[u] = in ? ldc(Rc + id) : 0.0;
+                            wv[u] = in ? ldc(Wc + id) : 0.0;
+                            sv[u] = (in && !first) ? ldc(Sc + id) : 0.0;
+                            dv[u] = in ? dinv[id] : 0.0;
+                            pv[u] = (own && !first) ? ldc(P + id) : 0.0;
+                            xv[u] = own ? ldc(X + id) : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int q = q0 + u * kThreads;
+                            const int id = lo + q;
+                            if (q < len) {
+                                const double s_new = first ? wv[u] : wv[u] + be * sv[u];
+                                const double r_new = rv[u] - al * s_new;
+                                LA[q] = dv[u] * r_new;
+                                if (id >= a && id < b) {
+                                    const double zi = dv[u] * rv[u];
+                                    const double pn = first ? zi : zi + be * pv[u];
+                                    stc(P + id, pn);
+                                    stc(Sn + id, s_new);
+                                    stc(X + id, xv[u] + al * pn);
+                                    stc(Rn + id, r_new);
+                                    LB[id - a] = r_new;
+                                }
+                            }
+                        }
+                    }
+                    lds_sync();
+                    for (int id = a + threadIdx.x; id < b; id += kThreads) {
+                        const int li2 = id - lo;
+                        double w = 0.0;
+                        if (!B.mask[id]) {
+                            const int j = id / C.W, i = id - j * C.W;
+                            const Coef aa = node_coef_l(C, LK, LC, ea, i, j, ms, 1.0);
+                            w = apply(aa, LA, li2, C.W);
+                        }
+                        stc(Wn + id, w);
+                        const double z = LA[li2];
+                        const double rn = LB[id - a];
+                        loc[0] += rn * z;
+                        loc[1] += z * w;
+                        loc[2] += rn * rn;
+                    }
+                }
+                }
+                block_sum<3>(loc, red);
+                const int par = nbar & 1;
+                if (threadIdx.x == 0) {
+                    stc(my_part(par) + 0, loc[0]);
+                    stc(my_part(par) + 1, loc[1]);
+                    stc(my_part(par) + 2, loc[2]);
+                }
+                ok = barrier(false);
+                if (!ok) break;
+                double tot[3];
+                group_sum<3>(all_part(par), g, tot, red);
+                mark_red();
+                c.it_local = i0 + 1;
+                c.iter += 1;
+                const double rn = sqrt(tot[2]);
+                if (rn <= C.rtol * c.bnorm || c.iter >= C.max_iter) {
+                    c.relres = rn / c.bnorm;
+                    if (C.verify && rn <= C.rtol * c.bnorm && c.restarts < 3) {
+                        // true-residual check: recompute r = b - A x, restart if needed
+                        c.verifying = true;
+                        c.restarts += 1;
+                        c.phase = PH_INIT;
+                    } else {
+                        c.phase = PH_POST;
+                    }
+                    if (rn > C.rtol * c.bnorm && rank == 0 && threadIdx.x == 0)
+                        set_status(ctl, -4);
+                } else {
+                    const double gnew = tot[0];
+                    const double bnew = gnew / c.gamma;
+                    const double anew = gnew / (tot[1] - bnew * gnew / al);
+                    c.beta = bnew;
+                    c.alpha = anew;
+                    c.gamma = gnew;
+                }
+            } else {  // PH_POST: lane-specific use of the converged solution x
+                const bool last = (c.step == c.nsteps - 1);
+                if (L.kind == SWEEP_PRI || L.kind == SWEEP_ADJ) {
+                    ok = waitf(flag_index(FL_F, st.n));
+                    if (!ok) break;
+                }
+                double loc[1] = {0.0};
+                const bool zx = c.zero_x;
+                for (int t = rank; t < ntiles; t += g) {
+                    const int a = t * TS;
+                    const int b = min(a + TS, C.Nn);
+                    for (int id = a + threadIdx.x; id < b; id += kThreads) {
+                        const double x = zx ? 0.0 : ldc(X + id);
+                        switch (L.kind) {
+                            case F_PRI: {
+                                B.S[(size_t)(st.j - 1) * C.Nn + id] = x;
+                                if (C.extrap) stc(TQ + id, ldc(TP + id));
+                                stc(TP + id, x);
+                                loc[0] += ipow(x, C.p);
+                                break;
+                            }
+                            case GK_PRI:
+                            case COLD_PRI: {
+                                B.Gk[(size_t)st.n * C.Nn + id] = x;
+                                stc(TP + id, x);
+                                loc[0] += ipow(x, C.p);
+                                break;
+                            }
+                            case SWEEP_PRI: {
+                                const int n = st.n;
+                                const size_t srow = (size_t)(C.M * (n + 1) - 1) * C.Nn + id;
+                                const double u = x + B.S[srow] - B.Gk[(size_t)n * C.Nn + id];
+                                B.S[srow] = u;
+                                B.out_T[(size_t)(n + 1) * C.Nn + id] = u;
+                                B.Gn[(size_t)n * C.Nn + id] = x;
+                                stc(TP + id, u);
+                                loc[0] += ipow(x, C.p);
+                                break;
+                            }
+                            case F_ADJ: {
+                                if (C.extrap) stc(TQ + id, ldc(TP + id));
+                                stc(TP + id, x);
+                                if (last) B.FL[(size_t)L.slice * C.Nn + id] = x;
+                                const int j2 = id / C.W, i2 = id - j2 * C.W;
+                                if (i2 < C.nx && j2 < C.ny) {
+                                    const int e = j2 * C.nx + i2;
+                                    const double l1 = zx ? 0.0 : ldc(X + id + 1);
+                                    const double l2 = zx ? 0.0 : ldc(X + id + C.W + 1);
+                                    const double l3 = zx ? 0.0 : ldc(X + id + C.W);
+                                    const double *Tr = B.S + (size_t)(st.j - 1) * C.Nn;
+                                    const double *Tp =
+                                        st.jprev > 0 ? B.S + (size_t)(st.jprev - 1) * C.Nn : nullptr;
+                                    B.acc[(size_t)(L.slice - 1) * C.Ne + e] +=
+                                        sens_term(C, B, I, id, e, x, l1, l2, l3, Tr, Tp, C.inv_dt);
+                                }
+                                break;
+                            }
+                            case GK_ADJ:
+                            case COLD_ADJ: {
+                                B.Gk[(size_t)st.n * C.Nn + id] = x;
+                                stc(TP + id, x);
+                                break;
+                            }
+                            default: {  // SWEEP_ADJ
+                                const int n = st.n;
+                                const double *FLn = B.FL + (size_t)n * C.Nn;
+                                const double *Gkn = B.Gk + (size_t)n * C.Nn;
+                                const double lam = x + FLn[id] - Gkn[id];
+                                B.out_L[(size_t)(n - 1) * C.Nn + id] = lam;
+                                B.Gn[(size_t)n * C.Nn + id] = x;
+                                stc(TP + id, lam);
+                                const int j2 = id / C.W, i2 = id - j2 * C.W;
+                                if (i2 < C.nx && j2 < C.ny) {
+                                    const int e = j2 * C.nx + i2;
+                                    auto dl = [&](int k) { return (zx ? 0.0 : ldc(X + k)) - Gkn[k]; };
+                                    const double *Tr = B.S + (size_t)(st.j - 1) * C.Nn;
+                                    const double *Tp =
+                                        st.jprev > 0 ? B.S + (size_t)(st.jprev - 1) * C.Nn : nullptr;
+                                    B.accG[e] += sens_term(C, B, I, id, e, dl(id), dl(id + 1),
+                                                           dl(id + C.W + 1), dl(id + C.W), Tr, Tp,
+                                                           C.inv_dtau);
+                                }
+                                break;
+                            }
                         }
                     }
                 }
-            }
-            block_sum<1>(loc, red);
-            const int par = nbar & 1;
-            if (threadIdx.x == 0) my_part(par)[0] = loc[0];
-            ok = barrier();
-            if (!ok) break;
-            double tot[1];
-            group_sum<1>(all_part(par), g, tot, red);
-            const bool leader = (rank == 0 && threadIdx.x == 0);
-            // theta updates (Alg. 1, step 2) and lane outputs
-            if (!is_adj) {
-                const double inv = st.fine ? C.inv_NtNe : C.inv_NtauNe;
-                const double thG = pow(ipow(c.theta, C.p) + tot[0] * inv, C.inv_p);
-                if (L.kind == SWEEP_PRI) {
-                    const int n = st.n;
-                    const double thu = thG + B.F_th[n] - B.Gk_th[n];
-                    if (leader) {
-                        B.out_th[n + 1] = thu;
-                        B.Gn_th[n] = thG;
+                block_sum<1>(loc, red);
+                const int par = nbar & 1;
+                if (threadIdx.x == 0) stc(my_part(par), loc[0]);
+                // release: plain stores of this step (S, Gk, FL, outputs) become visible
+                ok = barrier(true);
+                if (!ok) break;
+                double tot[1];
+                group_sum<1>(all_part(par), g, tot, red);
+                mark_red();
+                const bool leader = (rank == 0 && threadIdx.x == 0);
+                // theta updates (Alg. 1, step 2) and lane outputs
+                if (!is_adj) {
+                    const double inv = st.fine ? C.inv_NtNe : C.inv_NtauNe;
+                    const double thG = pow(ipow(c.theta, C.p) + tot[0] * inv, C.inv_p);
+                    if (L.kind == SWEEP_PRI) {
+                        const int n = st.n;
+                        const double thu = thG + B.F_th[n] - B.Gk_th[n];
+                        if (leader) {
+                            B.out_th[n + 1] = thu;
+                            B.Gn_th[n] = thG;
+                        }
+                        c.theta = thu;
+                    } else {
+                        c.theta = thG;
+                        if (leader && (L.kind == GK_PRI || L.kind == COLD_PRI)) B.Gk_th[st.n] = thG;
+                        if (leader && L.kind == F_PRI && last) B.F_th[L.slice] = thG;
                     }
-                    c.theta = thu;
-                } else {
-                    c.theta = thG;
-                    if (leader && (L.kind == GK_PRI || L.kind == COLD_PRI)) B.Gk_th[st.n] = thG;
-                    if (leader && L.kind == F_PRI && last) B.F_th[L.slice] = thG;
                 }
-            }
-            if (leader) {
-                // statistics
-                const int it = c.iter;
-                if (st.fine) {
-                    atomicAdd(&ctl->iters_fine, (unsigned long long)it);
-                    atomicAdd(&ctl->solves_fine, 1ull);
-                } else {
-                    atomicAdd(&ctl->iters_coarse, (unsigned long long)it);
-                    atomicAdd(&ctl->solves_coarse, 1ull);
+                if (leader) {
+                    const int it = c.iter;
+                    if (st.fine) {
+                        atomicAdd(&ctl->iters_fine, (unsigned long long)it);
+                        atomicAdd(&ctl->solves_fine, 1ull);
+                    } else {
+                        atomicAdd(&ctl->iters_coarse, (unsigned long long)it);
+                        atomicAdd(&ctl->solves_coarse, 1ull);
+                    }
+                    atomicMax(&ctl->max_iters, it);
+                    atomicMax(&ctl->max_relres_bits,
+                              (unsigned long long)__double_as_longlong(c.relres));
+                    if (L.kind == GK_PRI || L.kind == GK_ADJ)
+                        set_flag(B.flags, flag_index(FL_GK, st.n), I.epoch);
+                    if (L.kind == COLD_PRI || L.kind == COLD_ADJ)
+                        set_flag(B.flags, flag_index(FL_COLD, st.n), I.epoch);
+                    if ((L.kind == F_PRI || L.kind == F_ADJ) && last)
+                        set_flag(B.flags, flag_index(FL_F, L.slice), I.epoch);
                 }
-                atomicMax(&ctl->max_iters, it);
-                atomicMax(&ctl->max_relres_bits, (unsigned long long)__double_as_longlong(c.relres));
-                // flags
-                if (L.kind == GK_PRI || L.kind == GK_ADJ) set_flag(B.flags, flag_index(FL_GK, st.n), I.epoch);
-                if (L.kind == COLD_PRI || L.kind == COLD_ADJ)
-                    set_flag(B.flags, flag_index(FL_COLD, st.n), I.epoch);
-                if ((L.kind == F_PRI || L.kind == F_ADJ) && last)
-                    set_flag(B.flags, flag_index(FL_F, L.slice), I.epoch);
+                iters_all += c.iter;
+                if (tracer && c.step < B.trace_stride - TR_HDR)
+                    trec[TR_HDR + c.step] = (unsigned long long)now_ticks();
+                c.step += 1;
+                c.phase = (c.step < c.nsteps) ? PH_INIT : PH_DONE;
+                c.iter = 0;
+                c.verifying = false;
             }
-            c.step += 1;
-            c.phase = (c.step < c.nsteps) ? PH_INIT : PH_DONE;
-            c.iter = 0;
-            c.verifying = false;
+        }
+        if (tracer) {
+            trec[TR_ROUNDS] = nbar - nbar0;
+            trec[TR_ITERS] = iters_all;
+            trec[TR_T_WORK] = t_work;
+            trec[TR_T_BAR] = t_bar;
+            trec[TR_T_RED] = t_red;
+            trec[TR_T_FLAG] = t_flag;
+            t_work = t_bar = t_red = t_flag = 0;
         }
     }
     if (!ok && threadIdx.x == 0) {
@@ -937,8 +1319,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
 }
 
 // After the primal engine: u_0 = 0, Theta, and the N_tau = 1 case.
-__global__ void k_finalize_fwd(Consts C, Bufs B, double *Theta_out, double *uT_out,
-                               double *uth_out, int copy_out) {
+__global__ void k_finalize_fwd(Consts C, Bufs B, double *Theta_out) {
     const size_t Nn = C.Nn;
     for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < Nn;
          id += (size_t)gridDim.x * blockDim.x) {
@@ -953,19 +1334,15 @@ __global__ void k_finalize_fwd(Consts C, Bufs B, double *Theta_out, double *uT_o
         if (!(Th > 0.0) || !isfinite(Th)) atomicCAS(&B.ctl->status, 0, -5);
         B.ctl->fwd_done = 1;
     }
-    (void)uT_out;
-    (void)uth_out;
-    (void)copy_out;
 }
 
 // After the adjoint engine: lambda for N_tau = 1.
 __global__ void k_finalize_adj(Consts C, Bufs B) {
     const size_t Nn = C.Nn;
     if (C.Ntau == 1) {
-        const double *FL = B.pool + ((size_t)B.fvec[1] * kVecsPerLane + 0) * Nn;
         for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < Nn;
              id += (size_t)gridDim.x * blockDim.x) {
-            B.out_L[id] = FL[id];
+            B.out_L[id] = B.FL[Nn + id];
             B.out_L[Nn + id] = 0.0;
         }
         for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)C.Ne;

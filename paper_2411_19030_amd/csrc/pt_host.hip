@@ -19,11 +19,12 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t ctl, bar, flags, partials, wg_lane, lanes, fvec;
+    size_t ctl, bar, flags, partials, wg_group, groups, lanes, FL;
     size_t kq, cm, dk, dc, dinv_f, dinv_c, mask, qt, zero;
     size_t Gk, Gn, Gk_th, Gn_th, F_th, Uprev, Uprev_th, Ubuf, Ubuf_th, Lprev, Lbuf;
-    size_t acc, accG, pool;
+    size_t acc, accG, pool, trace, xch;
     size_t total;
+    int trace_stride;
     int max_lanes, max_grid;
 };
 
@@ -60,7 +61,7 @@ Layout layout(const pt_problem *p) {
     const size_t EP = (size_t)(p->nx + 2) * (p->ny + 2);
     const size_t Nt1 = (size_t)p->n_slices + 1;
     L.max_lanes = 2 * p->n_slices + 2;
-    L.max_grid = 4096;
+    L.max_grid = 1024;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -71,9 +72,10 @@ Layout layout(const pt_problem *p) {
     L.bar = take(sizeof(unsigned) * kMaxLanes);
     L.flags = take(sizeof(unsigned) * kMaxFlags);
     L.partials = take(sizeof(double) * (size_t)L.max_lanes * 2 * kMaxGroup * 4);
-    L.wg_lane = take(sizeof(int) * L.max_grid);
+    L.wg_group = take(sizeof(int) * L.max_grid);
+    L.groups = take(sizeof(Group) * kMaxLanes);
     L.lanes = take(sizeof(Lane) * L.max_lanes);
-    L.fvec = take(sizeof(int) * Nt1);
+    L.FL = take(sizeof(double) * Nt1 * Nn);
     L.kq = take(sizeof(double) * EP);
     L.cm = take(sizeof(double) * EP);
     L.dk = take(sizeof(double) * Ne);
@@ -97,6 +99,9 @@ Layout layout(const pt_problem *p) {
     L.acc = take(sizeof(double) * (size_t)p->n_slices * Ne);
     L.accG = take(sizeof(double) * Ne);
     L.pool = take(sizeof(double) * (size_t)L.max_lanes * kVecsPerLane * Nn);
+    L.trace_stride = TR_HDR + std::max(p->n_steps / p->n_slices, p->n_slices);
+    L.trace = take(sizeof(unsigned long long) * (size_t)L.max_lanes * L.trace_stride);
+    L.xch = take(sizeof(double) * (size_t)L.max_grid * 12 * (p->nx + 2));
     L.total = o;
     return L;
 }
@@ -114,7 +119,8 @@ Consts make_consts(const pt_problem *p) {
     C.M = p->n_steps / p->n_slices;
     C.p = p->pnorm;
     C.max_iter = p->max_iter;
-    C.verify = 1;
+    C.verify = getenv("PT_VERIFY") ? atoi(getenv("PT_VERIFY")) : 1;
+    C.extrap = getenv("PT_EXTRAP") ? atoi(getenv("PT_EXTRAP")) : 0;
     C.hx = 1.0 / p->nx;
     C.hy = 1.0 / p->ny;
     const double rx = C.hy / C.hx, ry = C.hx / C.hy;
@@ -151,9 +157,10 @@ Bufs make_bufs(void *ws, const Layout &L) {
     B.bar = at<unsigned>(ws, L.bar);
     B.flags = at<unsigned>(ws, L.flags);
     B.partials = at<double>(ws, L.partials);
-    B.wg_lane = at<int>(ws, L.wg_lane);
+    B.wg_group = at<int>(ws, L.wg_group);
+    B.groups = at<Group>(ws, L.groups);
     B.lanes = at<Lane>(ws, L.lanes);
-    B.fvec = at<int>(ws, L.fvec);
+    B.FL = at<double>(ws, L.FL);
     B.pool = at<double>(ws, L.pool);
     B.kq = at<double>(ws, L.kq);
     B.cm = at<double>(ws, L.cm);
@@ -171,6 +178,9 @@ Bufs make_bufs(void *ws, const Layout &L) {
     B.F_th = at<double>(ws, L.F_th);
     B.acc = at<double>(ws, L.acc);
     B.accG = at<double>(ws, L.accG);
+    B.trace = at<unsigned long long>(ws, L.trace);
+    B.xch = at<double>(ws, L.xch);
+    B.trace_stride = L.trace_stride;
     return B;
 }
 
@@ -184,43 +194,48 @@ int hip_ok(hipError_t e) { return e == hipSuccess ? PT_OK : PT_EHIP; }
 
 int launch_check() { return hip_ok(hipGetLastError()); }
 
-// Plan of one engine launch, built on the host and uploaded through a kernel
-// argument (so no host buffer must outlive the call).
-struct PlanArgs {
-    int n_lanes;
-    int grid;
-    // lanes are described in runs: [first, count, kind, slice0, slice_step, nwg, tile, vec0]
-    int runs;
-    int run[8][8];
+// Plan of one engine launch, built on the host and passed as a kernel
+// argument (so no host buffer must outlive the call). Groups come in runs of
+// identical shape: group r of a run gets the lanes with slices
+// s0 + r*gstride + k*lstride, k = 0..nlanes-1, kept if within [smin, smax].
+struct Run {
+    int kind, ngroups, nwg, tile, s0, gstride, lstride, nlanes, smin, smax;
 };
 
-__global__ void k_build_plan(PlanArgs P, Lane *lanes, int *wg_lane, int *fvec, int ntau) {
-    if (blockIdx.x != 0) return;
-    // lanes
-    for (int r = 0; r < P.runs; ++r) {
-        const int first = P.run[r][0], count = P.run[r][1];
-        for (int q = threadIdx.x; q < count; q += blockDim.x) {
-            Lane L;
-            L.kind = P.run[r][2];
-            L.slice = P.run[r][3] + q * P.run[r][4];
-            L.nwg = P.run[r][5];
-            L.tile = P.run[r][6];
-            L.vec = P.run[r][7] + q;
-            L.wg0 = 0;
-            lanes[first + q] = L;
+struct PlanArgs {
+    int grid;
+    int nruns;
+    Run run[6];
+};
+
+__global__ void k_build_plan(PlanArgs P, Group *groups, Lane *lanes, int *wg_group) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int gidx = 0, lidx = 0, w = 0;
+    for (int r = 0; r < P.nruns; ++r) {
+        const Run R = P.run[r];
+        for (int q = 0; q < R.ngroups; ++q) {
+            Group G;
+            G.wg0 = w;
+            G.nwg = R.nwg;
+            G.tile = R.tile;
+            G.vec = gidx;
+            G.lane0 = lidx;
+            int n = 0;
+            for (int k = 0; k < R.nlanes; ++k) {
+                const int sl = R.s0 + q * R.gstride + k * R.lstride;
+                if (sl < R.smin || sl > R.smax) continue;
+                lanes[lidx + n].kind = R.kind;
+                lanes[lidx + n].slice = sl;
+                ++n;
+            }
+            G.nlanes = n;
+            lidx += n;
+            groups[gidx] = G;
+            for (int k = 0; k < R.nwg; ++k) wg_group[w++] = gidx;
+            ++gidx;
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int w = 0;
-        for (int l = 0; l < P.n_lanes; ++l) {
-            lanes[l].wg0 = w;
-            for (int k = 0; k < lanes[l].nwg; ++k) wg_lane[w++] = l;
-            if (lanes[l].kind == F_PRI || lanes[l].kind == F_ADJ) fvec[lanes[l].slice] = lanes[l].vec;
-        }
-        for (; w < P.grid; ++w) wg_lane[w] = -1;
-        (void)ntau;
-    }
+    for (; w < P.grid; ++w) wg_group[w] = -1;
 }
 
 struct Device {
@@ -236,113 +251,196 @@ int device_info(Device &d) {
     return PT_OK;
 }
 
-// Work weights in CG iterations (coarse solves need several times more
-// iterations than fine ones; sweeps are latency-bound and get a fixed share).
-struct LanePlan {
-    int kind;
-    int count;
-    int slice0, slice_step;
-    double weight;  // per lane
-    int nwg = 1;
-    int tile = 256;
-};
+int env_int(const char *name, int dflt) {
+    const char *e = getenv(name);
+    return e ? atoi(e) : dflt;
+}
+
+double env_double(const char *name, double dflt) {
+    const char *e = getenv(name);
+    return e ? atof(e) : dflt;
+}
+
+// LDS doubles of the engine for tile size ts: two node windows (ts + 2H) and
+// two element windows ((ts-1)/W + 3 rows of nx+2 elements).
+size_t engine_lds_doubles(int ts, int W) {
+    const size_t H = W + 1;
+    return 2 * ((size_t)ts + 2 * H) + 2 * ((size_t)(ts - 1) / W + 3) * (W + 1);
+}
 
 int tile_for(int Nn, int nwg, int H, int lds_cap_doubles) {
     int ts = (Nn + nwg - 1) / nwg;
     ts = (ts + 255) / 256 * 256;
-    const int cap = (lds_cap_doubles / 2 - 2 * H) / 256 * 256;
-    ts = std::min(ts, std::max(cap, 256));
-    ts = std::min(ts, 8192);
+    while (ts > 256 && engine_lds_doubles(ts, H - 1) > (size_t)lds_cap_doubles) ts -= 256;
+    ts = std::min(ts, std::max(256, env_int("PT_TILE_MAX", 4096)));
     ts = std::max(ts, 256);
     return ts;
 }
 
-// Runs one engine launch over the given lane runs.
+// One kind of lane and how its lanes are queued on groups.
+struct LanePlan {
+    int kind;
+    int count;        // lanes
+    int slice0;       // first slice in queue order
+    int dir;          // +1 ascending, -1 descending slices
+    double weight;    // work per lane (relative)
+    bool latency;     // sweep-like: fixed group size
+    int queues = 0;   // groups (0: one lane per group)
+};
+
+// Runs one engine launch.
 int run_engine(const Consts &C, Bufs B, const LaunchInfo &I, std::vector<LanePlan> &plans,
-               void *ws, const Layout &Lay, hipStream_t stream, int sweep_share) {
+               void *ws, const Layout &Lay, hipStream_t stream) {
     Device dev;
     PT_TRY(device_info(dev));
     const int H = C.W + 1;
-    const int lds_cap = std::min(dev.lds_max, 160 * 1024) - 1024;  // bytes for the two windows
+    const int lds_cap = std::min(dev.lds_max, 160 * 1024) - 1024;
     const int lds_cap_d = lds_cap / 8;
-    // co-resident grid: one workgroup per CU (the engine's LDS windows are large)
-    int grid = dev.cus;
-    int n_lanes = 0;
-    for (auto &p : plans) n_lanes += p.count;
-    if (n_lanes > Lay.max_lanes || n_lanes > kMaxLanes) return PT_EINVAL;
-    if (n_lanes > grid) {
-        // more lanes than workgroups: give every lane one workgroup on a wider grid
-        grid = n_lanes;
+    int grid = dev.cus * std::max(1, env_int("PT_WG_PER_CU", 1));
+    const int sweep_wgs = env_int("PT_SWEEP_WGS", 32);
+
+    const int NT = kThreads;
+    const int res_npt_max = std::max(1, std::min(8, env_int("PT_RES_NPT", 8)));
+    const int g_min = (C.Nn + NT * res_npt_max - 1) / (NT * res_npt_max);
+    bool resident = env_int("PT_RESIDENT", 1) != 0 && g_min <= grid / 4 &&
+                    (C.Nn + g_min - 1) / g_min >= H;
+    // a tile must be at least one halo (H nodes) long
+    const int max_wg_per_lane = std::max(1, C.Nn / H);
+
+    std::vector<int> ngroups(plans.size()), per_group(plans.size()), nwg(plans.size()),
+        tile(plans.size());
+    if (resident) {
+        // one tile of <= NT*npt nodes per workgroup; every group holds a whole lane
+        int lat_wgs = 0;
+        double wF = 0.0;
+        int nq = 0;
+        for (size_t k = 0; k < plans.size(); ++k) {
+            auto &p = plans[k];
+            if (p.latency) {
+                nwg[k] = std::max(g_min, std::min(sweep_wgs, grid / 4));
+                nwg[k] = std::max(1, std::min(nwg[k], max_wg_per_lane));
+                ngroups[k] = p.count;
+                lat_wgs += nwg[k] * p.count;
+            } else {
+                nwg[k] = g_min;
+                wF += p.weight * p.count;
+                ++nq;
+            }
+        }
+        const int avail = (grid - lat_wgs) / g_min;  // groups left for batched lanes
+        if (avail < nq) resident = false;
     }
-    // split workgroups: sweeps first, then by weight
-    int fixed = 0;
-    double wsum = 0.0;
-    for (auto &p : plans) {
-        if (p.kind == SWEEP_PRI || p.kind == SWEEP_ADJ || p.kind == COLD_PRI || p.kind == COLD_ADJ) {
-            p.nwg = std::max(1, std::min(sweep_share, grid / 4));
-            fixed += p.nwg * p.count;
-        } else {
-            wsum += p.weight * p.count;
+    if (resident) {
+        int nq = 0;
+        double wF = 0.0;
+        int lat_wgs = 0;
+        for (size_t k = 0; k < plans.size(); ++k) {
+            if (plans[k].latency) lat_wgs += nwg[k] * plans[k].count;
+            else {
+                wF += plans[k].weight * plans[k].count;
+                ++nq;
+            }
+        }
+        const int avail = (grid - lat_wgs) / g_min;
+        int left = avail;
+        for (size_t k = 0; k < plans.size(); ++k) {
+            auto &p = plans[k];
+            if (p.latency) continue;
+            --nq;
+            int q = p.queues > 0 ? p.queues : (int)floor(avail * p.weight * p.count / wF);
+            q = std::max(1, std::min(q, std::min(p.count, left - nq)));
+            ngroups[k] = q;
+            left -= q;
+        }
+        for (size_t k = 0; k < plans.size(); ++k) {
+            per_group[k] = (plans[k].count + ngroups[k] - 1) / ngroups[k];
+            const int ts = (C.Nn + nwg[k] - 1) / nwg[k];
+            nwg[k] = (C.Nn + ts - 1) / ts;  // every workgroup owns a non-empty tile
+            if (ts < H || ts > NT * res_npt_max) return PT_EINVAL;
+            tile[k] = ts;
         }
     }
-    int rest = grid - fixed;
-    int used = fixed;
-    for (auto &p : plans) {
-        if (p.kind == SWEEP_PRI || p.kind == SWEEP_ADJ || p.kind == COLD_PRI || p.kind == COLD_ADJ)
-            continue;
-        int share = (int)floor(rest * p.weight / wsum);
-        p.nwg = std::max(1, share);
-        used += p.nwg * p.count;
+    if (!resident) {
+        int total_groups = 0, fixed = 0;
+        double wsum = 0.0;
+        for (size_t k = 0; k < plans.size(); ++k) {
+            auto &p = plans[k];
+            const int q = (p.queues <= 0 || p.queues > p.count) ? p.count : p.queues;
+            ngroups[k] = q;
+            per_group[k] = (p.count + q - 1) / q;
+            total_groups += q;
+            if (p.latency) fixed += std::max(1, std::min(sweep_wgs, grid / 2)) * q;
+            else wsum += p.weight * per_group[k] * q;
+        }
+        if (total_groups > kMaxLanes) return PT_EINVAL;
+        if (total_groups > grid) grid = total_groups;
+        const int rest = std::max(grid - fixed, 0);
+        for (size_t k = 0; k < plans.size(); ++k) {
+            auto &p = plans[k];
+            if (p.latency) nwg[k] = std::max(1, std::min(sweep_wgs, grid / 2));
+            else nwg[k] = std::max(1, (int)floor(rest * p.weight * per_group[k] / wsum));
+            tile[k] = tile_for(C.Nn, nwg[k], H, lds_cap_d);
+        }
     }
+    int used = 0, max_tile = 256, total_groups = 0;
+    for (size_t k = 0; k < plans.size(); ++k) {
+        if (nwg[k] > kMaxGroup) return PT_EINVAL;
+        used += nwg[k] * ngroups[k];
+        total_groups += ngroups[k];
+        max_tile = std::max(max_tile, tile[k]);
+    }
+    if (total_groups > kMaxLanes) return PT_EINVAL;
     if (used > grid) grid = used;
-    int max_tile = 256;
-    for (auto &p : plans) {
-        p.tile = tile_for(C.Nn, p.nwg, H, lds_cap_d);
-        max_tile = std::max(max_tile, p.tile);
-    }
     if (grid > Lay.max_grid) return PT_EINVAL;
-    const size_t lds_bytes = (size_t)2 * (max_tile + 2 * H) * sizeof(double);
+    int npt = 0;
+    if (resident) {
+        npt = 1;
+        while (npt * NT < max_tile) npt *= 2;
+    }
+    const size_t lds_bytes = engine_lds_doubles(max_tile, C.W) * sizeof(double);
     if (lds_bytes > (size_t)dev.lds_max) return PT_EINVAL;
 
     PlanArgs P{};
     P.grid = grid;
-    P.runs = 0;
-    int first = 0, vec = 0;
-    for (auto &p : plans) {
+    P.nruns = 0;
+    for (size_t k = 0; k < plans.size(); ++k) {
+        const auto &p = plans[k];
         if (p.count == 0) continue;
-        if (P.runs >= 8) return PT_EINVAL;
-        int *r = P.run[P.runs++];
-        r[0] = first;
-        r[1] = p.count;
-        r[2] = p.kind;
-        r[3] = p.slice0;
-        r[4] = p.slice_step;
-        r[5] = p.nwg;
-        r[6] = p.tile;
-        r[7] = vec;
-        first += p.count;
-        vec += p.count;
+        if (P.nruns >= 6) return PT_EINVAL;
+        Run &R = P.run[P.nruns++];
+        R.kind = p.kind;
+        R.ngroups = ngroups[k];
+        R.nwg = nwg[k];
+        R.tile = tile[k];
+        R.s0 = p.slice0;
+        R.gstride = p.dir;                 // neighbouring groups take consecutive slices
+        R.lstride = p.dir * ngroups[k];    // a group's queue advances by the group count
+        R.nlanes = per_group[k];
+        R.smin = std::min(p.slice0, p.slice0 + p.dir * (p.count - 1));
+        R.smax = std::max(p.slice0, p.slice0 + p.dir * (p.count - 1));
     }
-    P.n_lanes = first;
-    hipLaunchKernelGGL(k_build_plan, dim3(1), dim3(256), 0, stream, P, at<Lane>(ws, Lay.lanes),
-                       at<int>(ws, Lay.wg_lane), at<int>(ws, Lay.fvec), C.Ntau);
+    hipLaunchKernelGGL(k_build_plan, dim3(1), dim3(64), 0, stream, P, at<Group>(ws, Lay.groups),
+                       at<Lane>(ws, Lay.lanes), at<int>(ws, Lay.wg_group));
     PT_TRY(launch_check());
     hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream, B.bar, (size_t)kMaxLanes, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream, B.flags, (size_t)kMaxFlags, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream, (unsigned *)B.trace,
+                       (size_t)Lay.max_lanes * Lay.trace_stride * 2, 0u);
     PT_TRY(launch_check());
 
-    for (auto &p : plans)
-        if (p.nwg > kMaxGroup) return PT_EINVAL;
-    PT_TRY(hip_ok(hipFuncSetAttribute((const void *)k_engine,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+    const void *kern = npt == 0   ? (const void *)k_engine<0>
+                       : npt == 1 ? (const void *)k_engine<1>
+                       : npt == 2 ? (const void *)k_engine<2>
+                       : npt == 4 ? (const void *)k_engine<4>
+                                  : (const void *)k_engine<8>;
+    PT_TRY(hip_ok(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds_bytes)));
     int occ = 0;
-    PT_TRY(hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_engine, kThreads,
-                                                                lds_bytes)));
+    PT_TRY(hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, lds_bytes)));
     if ((long long)occ * dev.cus < grid) return PT_EHIP;
     void *args[] = {(void *)&C, (void *)&B, (void *)&I};
-    PT_TRY(hip_ok(hipLaunchCooperativeKernel((const void *)k_engine, dim3(grid), dim3(kThreads),
-                                             args, (unsigned)lds_bytes, stream)));
+    PT_TRY(hip_ok(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kThreads), args,
+                                             (unsigned)lds_bytes, stream)));
     return launch_check();
 }
 
@@ -473,21 +571,13 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
         B.Gn = Gb;
         B.Gn_th = Gb_th;
         std::vector<LanePlan> plans;
-        LanePlan f{F_PRI, Ntau, 0, 1, (double)C.M};
-        plans.push_back(f);
-        if (I.gk_lanes) {
-            LanePlan gk{GK_PRI, Ntau - 1, 1, 1, 4.0};
-            plans.push_back(gk);
-        }
-        if (I.cold) {
-            LanePlan cl{COLD_PRI, 1, 0, 1, 0.0};
-            plans.push_back(cl);
-        }
-        if (Ntau > 1) {
-            LanePlan sw{SWEEP_PRI, 1, 0, 1, 0.0};
-            plans.push_back(sw);
-        }
-        PT_TRY(run_engine(C, B, I, plans, ws, Lay, stream, 32));
+        plans.push_back({F_PRI, Ntau, 0, +1, (double)C.M, false, env_int("PT_FQUEUES", 0)});
+        if (I.gk_lanes)
+            plans.push_back({GK_PRI, Ntau - 1, 1, +1, env_double("PT_GK_WEIGHT", 4.0), false,
+                             env_int("PT_GQUEUES", 0)});
+        if (I.cold) plans.push_back({COLD_PRI, 1, 0, +1, 0.0, true, 0});
+        if (Ntau > 1) plans.push_back({SWEEP_PRI, 1, 0, +1, 0.0, true, 0});
+        PT_TRY(run_engine(C, B, I, plans, ws, Lay, stream));
         if (it + 1 < prob->iterations) {
             hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Uprev, outT, Nt1 * Nn);
             hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(256), 0, stream, Uprev_th, outth, Nt1);
@@ -498,8 +588,7 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
     }
     B.out_T = outT;
     B.out_th = outth;
-    hipLaunchKernelGGL(k_finalize_fwd, dim3(256), dim3(256), 0, stream, C, B, Theta_out, outT,
-                       outth, 0);
+    hipLaunchKernelGGL(k_finalize_fwd, dim3(256), dim3(256), 0, stream, C, B, Theta_out);
     return launch_check();
 }
 
@@ -541,21 +630,14 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
         B.Gk = Ga;
         B.Gn = Gb;
         std::vector<LanePlan> plans;
-        LanePlan f{F_ADJ, Ntau, 1, 1, (double)C.M};
-        plans.push_back(f);
-        if (I.gk_lanes) {
-            LanePlan gk{GK_ADJ, Ntau - 1, 1, 1, 4.0};
-            plans.push_back(gk);
-        }
-        if (I.cold) {
-            LanePlan cl{COLD_ADJ, 1, 0, 1, 0.0};
-            plans.push_back(cl);
-        }
-        if (Ntau > 1) {
-            LanePlan sw{SWEEP_ADJ, 1, 0, 1, 0.0};
-            plans.push_back(sw);
-        }
-        PT_TRY(run_engine(C, B, I, plans, ws, Lay, stream, 32));
+        // the reversed sweep consumes slices from N_tau downwards
+        plans.push_back({F_ADJ, Ntau, Ntau, -1, (double)C.M, false, env_int("PT_FQUEUES", 0)});
+        if (I.gk_lanes)
+            plans.push_back({GK_ADJ, Ntau - 1, Ntau - 1, -1, env_double("PT_GK_WEIGHT", 4.0),
+                             false, env_int("PT_GQUEUES", 0)});
+        if (I.cold) plans.push_back({COLD_ADJ, 1, 0, +1, 0.0, true, 0});
+        if (Ntau > 1) plans.push_back({SWEEP_ADJ, 1, 0, +1, 0.0, true, 0});
+        PT_TRY(run_engine(C, B, I, plans, ws, Lay, stream));
         if (it + 1 < prob->iterations) {
             hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Lprev, outL, Nt1 * Nn);
             PT_TRY(launch_check());
@@ -578,6 +660,20 @@ int pt_sensitivities(const pt_problem *prob, const double *rho, const void *ws, 
     hipLaunchKernelGGL(k_sensitivities, dim3(512), dim3(256), 0, stream, C, at<double>(w, Lay.acc),
                        at<double>(w, Lay.accG), dTheta_drho);
     return launch_check();
+}
+
+int pt_query_trace(const pt_problem *prob, const void *ws, hipStream_t stream,
+                   unsigned long long *out, size_t out_words, int *n_lanes, int *stride) {
+    if (!valid_problem(prob) || !ws || !out || !n_lanes || !stride) return PT_EINVAL;
+    const Layout Lay = layout(prob);
+    PT_TRY(hip_ok(hipStreamSynchronize(stream)));
+    const size_t words = (size_t)Lay.max_lanes * Lay.trace_stride;
+    const size_t n = std::min(words, out_words);
+    PT_TRY(hip_ok(hipMemcpy(out, static_cast<const char *>(ws) + Lay.trace,
+                            n * sizeof(unsigned long long), hipMemcpyDeviceToHost)));
+    *n_lanes = Lay.max_lanes;
+    *stride = Lay.trace_stride;
+    return PT_OK;
 }
 
 int pt_query_status(const void *ws, hipStream_t stream, pt_stats *out) {

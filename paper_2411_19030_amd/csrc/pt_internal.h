@@ -11,7 +11,7 @@ namespace pt {
 constexpr int kThreads = 512;       // threads per workgroup of the lane engine
 constexpr int kMaxLanes = 512;      // lanes per engine launch
 constexpr int kMaxGroup = 1024;     // workgroups per lane group (partials slots)
-constexpr int kVecsPerLane = 9;     // x, p, r[2], w[2], s[2], tp
+constexpr int kVecsPerLane = 10;    // x, p, r[2], w[2], s[2], tp, tq
 constexpr int kMaxFlags = 4 * 4096; // dependency flags per launch
 
 // Lane kinds: a lane is a sequence of linear solves executed by one group of
@@ -33,9 +33,15 @@ enum FlagKind : int { FL_F = 0, FL_GK = 1, FL_COLD = 2, FL_SWEEP = 3 };
 struct Lane {
     int kind;
     int slice;      // n for F/GK lanes; unused for sweeps
-    int wg0, nwg;   // workgroup range of the group
-    int vec;        // index of the lane's vector set in the pool
-    int tile;       // nodes per tile
+};
+
+// A group of workgroups runs a queue of lanes one after another; its
+// workgroups share one barrier counter, one partial-sum slot and one vector set.
+struct Group {
+    int wg0, nwg;     // workgroup range
+    int lane0, nlanes;  // lanes [lane0, lane0 + nlanes) in queue order
+    int tile;         // nodes per tile
+    int vec;          // vector set index in the pool
 };
 
 // Device-side control/status block at the start of the workspace.
@@ -55,6 +61,7 @@ struct Consts {
     int nx, ny, W, Nn, Ne, EW;  // W = nx+1 nodes per row, EW = nx+2 padded elements per row
     int Nt, Ntau, M, p;
     int max_iter, verify;
+    int extrap;  // fine steps start from the linear extrapolation 2 T_{j-1} - T_{j-2}
     double hx, hy;
     double e_self, e_x, e_y, e_d;   // stiffness stencil factors (times k/6)
     double cm_unit;                  // hx*hy/36
@@ -68,12 +75,14 @@ struct Consts {
 // Pointers into the workspace and the caller's arrays for one engine launch.
 struct Bufs {
     Control *ctl;
-    unsigned *bar;         // [kMaxLanes] group barrier counters
+    unsigned *bar;         // [kMaxLanes] group barrier counters (one per group)
     unsigned *flags;       // [kMaxFlags]
-    double *partials;      // [kMaxLanes][2][kMaxGroup][4]
-    const int *wg_lane;    // [grid] lane of each workgroup
+    double *partials;      // [kMaxLanes][2][kMaxGroup][4] (one block per group)
+    const int *wg_group;   // [grid] group of each workgroup (-1: idle)
+    const Group *groups;   // [n_groups]
     const Lane *lanes;     // [n_lanes]
-    double *pool;          // lane vectors [n_lanes][kVecsPerLane][Nn]
+    double *pool;          // group vectors [n_groups][kVecsPerLane][Nn]
+    double *FL;            // fine adjoint outputs F_adj(v^k_n), lambda part [Ntau+1][Nn]
     const double *kq;      // padded k/6   [(ny+2)(nx+2)]
     const double *cm;      // padded c*hx*hy/36
     const double *dk;      // k'(rho) per element [Ne]
@@ -100,7 +109,21 @@ struct Bufs {
     double *acc;           // per fine adjoint slice sensitivity sums [Ntau][Ne]
     double *accG;          // coarse correction sensitivity sums [Ne]
     const double *zero;    // Nn zeros
-    const int *fvec;       // pool index of the F lane of slice n, n = 0..Ntau
+    double *xch;           // resident-mode halo exchange [grid][2 parities][2 sides][3][W+2]
+    unsigned long long *trace;  // per-lane record [n_lanes][trace_stride]
+    int trace_stride;           // 8 header words + one timestamp per step
+};
+
+// Trace record of one lane (written by its leader): kind, slice, nwg, tile,
+// rounds (group barriers), CG iterations, start tick, then the end tick of
+// every step. Ticks are the 100 MHz s_memrealtime clock.
+enum {
+    TR_KIND = 0, TR_SLICE, TR_NWG, TR_TILE, TR_ROUNDS, TR_ITERS, TR_START,
+    TR_T_WORK,    // ticks between the end of one barrier and the arrival at the next
+    TR_T_BAR,     // ticks inside group barriers (drain + arrival + wait)
+    TR_T_RED,     // ticks reading partial sums after barriers
+    TR_T_FLAG,    // ticks waiting on other lanes' flags
+    TR_HDR = 12
 };
 
 struct LaunchInfo {
