@@ -30,6 +30,23 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "plain_fp64_256"
 
+# HBM bytes per engine launch of this workload, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs (each scaled by what the counter reads for a 1 GiB device
+# copy: x2.0 and x1.0), averaged over the forward and adjoint launches of a warm
+# cycle; valid only for the kernel sources with this hash (see profiles/).
+TRAFFIC = {"sources_sha1": "ce7eca6a1a0b19359d1866ccf5cd0d5d350c5f12",
+           "bytes_per_launch": 0.5 * (42.34e9 + 43.27e9)}
+
+
+def sources_sha1() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha1()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2411_19030_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -38,7 +55,22 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of 1 GiB (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of exactly 1 GiB, three times: the HBM
+    byte counters of this kernel calibrate FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "repeats": 3}))
 
 
 def cpu_sample() -> dict:
@@ -82,6 +114,9 @@ def main():
     args = parse()
     if args.cpu_sample_only:
         print(json.dumps(cpu_sample()))
+        return
+    if args.copy_calibration:
+        copy_calibration()
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -171,7 +206,9 @@ def main():
                    "parareal_iterations": 1, "guess": "previous (cold) cycle",
                    "precision": "fp64", "preconditioner": "jacobi"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (TRAFFIC["bytes_per_launch"]
+                                 if sources_sha1() == TRAFFIC["sources_sha1"] else None)},
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
         "phase_ms": {"forward": t_fwd, "adjoint": t_adj, "sensitivities": t_sen},
         "cg_iterations": {"forward": it_f, "adjoint": it_a},
