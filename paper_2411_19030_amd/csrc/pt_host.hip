@@ -352,6 +352,14 @@ int run_engine(const Consts &C, Bufs B, const LaunchInfo &I, std::vector<LanePla
             ngroups[k] = q;
             left -= q;
         }
+        // few batched lanes (e.g. one slice): spread each over more workgroups
+        int used_b = 0;
+        for (size_t k = 0; k < plans.size(); ++k)
+            if (!plans[k].latency) used_b += ngroups[k] * g_min;
+        const int spread = std::max(1, (grid - lat_wgs) / std::max(used_b, 1));
+        for (size_t k = 0; k < plans.size(); ++k)
+            if (!plans[k].latency)
+                nwg[k] = std::max(g_min, std::min(g_min * spread, max_wg_per_lane));
         for (size_t k = 0; k < plans.size(); ++k) {
             per_group[k] = (plans[k].count + ngroups[k] - 1) / ngroups[k];
             const int ts = (C.Nn + nwg[k] - 1) / nwg[k];
