@@ -77,7 +77,8 @@ typedef struct pt_problem {
     int32_t iterations;        /* Parareal iterations per pass, >= 1 (1 = one-shot, Alg. 3)       */
     double cg_rtol;            /* stop when ||b - A x||_2 <= cg_rtol ||b||_2, per system, > 0     */
     int32_t max_iter;          /* CG iteration cap per solve, >= 1                                */
-    int32_t precision;         /* PT_FP64 (only value accepted by this build)                     */
+    int32_t precision;         /* PT_FP64, or PT_FP32_REFINE: FP32 CG (stencil, vectors, halo)    */
+                               /* with FP64 dot products, FP64 x and FP64 residual refinement     */
     int32_t precond;           /* PT_JACOBI (only value accepted by this build)                   */
     int32_t storage;           /* PT_STORE_ALL (only value accepted by this build)                */
     int32_t bc;                /* PT_BC_*                                                         */

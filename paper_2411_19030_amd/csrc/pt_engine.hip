@@ -65,6 +65,12 @@ __device__ __forceinline__ double ldc(const double *p) {
 __device__ __forceinline__ void stc(double *p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ float ldc(const float *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stc(float *p, float v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ void set_status(Control *ctl, int code) {
     atomicCAS(&ctl->status, 0, code);
@@ -262,6 +268,39 @@ __device__ __forceinline__ double apply(const Coef &a, const double *L, int li, 
            a.sw * L[li - W - 1];
 }
 
+// The CG working precision (FP64, or FP32 inside FP64 refinement): the same
+// coefficients rounded to Real and the stencil evaluated in Real.
+template <typename Real>
+struct CoefT {
+    Real c, e, w, n, s, ne, nw, se, sw;
+};
+
+template <typename Real>
+__device__ __forceinline__ CoefT<Real> node_coef_t(const Consts &C, const double *LK,
+                                                   const double *LC, int ea, int i, int j,
+                                                   double ms, double ks) {
+    const Coef a = node_coef_l(C, LK, LC, ea, i, j, ms, ks);
+    CoefT<Real> r;
+    r.c = (Real)a.c;
+    r.e = (Real)a.e;
+    r.w = (Real)a.w;
+    r.n = (Real)a.n;
+    r.s = (Real)a.s;
+    r.ne = (Real)a.ne;
+    r.nw = (Real)a.nw;
+    r.se = (Real)a.se;
+    r.sw = (Real)a.sw;
+    return r;
+}
+
+template <typename Real>
+__device__ __forceinline__ Real apply_t(const CoefT<Real> &a, const Real *L, int li, int W) {
+    return a.c * L[li] + a.e * L[li + 1] + a.w * L[li - 1] + a.n * L[li + W] + a.s * L[li - W] +
+           a.ne * L[li + W + 1] + a.nw * L[li + W - 1] + a.se * L[li - W + 1] +
+           a.sw * L[li - W - 1];
+}
+
+
 // lambda^T K0 T and lambda^T C0 D of one element (unit k and c), local node
 // order (ex,ey), (ex+1,ey), (ex+1,ey+1), (ex,ey+1).
 __device__ __forceinline__ double elem_k(const Consts &C, double l0, double l1, double l2,
@@ -456,6 +495,7 @@ struct Ctl {
     bool verifying, zero_x;
     double alpha, beta, gamma;
     double bnorm, relres;
+    double r0n;        // ||r|| at the last (re)start of CG
     double theta;      // primal: theta carried by the lane
     double src_scale;  // adjoint: Theta^{1-p} / N_e
 };
@@ -560,7 +600,7 @@ __global__ void k_copy_f64(double *dst, const double *src, size_t n) {
 // ---------------------------------------------------------------------------
 // The engine
 // ---------------------------------------------------------------------------
-template <int NPT>
+template <int NPT, typename Real>
 __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInfo I) {
     extern __shared__ double lds[];
     __shared__ double red[kWaves * 4];
@@ -586,21 +626,25 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
     const long long tmo = C.timeout_ticks;
 
     double *X = group_vec(B, C, G.vec, V_X);
-    double *P = group_vec(B, C, G.vec, V_P);
+    Real *P = reinterpret_cast<Real *>(group_vec(B, C, G.vec, V_P));
     double *TP = group_vec(B, C, G.vec, V_TP);
     double *TQ = group_vec(B, C, G.vec, V_TQ);
-    double *Rb[2] = {group_vec(B, C, G.vec, V_R0), group_vec(B, C, G.vec, V_R1)};
-    double *Wb[2] = {group_vec(B, C, G.vec, V_W0), group_vec(B, C, G.vec, V_W1)};
-    double *Sb[2] = {group_vec(B, C, G.vec, V_S0), group_vec(B, C, G.vec, V_S1)};
+    auto rv_ = [&](int which) { return reinterpret_cast<Real *>(group_vec(B, C, G.vec, which)); };
+    Real *Rb[2] = {rv_(V_R0), rv_(V_R1)};
+    Real *Wb[2] = {rv_(V_W0), rv_(V_W1)};
+    Real *Sb[2] = {rv_(V_S0), rv_(V_S1)};
+    Real *LZ = reinterpret_cast<Real *>(LA);  // z window of the CG rounds
+    Real *LR = reinterpret_cast<Real *>(LB);  // own residuals of the CG rounds
 
     // resident mode (NPT > 0): this workgroup's tile values of p, r, w, s live
     // in registers across rounds, D^{-1} of the tile in LDS, x in global memory
     // (updated in place each round); the tile's element window is staged once.
     constexpr int NR = NPT > 0 ? NPT : 1;
-    double rp[NR], rr[NR], rw[NR], rs[NR];
+    Real rp[NR], rr[NR], rw[NR], rs[NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) rp[k] = rr[k] = rw[k] = rs[k] = 0.0;
-    double *LD = LB;  // resident: D^{-1} of the tile (LB is free after FIRST)
+    for (int k = 0; k < NR; ++k) rp[k] = rr[k] = rw[k] = rs[k] = 0;
+    Real *LD = LR;  // resident: D^{-1} of the tile (the INIT window is free after FIRST)
+    Real *XCH = reinterpret_cast<Real *>(B.xch);
     int ea_res = 0;
     if constexpr (NPT > 0) {
         const int a = min(rank * TS, C.Nn);
@@ -614,17 +658,17 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
     }
     // boundary values of r, w, s for the neighbours' halos: the first H nodes
     // of the tile go to side 0 (read by rank-1), the last H to side 1 (rank+1)
-    auto publish = [&](int id, int a, int b, double r, double w, double sv, int par) {
+    auto publish = [&](int id, int a, int b, Real r, Real w, Real sv, int par) {
         const int off = id - a;
         if (off < H && rank > 0) {
-            double *base = B.xch + (((size_t)blockIdx.x * 2 + par) * 2 + 0) * 3 * H;
+            Real *base = XCH + (((size_t)blockIdx.x * 2 + par) * 2 + 0) * 3 * H;
             stc(base + off, r);
             stc(base + H + off, w);
             stc(base + 2 * H + off, sv);
         }
         const int o2 = off - ((b - a) - H);
         if (o2 >= 0 && rank < g - 1) {
-            double *base = B.xch + (((size_t)blockIdx.x * 2 + par) * 2 + 1) * 3 * H;
+            Real *base = XCH + (((size_t)blockIdx.x * 2 + par) * 2 + 1) * 3 * H;
             stc(base + o2, r);
             stc(base + H + o2, w);
             stc(base + 2 * H + o2, sv);
@@ -697,6 +741,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
         c.zero_x = false;
         c.alpha = c.beta = c.gamma = 0.0;
         c.bnorm = c.relres = 0.0;
+        c.r0n = 0.0;
         c.theta = 0.0;
         c.src_scale = 0.0;
         if (is_adj) {
@@ -803,7 +848,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                             r0 = bval - ax;
                         }
                         if (x0copy) stc(X + id, x0);
-                        stc(Rb[0] + id, r0);
+                        stc(Rb[0] + id, (Real)r0);
                         loc[0] += bval * bval;
                         loc[1] += r0 * r0;
                         // first step of a lane: zero sensitivity sums, publish copies
@@ -843,6 +888,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                     c.zero_x = false;
                 }
                 c.it_local = 0;
+                const int restart_cap = C.fp32 ? C.max_restarts : 3;
                 if (c.bnorm == 0.0) {
                     c.zero_x = true;
                     c.relres = 0.0;
@@ -850,7 +896,13 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                 } else if (rn <= C.rtol * c.bnorm) {
                     c.relres = rn / c.bnorm;
                     c.phase = PH_POST;
+                } else if (!first_entry && (c.restarts >= restart_cap || c.iter >= C.max_iter)) {
+                    // refinement / verification exhausted: keep x, report
+                    c.relres = rn / c.bnorm;
+                    c.phase = PH_POST;
+                    if (rank == 0 && threadIdx.x == 0) set_status(ctl, -4);
                 } else {
+                    c.r0n = rn;
                     c.phase = PH_FIRST;
                 }
                 c.verifying = false;
@@ -868,22 +920,22 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                     const int len = (b - a) + 2 * H;
                     lds_sync();
                     for (int q0 = threadIdx.x; q0 < len; q0 += kThreads * kU) {
-                        double rv[kU], dv[kU];
+                        Real rv[kU], dv[kU];
 #pragma unroll
                         for (int u = 0; u < kU; ++u) {
                             const int q = q0 + u * kThreads;
                             const int id = lo + q;
                             const bool in = q < len && id >= 0 && id < C.Nn;
-                            rv[u] = in ? ldc(Rb[0] + id) : 0.0;
-                            dv[u] = in ? dinv[id] : 0.0;
+                            rv[u] = in ? ldc(Rb[0] + id) : (Real)0;
+                            dv[u] = in ? (Real)dinv[id] : (Real)0;
                         }
 #pragma unroll
                         for (int u = 0; u < kU; ++u) {
                             const int q = q0 + u * kThreads;
                             const int id = lo + q;
                             if (q < len) {
-                                LA[q] = dv[u] * rv[u];
-                                if (id >= a && id < b) LB[id - a] = rv[u];
+                                LZ[q] = dv[u] * rv[u];
+                                if (id >= a && id < b) LR[id - a] = rv[u];
                             }
                         }
                     }
@@ -897,19 +949,19 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                         rp[k] = rs[k] = 0.0;
                         if (id < b) {
                             const int li2 = id - lo;
-                            double w = 0.0;
+                            Real w = 0;
                             if (!B.mask[id]) {
                                 const int j = id / C.W, i = id - j * C.W;
-                                const Coef aa = node_coef_l(C, LK, LC, ea_res, i, j, ms, 1.0);
-                                w = apply(aa, LA, li2, C.W);
+                                const CoefT<Real> aa = node_coef_t<Real>(C, LK, LC, ea_res, i, j, ms, 1.0);
+                                w = apply_t<Real>(aa, LZ, li2, C.W);
                             }
-                            rr[k] = LB[id - a];
-                            LD[id - a] = dinv[id];
+                            rr[k] = LR[id - a];
+                            LD[id - a] = (Real)dinv[id];
                             rw[k] = w;
-                            const double z = LA[li2];
-                            loc[0] += rr[k] * z;
-                            loc[1] += z * w;
-                            publish(id, a, b, rr[k], rw[k], 0.0, par);
+                            const Real z = LZ[li2];
+                            loc[0] += (double)rr[k] * (double)z;
+                            loc[1] += (double)z * (double)w;
+                            publish(id, a, b, rr[k], rw[k], (Real)0, par);
                         } else {
                             rr[k] = rw[k] = 0.0;
                         }
@@ -927,38 +979,38 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                     lds_sync();
                     stage_elems(B, ea, elen, LK, LC);
                     for (int q0 = threadIdx.x; q0 < len; q0 += kThreads * kU) {
-                        double rv[kU], dv[kU];
+                        Real rv[kU], dv[kU];
 #pragma unroll
                         for (int u = 0; u < kU; ++u) {
                             const int q = q0 + u * kThreads;
                             const int id = lo + q;
                             const bool in = q < len && id >= 0 && id < C.Nn;
-                            rv[u] = in ? ldc(Rb[0] + id) : 0.0;
-                            dv[u] = in ? dinv[id] : 0.0;
+                            rv[u] = in ? ldc(Rb[0] + id) : (Real)0;
+                            dv[u] = in ? (Real)dinv[id] : (Real)0;
                         }
 #pragma unroll
                         for (int u = 0; u < kU; ++u) {
                             const int q = q0 + u * kThreads;
                             const int id = lo + q;
                             if (q < len) {
-                                LA[q] = dv[u] * rv[u];
-                                if (id >= a && id < b) LB[id - a] = rv[u];
+                                LZ[q] = dv[u] * rv[u];
+                                if (id >= a && id < b) LR[id - a] = rv[u];
                             }
                         }
                     }
                     lds_sync();
                     for (int id = a + threadIdx.x; id < b; id += kThreads) {
                         const int li2 = id - lo;
-                        double w = 0.0;
-                        const double z = LA[li2];
+                        Real w = 0;
+                        const Real z = LZ[li2];
                         if (!B.mask[id]) {
                             const int j = id / C.W, i = id - j * C.W;
-                            const Coef aa = node_coef_l(C, LK, LC, ea, i, j, ms, 1.0);
-                            w = apply(aa, LA, li2, C.W);
+                            const CoefT<Real> aa = node_coef_t<Real>(C, LK, LC, ea, i, j, ms, 1.0);
+                            w = apply_t<Real>(aa, LZ, li2, C.W);
                         }
                         stc(Wb[0] + id, w);
-                        loc[0] += LB[id - a] * z;
-                        loc[1] += z * w;
+                        loc[0] += (double)LR[id - a] * (double)z;
+                        loc[1] += (double)z * (double)w;
                     }
                 }
                 }
@@ -1004,33 +1056,33 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                     for (int q = threadIdx.x; q < 2 * H; q += kThreads) {
                         const bool left = q < H;
                         const int id = left ? a - H + q : b + (q - H);
-                        double z = 0.0;
+                        Real z = 0;
                         if (id >= 0 && id < C.Nn) {
                             const int nb = left ? blockIdx.x - 1 : blockIdx.x + 1;
                             const int k = left ? q : q - H;
-                            const double *base =
-                                B.xch + (((size_t)nb * 2 + ppar) * 2 + (left ? 1 : 0)) * 3 * H;
-                            const double rh = ldc(base + k);
-                            const double wh = ldc(base + H + k);
-                            const double sh = first ? 0.0 : ldc(base + 2 * H + k);
-                            const double sv = first ? wh : wh + be * sh;
-                            z = dinv[id] * (rh - al * sv);
+                            const Real *base =
+                                XCH + (((size_t)nb * 2 + ppar) * 2 + (left ? 1 : 0)) * 3 * H;
+                            const Real rh = ldc(base + k);
+                            const Real wh = ldc(base + H + k);
+                            const Real sh = first ? (Real)0 : ldc(base + 2 * H + k);
+                            const Real sv = first ? wh : wh + (Real)be * sh;
+                            z = (Real)dinv[id] * (rh - (Real)al * sv);
                         }
-                        LA[left ? q : (b - lo) + (q - H)] = z;
+                        LZ[left ? q : (b - lo) + (q - H)] = z;
                     }
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
                         const int id = a + tid + k * kThreads;
                         if (id < b) {
-                            const double dk = LD[id - a];
-                            const double zi = dk * rr[k];
-                            const double pn = first ? zi : zi + be * rp[k];
-                            const double sn = first ? rw[k] : rw[k] + be * rs[k];
-                            stc(X + id, xo[k] + al * pn);
-                            rr[k] -= al * sn;
+                            const Real dk = LD[id - a];
+                            const Real zi = dk * rr[k];
+                            const Real pn = first ? zi : zi + (Real)be * rp[k];
+                            const Real sn = first ? rw[k] : rw[k] + (Real)be * rs[k];
+                            stc(X + id, xo[k] + al * (double)pn);
+                            rr[k] -= (Real)al * sn;
                             rp[k] = pn;
                             rs[k] = sn;
-                            LA[id - lo] = dk * rr[k];
+                            LZ[id - lo] = dk * rr[k];
                         }
                     }
                     lds_sync();
@@ -1040,17 +1092,17 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                         const int id = a + tid + k * kThreads;
                         if (id < b) {
                             const int li2 = id - lo;
-                            double w = 0.0;
+                            Real w = 0;
                             if (!B.mask[id]) {
                                 const int j = id / C.W, i = id - j * C.W;
-                                const Coef aa = node_coef_l(C, LK, LC, ea_res, i, j, ms, 1.0);
-                                w = apply(aa, LA, li2, C.W);
+                                const CoefT<Real> aa = node_coef_t<Real>(C, LK, LC, ea_res, i, j, ms, 1.0);
+                                w = apply_t<Real>(aa, LZ, li2, C.W);
                             }
                             rw[k] = w;
-                            const double z = LA[li2];
-                            loc[0] += rr[k] * z;
-                            loc[1] += z * w;
-                            loc[2] += rr[k] * rr[k];
+                            const Real z = LZ[li2];
+                            loc[0] += (double)rr[k] * (double)z;
+                            loc[1] += (double)z * (double)w;
+                            loc[2] += (double)rr[k] * (double)rr[k];
                             publish(id, a, b, rr[k], rw[k], rs[k], par);
                         }
                         // keep the unrolled node iterations from being interleaved
@@ -1060,8 +1112,8 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                 }
                 } else {
                 const int cur = i0 & 1, nxt = cur ^ 1;
-                double *Rc = Rb[cur], *Rn = Rb[nxt], *Wc = Wb[cur], *Wn = Wb[nxt];
-                double *Sc = Sb[cur], *Sn = Sb[nxt];
+                Real *Rc = Rb[cur], *Rn = Rb[nxt], *Wc = Wb[cur], *Wn = Wb[nxt];
+                Real *Sc = Sb[cur], *Sn = Sb[nxt];
                 for (int t = rank; t < ntiles; t += g) {
                     const int a = t * TS;
                     const int b = min(a + TS, C.Nn);
@@ -1072,7 +1124,8 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                     lds_sync();
                     stage_elems(B, ea, elen, LK, LC);
                     for (int q0 = threadIdx.x; q0 < len; q0 += kThreads * kU) {
-                        double rv[kU], wv[kU], sv[kU], dv[kU], pv[kU], xv[kU];
+                        Real rv[kU], wv[kU], sv[kU], dv[kU], pv[kU];
+                        double xv[kU];
 #pragma unroll
                         for (int u = 0; u < kU; ++u) {
                             const int q = q0 + u * kThreads;
@@ -1082,7 +1135,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                             rv[u] = in ? ldc(Rc + id) : 0.0;
                             wv[u] = in ? ldc(Wc + id) : 0.0;
                             sv[u] = (in && !first) ? ldc(Sc + id) : 0.0;
-                            dv[u] = in ? dinv[id] : 0.0;
+                            dv[u] = in ? (Real)dinv[id] : (Real)0;
                             pv[u] = (own && !first) ? ldc(P + id) : 0.0;
                             xv[u] = own ? ldc(X + id) : 0.0;
                         }
@@ -1091,17 +1144,17 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                             const int q = q0 + u * kThreads;
                             const int id = lo + q;
                             if (q < len) {
-                                const double s_new = first ? wv[u] : wv[u] + be * sv[u];
-                                const double r_new = rv[u] - al * s_new;
-                                LA[q] = dv[u] * r_new;
+                                const Real s_new = first ? wv[u] : wv[u] + (Real)be * sv[u];
+                                const Real r_new = rv[u] - (Real)al * s_new;
+                                LZ[q] = dv[u] * r_new;
                                 if (id >= a && id < b) {
-                                    const double zi = dv[u] * rv[u];
-                                    const double pn = first ? zi : zi + be * pv[u];
+                                    const Real zi = dv[u] * rv[u];
+                                    const Real pn = first ? zi : zi + (Real)be * pv[u];
                                     stc(P + id, pn);
                                     stc(Sn + id, s_new);
-                                    stc(X + id, xv[u] + al * pn);
+                                    stc(X + id, xv[u] + al * (double)pn);
                                     stc(Rn + id, r_new);
-                                    LB[id - a] = r_new;
+                                    LR[id - a] = r_new;
                                 }
                             }
                         }
@@ -1109,17 +1162,17 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                     lds_sync();
                     for (int id = a + threadIdx.x; id < b; id += kThreads) {
                         const int li2 = id - lo;
-                        double w = 0.0;
+                        Real w = 0;
                         if (!B.mask[id]) {
                             const int j = id / C.W, i = id - j * C.W;
-                            const Coef aa = node_coef_l(C, LK, LC, ea, i, j, ms, 1.0);
-                            w = apply(aa, LA, li2, C.W);
+                            const CoefT<Real> aa = node_coef_t<Real>(C, LK, LC, ea, i, j, ms, 1.0);
+                            w = apply_t<Real>(aa, LZ, li2, C.W);
                         }
                         stc(Wn + id, w);
-                        const double z = LA[li2];
-                        const double rn = LB[id - a];
+                        const Real z = LZ[li2];
+                        const double rn = LR[id - a];
                         loc[0] += rn * z;
-                        loc[1] += z * w;
+                        loc[1] += (double)z * (double)w;
                         loc[2] += rn * rn;
                     }
                 }
@@ -1139,18 +1192,25 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                 c.it_local = i0 + 1;
                 c.iter += 1;
                 const double rn = sqrt(tot[2]);
-                if (rn <= C.rtol * c.bnorm || c.iter >= C.max_iter) {
+                // FP32 inner solves stop at a relative reduction inner_rtol of the
+                // residual they started from; the FP64 residual of the refinement
+                // step (INIT) decides convergence
+                const double target =
+                    C.fp32 ? fmax(C.rtol * c.bnorm, C.inner_rtol * c.r0n) : C.rtol * c.bnorm;
+                if (rn <= target || c.iter >= C.max_iter) {
                     c.relres = rn / c.bnorm;
-                    if (C.verify && rn <= C.rtol * c.bnorm && c.restarts < 3) {
-                        // true-residual check: recompute r = b - A x, restart if needed
+                    const bool check = C.fp32 ? (c.iter < C.max_iter)
+                                              : (C.verify && rn <= C.rtol * c.bnorm && c.restarts < 3);
+                    if (check) {
+                        // recompute r = b - A x in FP64, restart CG if needed
                         c.verifying = true;
                         c.restarts += 1;
                         c.phase = PH_INIT;
                     } else {
                         c.phase = PH_POST;
+                        if (rn > C.rtol * c.bnorm && rank == 0 && threadIdx.x == 0)
+                            set_status(ctl, -4);
                     }
-                    if (rn > C.rtol * c.bnorm && rank == 0 && threadIdx.x == 0)
-                        set_status(ctl, -4);
                 } else {
                     const double gnew = tot[0];
                     const double bnew = gnew / c.gamma;

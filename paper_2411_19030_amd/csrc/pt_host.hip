@@ -44,7 +44,8 @@ bool valid_problem(const pt_problem *p) {
     if (!(p->kmin > 0.0) || !(p->k0 > 0.0) || !(p->cmin > 0.0) || !(p->c0 > 0.0)) return false;
     if (p->pk < 1.0 || p->pc < 1.0) return false;
     if (!p->q_t && !isfinite(p->q)) return false;
-    if (p->precision != PT_FP64 || p->precond != PT_JACOBI || p->storage != PT_STORE_ALL)
+    if ((p->precision != PT_FP64 && p->precision != PT_FP32_REFINE) || p->precond != PT_JACOBI ||
+        p->storage != PT_STORE_ALL)
         return false;
     if (p->bc < 0 || p->bc > 3) return false;
     if (p->bc == PT_BC_MASK && !p->dirichlet_mask) return false;
@@ -121,6 +122,9 @@ Consts make_consts(const pt_problem *p) {
     C.max_iter = p->max_iter;
     C.verify = getenv("PT_VERIFY") ? atoi(getenv("PT_VERIFY")) : 1;
     C.extrap = getenv("PT_EXTRAP") ? atoi(getenv("PT_EXTRAP")) : 0;
+    C.fp32 = p->precision == PT_FP32_REFINE ? 1 : 0;
+    C.max_restarts = 40;
+    C.inner_rtol = getenv("PT_INNER_RTOL") ? atof(getenv("PT_INNER_RTOL")) : 1e-5;
     C.hx = 1.0 / p->nx;
     C.hy = 1.0 / p->ny;
     const double rx = C.hy / C.hx, ry = C.hx / C.hy;
@@ -436,11 +440,19 @@ int run_engine(const Consts &C, Bufs B, const LaunchInfo &I, std::vector<LanePla
                        (size_t)Lay.max_lanes * Lay.trace_stride * 2, 0u);
     PT_TRY(launch_check());
 
-    const void *kern = npt == 0   ? (const void *)k_engine<0>
-                       : npt == 1 ? (const void *)k_engine<1>
-                       : npt == 2 ? (const void *)k_engine<2>
-                       : npt == 4 ? (const void *)k_engine<4>
-                                  : (const void *)k_engine<8>;
+    const void *kern;
+    if (C.fp32)
+        kern = npt == 0   ? (const void *)k_engine<0, float>
+               : npt == 1 ? (const void *)k_engine<1, float>
+               : npt == 2 ? (const void *)k_engine<2, float>
+               : npt == 4 ? (const void *)k_engine<4, float>
+                          : (const void *)k_engine<8, float>;
+    else
+        kern = npt == 0   ? (const void *)k_engine<0, double>
+               : npt == 1 ? (const void *)k_engine<1, double>
+               : npt == 2 ? (const void *)k_engine<2, double>
+               : npt == 4 ? (const void *)k_engine<4, double>
+                          : (const void *)k_engine<8, double>;
     PT_TRY(hip_ok(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds_bytes)));
     int occ = 0;

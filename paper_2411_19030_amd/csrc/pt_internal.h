@@ -62,6 +62,9 @@ struct Consts {
     int Nt, Ntau, M, p;
     int max_iter, verify;
     int extrap;  // fine steps start from the linear extrapolation 2 T_{j-1} - T_{j-2}
+    int fp32;          // CG in FP32 inside FP64 iterative refinement
+    int max_restarts;  // FP64 refinement steps per solve (FP32 mode)
+    double inner_rtol; // relative residual reduction of one FP32 inner solve
     double hx, hy;
     double e_self, e_x, e_y, e_d;   // stiffness stencil factors (times k/6)
     double cm_unit;                  // hx*hy/36
