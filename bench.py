@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-compare", action="store_true",
+                    help="skip the FP32+refine vs FP64 comparison at equal objective accuracy")
     ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (counter calibration)")
@@ -108,6 +110,58 @@ def cpu_baseline() -> dict:
             "sample": (f"one cold one-iteration cycle (forward + adjoint + sensitivities) of "
                        f"the {WORKLOAD} workload by the FP64 oracle, sparse LU per step, one "
                        f"thread: {r['seconds']:.1f} s for {r['cells']} cell updates")}
+
+
+def precision_compare(prob, rho, gT, gth, gl, accuracy=1e-6, repeats=3) -> dict:
+    """FP32 inner CG with FP64 refinement against plain FP64 at equal objective
+    accuracy. For each precision the loosest CG tolerance of a fixed ladder whose
+    warm-cycle Theta stays within `accuracy` (relative) of a FP64 cycle solved to
+    rtol 1e-13 is chosen, then that cycle is timed (median of `repeats`). The
+    FP64 rtol-1e-13 path matches the oracle to 1e-10 in the parity tests."""
+    import dataclasses
+
+    import torch
+
+    from paper_2411_19030_amd.cycle import Cycle
+    stream = torch.cuda.current_stream()
+
+    def cycle_for(precision, rtol):
+        return Cycle(dataclasses.replace(prob, precision=precision, cg_rtol=rtol), rho.device)
+
+    def timed(cyc):
+        ts = []
+        for _ in range(repeats):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            cyc.run(rho, gT, gth, gl)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+
+    ref = cycle_for(0, 1e-13)
+    ref.run(rho, gT, gth, gl)
+    torch.cuda.synchronize()
+    th_ref = float(ref.Theta)
+    g_ref = ref.grad.clone()
+    out = {"accuracy": accuracy, "reference": "fp64 warm cycle at cg_rtol 1e-13"}
+    for name, prec in (("fp64", 0), ("fp32_refine", 1)):
+        best = None
+        for rtol in (1e-5, 1e-6, 1e-7, 1e-8, 1e-9):
+            cyc = cycle_for(prec, rtol)
+            cyc.run(rho, gT, gth, gl)
+            torch.cuda.synchronize()
+            err = abs(float(cyc.Theta) - th_ref) / abs(th_ref)
+            if err <= accuracy:
+                gerr = float(torch.linalg.norm(cyc.grad - g_ref) / torch.linalg.norm(g_ref))
+                best = {"cg_rtol": rtol, "ms_per_cycle": timed(cyc), "Theta_rel_err": err,
+                        "grad_rel_err": gerr, "status": cyc.status()["status"]}
+                break
+        out[name] = best
+    if out["fp64"] and out["fp32_refine"]:
+        out["speedup_fp32_refine_over_fp64"] = (out["fp64"]["ms_per_cycle"]
+                                                / out["fp32_refine"]["ms_per_cycle"])
+    return out
 
 
 def main():
@@ -215,6 +269,8 @@ def main():
         "status": st["status"],
         "Theta": float(cyc.Theta),
     }
+    if not args.no_precision_compare:
+        out["vs_fp64"] = precision_compare(prob, rho, gT, gth, gl)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -166,6 +166,74 @@ int pt_query_status(const void *ws, hipStream_t stream, pt_stats *out);
 /* Static string for a return code. */
 const char *pt_strerror(int code);
 
+/* ------------------------------------------------------------------------
+ * Many designs in one cycle (one persistent launch per pass for all designs).
+ *
+ * Each design is an independent problem of its own grid and slice count; all
+ * designs of a batch share `precision` and take one Parareal iteration
+ * (iterations == 1). One call runs a whole optimisation cycle of every design
+ * (Sec. 4.4 steps 1-4): the primal passes of all designs in one engine launch,
+ * the adjoint passes of all designs in a second launch, then the sensitivities.
+ * The workspace keeps each design's S, its corrected coarse states u_n and
+ * adjoint states v_n; with warm = 1 the next call restarts every design from
+ * them (the one-shot warm restart of Alg. 3), so consecutive warm calls must
+ * pass the same `probs` and the same workspace. Apart from caller masks and
+ * q(t) (host copies), a call enqueues kernels only and can be captured in a
+ * graph; the engine launch is then a plain launch of a grid that the
+ * occupancy check has shown to be co-resident.
+ * ------------------------------------------------------------------------ */
+
+/* Worker shapes of a multi-design launch. Lanes (a slice's fine propagator or
+ * a batched coarse step; a design's coarse sweep) are taken from two queues by
+ * groups of workgroups: `sweep_groups` groups of `sweep_wgs` workgroups run
+ * the sequential coarse sweeps, the rest of the grid is cut into groups of
+ * `fine_wgs` workgroups for the fine and batched coarse lanes. */
+typedef struct pt_batch_tuning {
+    int32_t fine_wgs;      /* workgroups per fine-lane group, 1..1024                         */
+    int32_t sweep_wgs;     /* workgroups per sweep group, 1..1024                             */
+    int32_t sweep_groups;  /* sweep groups, >= 1                                              */
+    int32_t resident;      /* 1: vectors held in registers (every design's tile must fit)   */
+    int32_t grid;          /* workgroups of the launch, 0 = as many as are co-resident        */
+    int32_t reserved[3];
+} pt_batch_tuning;
+
+/* Workspace bytes of a batch of n designs; 0 if any problem is invalid, the
+ * precisions differ, or a design has iterations != 1. */
+size_t pt_batched_workspace_bytes(int n, const pt_problem *probs);
+
+/* The built-in worker shapes for n designs (environment overrides included). */
+int pt_batch_default_tuning(int n, pt_batch_tuning *out);
+
+/*
+ * One optimisation cycle of n designs.
+ *   probs        [n] HOST problem descriptions (as for the single-design calls)
+ *   rho          [n] HOST array of device pointers, rho[k] has probs[k].nx*ny elements
+ *   warm         0: cold start from the coarse sweeps; 1: restart from the previous call's
+ *                solution kept in ws
+ *   tuning       worker shapes, or NULL for pt_batch_default_tuning
+ *   Theta_out    [n] device array: Theta of every design
+ *   dTheta_drho  [n] HOST array of device pointers to [N_e] outputs
+ * Outputs must not overlap ws. Device-side problems are reported per design
+ * by pt_batched_status.
+ */
+int pt_parareal_batched(int n, const pt_problem *probs, const double *const *rho, int warm,
+                        const pt_batch_tuning *tuning, double *Theta_out,
+                        double *const *dTheta_drho, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Synchronises `stream` and reads the status and counters of every design. */
+int pt_batched_status(int n, const pt_problem *probs, const void *ws, hipStream_t stream,
+                      pt_stats *out /* [n] */);
+
+/* Times whole warm cycles of this batch for a set of worker shapes (coordinate
+ * descent over fine_wgs, sweep_wgs and sweep_groups, starting from the
+ * defaults) and returns the fastest. Synchronous; runs one cold cycle first,
+ * leaves ws holding a valid warm state and the outputs of the last cycle. */
+int pt_autotune_batched(int n, const pt_problem *probs, const double *const *rho,
+                        double *Theta_out, double *const *dTheta_drho, void *ws,
+                        size_t ws_bytes, hipStream_t stream, pt_batch_tuning *best,
+                        double *best_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,9 @@ PT_JACOBI, PT_GMG = 0, 1
 PT_STORE_ALL, PT_CHECKPOINT = 0, 1
 
 EXPORTS = ["pt_workspace_bytes", "pt_validate", "pt_parareal_forward", "pt_parareal_adjoint",
-           "pt_sensitivities", "pt_query_status", "pt_query_trace", "pt_strerror"]
+           "pt_sensitivities", "pt_query_status", "pt_query_trace", "pt_strerror",
+           "pt_batched_workspace_bytes", "pt_batch_default_tuning", "pt_parareal_batched",
+           "pt_batched_status", "pt_autotune_batched"]
 
 
 class PtProblem(ctypes.Structure):
@@ -49,6 +51,25 @@ class PtStats(ctypes.Structure):
         ("solves_fine", ctypes.c_int64), ("solves_coarse", ctypes.c_int64),
         ("max_rel_residual", ctypes.c_double),
     ]
+
+
+class PtBatchTuning(ctypes.Structure):
+    _fields_ = [
+        ("fine_wgs", ctypes.c_int32), ("sweep_wgs", ctypes.c_int32),
+        ("sweep_groups", ctypes.c_int32), ("resident", ctypes.c_int32),
+        ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+    ]
+
+    def as_dict(self) -> dict:
+        return dict(fine_wgs=self.fine_wgs, sweep_wgs=self.sweep_wgs,
+                    sweep_groups=self.sweep_groups, resident=self.resident, grid=self.grid)
+
+    @staticmethod
+    def from_dict(d: dict) -> "PtBatchTuning":
+        t = PtBatchTuning()
+        for k in ("fine_wgs", "sweep_wgs", "sweep_groups", "resident", "grid"):
+            setattr(t, k, int(d.get(k, 0)))
+        return t
 
 
 _lib = None
@@ -82,6 +103,20 @@ def load_library(path: str = LIB_PATH):
     lib.pt_query_trace.restype = ctypes.c_int
     lib.pt_strerror.argtypes = [ctypes.c_int]
     lib.pt_strerror.restype = ctypes.c_char_p
+    TP = ctypes.POINTER(PtBatchTuning)
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    lib.pt_batched_workspace_bytes.argtypes = [ctypes.c_int, P]
+    lib.pt_batched_workspace_bytes.restype = ctypes.c_size_t
+    lib.pt_batch_default_tuning.argtypes = [ctypes.c_int, TP]
+    lib.pt_batch_default_tuning.restype = ctypes.c_int
+    lib.pt_parareal_batched.argtypes = [ctypes.c_int, P, pp, ctypes.c_int, TP, vp, pp, vp,
+                                        ctypes.c_size_t, vp]
+    lib.pt_parareal_batched.restype = ctypes.c_int
+    lib.pt_batched_status.argtypes = [ctypes.c_int, P, vp, vp, ctypes.POINTER(PtStats)]
+    lib.pt_batched_status.restype = ctypes.c_int
+    lib.pt_autotune_batched.argtypes = [ctypes.c_int, P, pp, vp, pp, vp, ctypes.c_size_t, vp, TP,
+                                        ctypes.POINTER(ctypes.c_double)]
+    lib.pt_autotune_batched.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -252,3 +287,61 @@ def pt_query_status(ws, stream=None) -> dict:
     _check(load_library().pt_query_status(_ptr(ws), _stream(stream), ctypes.byref(st)),
            "pt_query_status")
     return {k: getattr(st, k) for k, _ in PtStats._fields_}
+
+
+# ---------------------------------------------------------------------------
+# Multi-design cycles
+# ---------------------------------------------------------------------------
+
+def _probs_array(probs):
+    arr = (PtProblem * len(probs))()
+    for k, p in enumerate(probs):
+        arr[k] = p.to_c()
+    return arr
+
+
+def _ptr_array(tensors):
+    return (ctypes.c_void_p * len(tensors))(*[_ptr(t) for t in tensors])
+
+
+def pt_batched_workspace_bytes(probs) -> int:
+    arr = _probs_array(probs)
+    return int(load_library().pt_batched_workspace_bytes(len(probs), arr))
+
+
+def pt_batch_default_tuning(n: int) -> dict:
+    t = PtBatchTuning()
+    _check(load_library().pt_batch_default_tuning(n, ctypes.byref(t)), "pt_batch_default_tuning")
+    return t.as_dict()
+
+
+def pt_parareal_batched(probs, rhos, warm: bool, tuning: Optional[dict], Theta_out, grads, ws,
+                        stream=None, check: bool = True) -> int:
+    arr = _probs_array(probs)
+    t = PtBatchTuning.from_dict(tuning) if tuning is not None else None
+    rc = load_library().pt_parareal_batched(
+        len(probs), arr, _ptr_array(rhos), 1 if warm else 0,
+        ctypes.byref(t) if t is not None else None, _ptr(Theta_out), _ptr_array(grads),
+        _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
+    if check:
+        _check(rc, "pt_parareal_batched")
+    return rc
+
+
+def pt_batched_status(probs, ws, stream=None) -> list:
+    arr = _probs_array(probs)
+    st = (PtStats * len(probs))()
+    _check(load_library().pt_batched_status(len(probs), arr, _ptr(ws), _stream(stream), st),
+           "pt_batched_status")
+    return [{k: getattr(s, k) for k, _ in PtStats._fields_} for s in st]
+
+
+def pt_autotune_batched(probs, rhos, Theta_out, grads, ws, stream=None) -> tuple:
+    arr = _probs_array(probs)
+    t = PtBatchTuning()
+    ms = ctypes.c_double()
+    _check(load_library().pt_autotune_batched(
+        len(probs), arr, _ptr_array(rhos), _ptr(Theta_out), _ptr_array(grads), _ptr(ws),
+        ws.numel() * ws.element_size(), _stream(stream), ctypes.byref(t), ctypes.byref(ms)),
+        "pt_autotune_batched")
+    return t.as_dict(), ms.value

@@ -71,6 +71,12 @@ __device__ __forceinline__ float ldc(const float *p) {
 __device__ __forceinline__ void stc(float *p, float v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ int ldc(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stc(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ void set_status(Control *ctl, int code) {
     atomicCAS(&ctl->status, 0, code);
@@ -349,8 +355,8 @@ __device__ __forceinline__ int lane_steps(const Consts &C, int kind) {
 
 enum { V_X = 0, V_P = 1, V_R0 = 2, V_R1 = 3, V_W0 = 4, V_W1 = 5, V_S0 = 6, V_S1 = 7, V_TP = 8, V_TQ = 9 };
 
-__device__ __forceinline__ double *group_vec(const Bufs &B, const Consts &C, int vec, int which) {
-    return B.pool + ((size_t)vec * kVecsPerLane + which) * (size_t)C.Nn;
+__device__ __forceinline__ double *group_vec(const Bufs &B, int vec, int which) {
+    return B.pool + ((size_t)vec * kVecsPerLane + which) * B.pool_stride;
 }
 
 __device__ StepInfo step_info(const Consts &C, const Bufs &B, const LaunchInfo &I, const Lane &L,
@@ -529,53 +535,81 @@ __device__ __forceinline__ double sens_term(const Consts &C, const Bufs &B, cons
 // ---------------------------------------------------------------------------
 
 // Material (Eq. 2.5-2.6): padded k/6 and c hx hy/36, derivatives k', c'.
-__global__ void k_material(Consts C, const double *rho, double *kq, double *cm, double *dk,
-                           double *dc, double k0, double kmin, double pk, double c0, double cmin,
-                           double pc, Control *ctl) {
+// Setup of every design of a launch (blockIdx.y = design): Dirichlet mask of
+// the standard rules (PT_BC_*), the source history q(t_n) when it is constant,
+// the zero vector, and the SIMP material of Eq. 2.5-2.6 per element:
+// kq = k(rho)/6 and cm = c(rho) hx hy / 36 on a zero-padded element grid,
+// dk = k'(rho), dc = c'(rho). Negative or non-finite densities set PT_EDOMAIN.
+__global__ void k_setup_design(const EngineDesc *__restrict__ D) {
+    const EngineDesc &E = D[blockIdx.y];
+    const Consts &C = E.C;
+    const Bufs &B = E.B;
+    const int stride = gridDim.x * blockDim.x;
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (C.bc_rule != 3) {
+        for (int id = t0; id < C.Nn; id += stride) {
+            const int j = id / C.W, i = id - j * C.W;
+            unsigned char m = 0;
+            if (C.bc_rule == 0) m = (i == 0 && 9 * C.ny <= 20 * j && 20 * j <= 11 * C.ny) ? 1 : 0;
+            if (C.bc_rule == 1) m = (j == 0 && 9 * C.nx <= 20 * i && 20 * i <= 11 * C.nx) ? 1 : 0;
+            B.mask[id] = m;
+        }
+    }
+    if (!C.has_qt)
+        for (int n = t0; n <= C.Nt; n += stride) B.qt[n] = C.q;
+    for (int id = t0; id < C.Nn; id += stride) B.zero[id] = 0.0;
     const int EH = C.ny + 2;
     const int total = EH * C.EW;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    for (int t = t0; t < total; t += stride) {
         const int py = t / C.EW, px = t - py * C.EW;
         const int ex = px - 1, ey = py - 1;
         double kv = 0.0, cv = 0.0;
         if (ex >= 0 && ex < C.nx && ey >= 0 && ey < C.ny) {
             const int e = ey * C.nx + ex;
-            const double r = rho[e];
-            if (!(r >= 0.0) || !isfinite(r)) set_status(ctl, -5);
+            const double r = B.rho[e];
+            if (!(r >= 0.0) || !isfinite(r)) set_status(B.ctl, -5);
             const double rr = r > 0.0 ? r : 0.0;
-            const double kk = kmin + (k0 - kmin) * pow(rr, pk);
-            const double cc = cmin + (c0 - cmin) * pow(rr, pc);
-            dk[e] = pk * (k0 - kmin) * pow(rr, pk - 1.0);
-            dc[e] = pc * (c0 - cmin) * pow(rr, pc - 1.0);
+            const double kk = C.kmin + (C.k0 - C.kmin) * pow(rr, C.pk);
+            const double cc = C.cmin + (C.c0 - C.cmin) * pow(rr, C.pc);
+            B.dk[e] = C.pk * (C.k0 - C.kmin) * pow(rr, C.pk - 1.0);
+            B.dc[e] = C.pc * (C.c0 - C.cmin) * pow(rr, C.pc - 1.0);
             kv = kk * (1.0 / 6.0);
             cv = cc * C.cm_unit;
         }
-        kq[t] = kv;
-        cm[t] = cv;
+        B.kq[t] = kv;
+        B.cm[t] = cv;
     }
 }
 
-// Jacobi inverse diagonals of C/dt + K and C/dtau + K (0 on Dirichlet nodes).
-__global__ void k_diag(Consts C, const double *kq, const double *cm, const unsigned char *mask,
-                       double *dinv_f, double *dinv_c) {
+// Jacobi inverse diagonals of C/dt + K and C/dtau + K (0 on Dirichlet nodes),
+// blockIdx.y = design.
+__global__ void k_diag(const EngineDesc *__restrict__ D) {
+    const EngineDesc &E = D[blockIdx.y];
+    const Consts &C = E.C;
+    const Bufs &B = E.B;
     for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < C.Nn; id += gridDim.x * blockDim.x) {
         const int j = id / C.W, i = id - j * C.W;
-        const Coef af = node_coef(C, kq, cm, i, j, C.inv_dt, 1.0);
-        const Coef ac = node_coef(C, kq, cm, i, j, C.inv_dtau, 1.0);
-        const bool d = mask[id] != 0;
-        dinv_f[id] = d ? 0.0 : 1.0 / af.c;
-        dinv_c[id] = d ? 0.0 : 1.0 / ac.c;
+        const Coef af = node_coef(C, B.kq, B.cm, i, j, C.inv_dt, 1.0);
+        const Coef ac = node_coef(C, B.kq, B.cm, i, j, C.inv_dtau, 1.0);
+        const bool d = B.mask[id] != 0;
+        B.dinv_f[id] = d ? 0.0 : 1.0 / af.c;
+        B.dinv_c[id] = d ? 0.0 : 1.0 / ac.c;
     }
 }
 
-// Dirichlet masks of the standard rules (PT_BC_*).
-__global__ void k_mask_rule(Consts C, int rule, unsigned char *mask) {
-    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < C.Nn; id += gridDim.x * blockDim.x) {
-        const int j = id / C.W, i = id - j * C.W;
-        unsigned char m = 0;
-        if (rule == 0) m = (i == 0 && 9 * C.ny <= 20 * j && 20 * j <= 11 * C.ny) ? 1 : 0;
-        if (rule == 1) m = (j == 0 && 9 * C.nx <= 20 * i && 20 * i <= 11 * C.nx) ? 1 : 0;
-        mask[id] = m;
+// Reset of each design's status block (blockIdx.x = design); the forward-done
+// marker survives into the adjoint call.
+__global__ void k_reset_ctl(const EngineDesc *__restrict__ D, int keep_markers) {
+    if (threadIdx.x == 0) {
+        Control *ctl = D[blockIdx.x].B.ctl;
+        const int f = ctl->fwd_done;
+        ctl->status = 0;
+        ctl->abort = 0;
+        ctl->max_iters = 0;
+        ctl->iters_fine = ctl->iters_coarse = ctl->solves_fine = ctl->solves_coarse = 0;
+        ctl->max_relres_bits = 0;
+        ctl->fwd_done = keep_markers ? f : 0;
+        ctl->adj_done = 0;
     }
 }
 
@@ -601,125 +635,151 @@ __global__ void k_copy_f64(double *dst, const double *src, size_t n) {
 // The engine
 // ---------------------------------------------------------------------------
 template <int NPT, typename Real>
-__global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInfo I) {
+__global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restrict__ D, Launch S) {
     extern __shared__ double lds[];
     __shared__ double red[kWaves * 4];
 
-    const int gid = B.wg_group[blockIdx.x];
+    const int gid = S.wg_group[blockIdx.x];
     if (gid < 0) return;
-    const Group G = B.groups[gid];
+    const Group G = S.groups[gid];
     const int rank = blockIdx.x - G.wg0;
     const int g = G.nwg;
-    const int H = C.W + 1;  // halo on each side of a tile window
-    const int TS = G.tile;
-    const int win = TS + 2 * H;
-    const int ewin = ((TS - 1) / C.W + 3) * C.EW;  // element window bound
-    double *LA = lds;        // window A (halo'd)
-    double *LB = lds + win;  // window B (INIT) / own residuals (ITER)
-    double *LK = lds + 2 * win;          // k/6 of the tile's elements
-    double *LC = lds + 2 * win + ewin;   // c hx hy/36 of the tile's elements
-    const int ntiles = (C.Nn + TS - 1) / TS;
-    Control *ctl = B.ctl;
-    unsigned *bar = B.bar + gid;
-    double *part = B.partials + (size_t)gid * 2 * kMaxGroup * 4;
+    unsigned *bar = S.bar + gid;
+    double *part = S.partials + (size_t)gid * 2 * kMaxGroup * 4;
     unsigned nbar = 0;
-    const long long tmo = C.timeout_ticks;
-
-    double *X = group_vec(B, C, G.vec, V_X);
-    Real *P = reinterpret_cast<Real *>(group_vec(B, C, G.vec, V_P));
-    double *TP = group_vec(B, C, G.vec, V_TP);
-    double *TQ = group_vec(B, C, G.vec, V_TQ);
-    auto rv_ = [&](int which) { return reinterpret_cast<Real *>(group_vec(B, C, G.vec, which)); };
-    Real *Rb[2] = {rv_(V_R0), rv_(V_R1)};
-    Real *Wb[2] = {rv_(V_W0), rv_(V_W1)};
-    Real *Sb[2] = {rv_(V_S0), rv_(V_S1)};
-    Real *LZ = reinterpret_cast<Real *>(LA);  // z window of the CG rounds
-    Real *LR = reinterpret_cast<Real *>(LB);  // own residuals of the CG rounds
+    const int XS = S.xch_stride;  // launch-wide halo slot length (>= H of every design)
 
     // resident mode (NPT > 0): this workgroup's tile values of p, r, w, s live
     // in registers across rounds, D^{-1} of the tile in LDS, x in global memory
-    // (updated in place each round); the tile's element window is staged once.
+    // (updated in place each round); the tile's element window is staged once
+    // per lane.
     constexpr int NR = NPT > 0 ? NPT : 1;
     Real rp[NR], rr[NR], rw[NR], rs[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) rp[k] = rr[k] = rw[k] = rs[k] = 0;
-    Real *LD = LR;  // resident: D^{-1} of the tile (the INIT window is free after FIRST)
-    Real *XCH = reinterpret_cast<Real *>(B.xch);
-    int ea_res = 0;
-    if constexpr (NPT > 0) {
-        const int a = min(rank * TS, C.Nn);
-        const int b = min(a + TS, C.Nn);
-        int elen = 0;
-        if (a < b) {
-            elem_window(C, a, b, ea_res, elen);
-            stage_elems(B, ea_res, elen, LK, LC);
-        }
-        lds_sync();
-    }
-    // boundary values of r, w, s for the neighbours' halos: the first H nodes
-    // of the tile go to side 0 (read by rank-1), the last H to side 1 (rank+1)
-    auto publish = [&](int id, int a, int b, Real r, Real w, Real sv, int par) {
-        const int off = id - a;
-        if (off < H && rank > 0) {
-            Real *base = XCH + (((size_t)blockIdx.x * 2 + par) * 2 + 0) * 3 * H;
-            stc(base + off, r);
-            stc(base + H + off, w);
-            stc(base + 2 * H + off, sv);
-        }
-        const int o2 = off - ((b - a) - H);
-        if (o2 >= 0 && rank < g - 1) {
-            Real *base = XCH + (((size_t)blockIdx.x * 2 + par) * 2 + 1) * 3 * H;
-            stc(base + o2, r);
-            stc(base + H + o2, w);
-            stc(base + 2 * H + o2, sv);
-        }
-    };
-    (void)publish;
+    Real *XCH = reinterpret_cast<Real *>(S.xch);
 
-    // phase timers of this lane (kept by thread 0 of rank 0, written to the trace)
+    // phase timers of the current lane (kept by thread 0 of rank 0, written to the trace)
     unsigned long long t_work = 0, t_bar = 0, t_red = 0, t_flag = 0;
     long long t_mark = now_ticks();
     const bool timer = (rank == 0 && threadIdx.x == 0);
-    auto barrier = [&](bool release) -> bool {
-        ++nbar;
-        const long long t0 = now_ticks();
-        const bool r = group_barrier(bar, nbar * (unsigned)g, ctl, tmo, release);
-        const long long t1 = now_ticks();
-        if (timer) {
-            t_work += t0 - t_mark;
-            t_bar += t1 - t0;
-            t_mark = t1;
-        }
-        return r;
-    };
-    auto mark_red = [&]() {
-        const long long t = now_ticks();
-        if (timer) {
-            t_red += t - t_mark;
-            t_mark = t;
-        }
-    };
-    auto waitf = [&](int idx) -> bool {
-        const long long t0 = now_ticks();
-        const bool r = wait_flag(B.flags, idx, I.epoch, ctl, tmo);
-        const long long t1 = now_ticks();
-        if (timer) {
-            t_work += t0 - t_mark;
-            t_flag += t1 - t0;
-            t_mark = t1;
-        }
-        return r;
-    };
     auto my_part = [&](int parity) { return part + ((size_t)parity * kMaxGroup + rank) * 4; };
     auto all_part = [&](int parity) { return part + (size_t)parity * kMaxGroup * 4; };
 
+    Control *ctl = S.ctl0;  // status block of the lane being run
     bool ok = true;
-    for (int li = 0; li < G.nlanes && ok; ++li) {
-        const int lane_id = G.lane0 + li;
-        const Lane L = B.lanes[lane_id];
+    for (int li = 0; ok; ++li) {
+        int lane_id;
+        if (G.queue < 0) {
+            if (li >= G.nlanes) break;
+            lane_id = G.lane0 + li;
+        } else {
+            // shared queue: the group leader takes the next position and the
+            // barrier hands it to the group's other workgroups
+            if (rank == 0 && threadIdx.x == 0)
+                stc(S.qslot + gid, (int)__hip_atomic_fetch_add(S.qhead + G.queue, 1u,
+                                                               __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT));
+            ++nbar;
+            ok = group_barrier(bar, nbar * (unsigned)g, ctl, S.timeout_ticks, false);
+            if (!ok) break;
+            const int pos = ldc(S.qslot + gid);
+            if (pos >= G.nlanes) break;
+            lane_id = G.lane0 + pos;
+        }
+        const Lane L = S.lanes[lane_id];
+        const EngineDesc &E = D[L.design];
+        const Consts &C = E.C;
+        const Bufs &B = E.B;
+        const LaunchInfo &I = E.I;
+        ctl = B.ctl;
+        const long long tmo = C.timeout_ticks;
+        const int H = C.W + 1;  // halo on each side of a tile window
+        const int TS = L.tile;
+        const int win = TS + 2 * H;
+        const int ewin = ((TS - 1) / C.W + 3) * C.EW;  // element window bound
+        double *LA = lds;        // window A (halo'd)
+        double *LB = lds + win;  // window B (INIT) / own residuals (ITER)
+        double *LK = lds + 2 * win;          // k/6 of the tile's elements
+        double *LC = lds + 2 * win + ewin;   // c hx hy/36 of the tile's elements
+        const int ntiles = (C.Nn + TS - 1) / TS;
+
+        double *X = group_vec(B, G.vec, V_X);
+        Real *P = reinterpret_cast<Real *>(group_vec(B, G.vec, V_P));
+        double *TP = group_vec(B, G.vec, V_TP);
+        double *TQ = group_vec(B, G.vec, V_TQ);
+        auto rv_ = [&](int which) { return reinterpret_cast<Real *>(group_vec(B, G.vec, which)); };
+        Real *Rb[2] = {rv_(V_R0), rv_(V_R1)};
+        Real *Wb[2] = {rv_(V_W0), rv_(V_W1)};
+        Real *Sb[2] = {rv_(V_S0), rv_(V_S1)};
+        Real *LZ = reinterpret_cast<Real *>(LA);  // z window of the CG rounds
+        Real *LR = reinterpret_cast<Real *>(LB);  // own residuals of the CG rounds
+        Real *LD = LR;  // resident: D^{-1} of the tile (the INIT window is free after FIRST)
+        int ea_res = 0;
+        if constexpr (NPT > 0) {
+            const int a = min(rank * TS, C.Nn);
+            const int b = min(a + TS, C.Nn);
+            int elen = 0;
+            lds_sync();
+            if (a < b) {
+                elem_window(C, a, b, ea_res, elen);
+                stage_elems(B, ea_res, elen, LK, LC);
+            }
+            lds_sync();
+        }
+        // boundary values of r, w, s for the neighbours' halos: the first H nodes
+        // of the tile go to side 0 (read by rank-1), the last H to side 1 (rank+1)
+        auto publish = [&](int id, int a, int b, Real r, Real w, Real sv, int par) {
+            const int off = id - a;
+            if (off < H && rank > 0) {
+                Real *base = XCH + (((size_t)blockIdx.x * 2 + par) * 2 + 0) * 3 * XS;
+                stc(base + off, r);
+                stc(base + XS + off, w);
+                stc(base + 2 * XS + off, sv);
+            }
+            const int o2 = off - ((b - a) - H);
+            if (o2 >= 0 && rank < g - 1) {
+                Real *base = XCH + (((size_t)blockIdx.x * 2 + par) * 2 + 1) * 3 * XS;
+                stc(base + o2, r);
+                stc(base + XS + o2, w);
+                stc(base + 2 * XS + o2, sv);
+            }
+        };
+        (void)publish;
+        auto barrier = [&](bool release) -> bool {
+            ++nbar;
+            const long long t0 = now_ticks();
+            const bool r = group_barrier(bar, nbar * (unsigned)g, ctl, tmo, release);
+            const long long t1 = now_ticks();
+            if (timer) {
+                t_work += t0 - t_mark;
+                t_bar += t1 - t0;
+                t_mark = t1;
+            }
+            return r;
+        };
+        auto mark_red = [&]() {
+            const long long t = now_ticks();
+            if (timer) {
+                t_red += t - t_mark;
+                t_mark = t;
+            }
+        };
+        auto waitf = [&](int idx) -> bool {
+            const long long t0 = now_ticks();
+            const bool r = wait_flag(B.flags, idx, I.epoch, ctl, tmo);
+            const long long t1 = now_ticks();
+            if (timer) {
+                t_work += t0 - t_mark;
+                t_flag += t1 - t0;
+                t_mark = t1;
+            }
+            return r;
+        };
+
         const bool is_adj = L.kind >= F_ADJ;
         const bool tracer = (rank == 0 && threadIdx.x == 0);
-        unsigned long long *trec = B.trace + (size_t)lane_id * B.trace_stride;
+        unsigned long long *trec = S.trace + (size_t)lane_id * S.trace_stride;
         unsigned long long iters_all = 0;
         const unsigned nbar0 = nbar;
         if (tracer) {
@@ -728,6 +788,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
             trec[TR_NWG] = g;
             trec[TR_TILE] = TS;
             trec[TR_START] = (unsigned long long)now_ticks();
+            t_mark = now_ticks();
         }
 
         Ctl c;
@@ -1061,10 +1122,10 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                             const int nb = left ? blockIdx.x - 1 : blockIdx.x + 1;
                             const int k = left ? q : q - H;
                             const Real *base =
-                                XCH + (((size_t)nb * 2 + ppar) * 2 + (left ? 1 : 0)) * 3 * H;
+                                XCH + (((size_t)nb * 2 + ppar) * 2 + (left ? 1 : 0)) * 3 * XS;
                             const Real rh = ldc(base + k);
-                            const Real wh = ldc(base + H + k);
-                            const Real sh = first ? (Real)0 : ldc(base + 2 * H + k);
+                            const Real wh = ldc(base + XS + k);
+                            const Real sh = first ? (Real)0 : ldc(base + 2 * XS + k);
                             const Real sv = first ? wh : wh + (Real)be * sh;
                             z = (Real)dinv[id] * (rh - (Real)al * sv);
                         }
@@ -1354,7 +1415,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
                         set_flag(B.flags, flag_index(FL_F, L.slice), I.epoch);
                 }
                 iters_all += c.iter;
-                if (tracer && c.step < B.trace_stride - TR_HDR)
+                if (tracer && c.step < S.trace_stride - TR_HDR)
                     trec[TR_HDR + c.step] = (unsigned long long)now_ticks();
                 c.step += 1;
                 c.phase = (c.step < c.nsteps) ? PH_INIT : PH_DONE;
@@ -1378,8 +1439,12 @@ __global__ void __launch_bounds__(kThreads) k_engine(Consts C, Bufs B, LaunchInf
     }
 }
 
-// After the primal engine: u_0 = 0, Theta, and the N_tau = 1 case.
-__global__ void k_finalize_fwd(Consts C, Bufs B, double *Theta_out) {
+// After the primal engine (blockIdx.y = design): u_0 = 0, Theta, and the
+// N_tau = 1 case.
+__global__ void k_finalize_fwd(const EngineDesc *__restrict__ D) {
+    const EngineDesc &E = D[blockIdx.y];
+    const Consts &C = E.C;
+    const Bufs &B = E.B;
     const size_t Nn = C.Nn;
     for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < Nn;
          id += (size_t)gridDim.x * blockDim.x) {
@@ -1390,14 +1455,17 @@ __global__ void k_finalize_fwd(Consts C, Bufs B, double *Theta_out) {
         B.out_th[0] = 0.0;
         if (C.Ntau == 1) B.out_th[1] = B.F_th[0];
         const double Th = B.out_th[C.Ntau];
-        *Theta_out = Th;
+        *B.Theta_out = Th;
         if (!(Th > 0.0) || !isfinite(Th)) atomicCAS(&B.ctl->status, 0, -5);
         B.ctl->fwd_done = 1;
     }
 }
 
-// After the adjoint engine: lambda for N_tau = 1.
-__global__ void k_finalize_adj(Consts C, Bufs B) {
+// After the adjoint engine (blockIdx.y = design): lambda for N_tau = 1.
+__global__ void k_finalize_adj(const EngineDesc *__restrict__ D) {
+    const EngineDesc &E = D[blockIdx.y];
+    const Consts &C = E.C;
+    const Bufs &B = E.B;
     const size_t Nn = C.Nn;
     if (C.Ntau == 1) {
         for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < Nn;
@@ -1412,12 +1480,46 @@ __global__ void k_finalize_adj(Consts C, Bufs B) {
     if (blockIdx.x == 0 && threadIdx.x == 0) B.ctl->adj_done = 1;
 }
 
-// grad_e = -(1/N_t) sum_n acc[n][e] - (1/N_tau) accG[e]  (Eq. 4.10 summed, Sec. 4.4 step 4)
-__global__ void k_sensitivities(Consts C, const double *acc, const double *accG, double *grad) {
+// grad_e = -(1/N_t) sum_n acc[n][e] - (1/N_tau) accG[e]  (Eq. 4.10 summed,
+// Sec. 4.4 step 4); blockIdx.y = design.
+__global__ void k_sensitivities(const EngineDesc *__restrict__ D) {
+    const EngineDesc &E = D[blockIdx.y];
+    const Consts &C = E.C;
+    const Bufs &B = E.B;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < C.Ne; e += gridDim.x * blockDim.x) {
         double s = 0.0;
-        for (int n = 0; n < C.Ntau; ++n) s += acc[(size_t)n * C.Ne + e];
-        grad[e] = -s / (double)C.Nt - accG[e] / (double)C.Ntau;
+        for (int n = 0; n < C.Ntau; ++n) s += B.acc[(size_t)n * C.Ne + e];
+        B.grad[e] = -s / (double)C.Nt - B.accG[e] / (double)C.Ntau;
+    }
+}
+
+// Keeps a design's corrected u^{k+1} and lambda^{k+1} as its next guesses
+// (warm restart of Alg. 3); blockIdx.y = design.
+__global__ void k_save_guess(const EngineDesc *__restrict__ D) {
+    const EngineDesc &E = D[blockIdx.y];
+    const Consts &C = E.C;
+    const Bufs &B = E.B;
+    const size_t n = (size_t)(C.Ntau + 1) * C.Nn;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x) {
+        B.save_T[t] = B.out_T[t];
+        B.save_L[t] = B.out_L[t];
+    }
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k <= C.Ntau; k += blockDim.x) B.save_th[k] = B.out_th[k];
+}
+
+// Copies n descriptors given by value into device memory (n <= kDescPerCopy).
+constexpr int kDescPerCopy = 4;
+struct DescChunk {
+    EngineDesc d[kDescPerCopy];
+};
+__global__ void k_put_desc(DescChunk chunk, int n, EngineDesc *dst) {
+    const int words = (int)(sizeof(EngineDesc) / sizeof(unsigned));
+    for (int k = 0; k < n; ++k) {
+        const unsigned *src = reinterpret_cast<const unsigned *>(&chunk.d[k]);
+        unsigned *out = reinterpret_cast<unsigned *>(dst + k);
+        for (int w = threadIdx.x; w < words; w += blockDim.x) out[w] = src[w];
     }
 }
 

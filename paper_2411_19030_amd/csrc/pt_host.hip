@@ -1,10 +1,12 @@
 // Host side of libpt: argument checks, workspace layout, lane planning and the
-// stream-ordered launches of one forward / adjoint / sensitivity call.
+// stream-ordered launches of the single-design calls (forward / adjoint /
+// sensitivities) and of the multi-design cycle.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <numeric>
 #include <vector>
 
 #include "../../include/pt.h"
@@ -15,17 +17,18 @@ using namespace pt;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxGrid = 1024;         // workgroups of one engine launch
+constexpr int kMaxBatchGroups = 512;   // worker groups of a multi-design launch
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-struct Layout {
-    size_t ctl, bar, flags, partials, wg_group, groups, lanes, FL;
-    size_t kq, cm, dk, dc, dinv_f, dinv_c, mask, qt, zero;
-    size_t Gk, Gn, Gk_th, Gn_th, F_th, Uprev, Uprev_th, Ubuf, Ubuf_th, Lprev, Lbuf;
-    size_t acc, accG, pool, trace, xch;
-    size_t total;
-    int trace_stride;
-    int max_lanes, max_grid;
+struct Carver {
+    size_t o = 0;
+    size_t take(size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    }
 };
 
 bool valid_problem(const pt_problem *p) {
@@ -55,55 +58,132 @@ bool valid_problem(const pt_problem *p) {
     return true;
 }
 
-Layout layout(const pt_problem *p) {
-    Layout L{};
+// ---------------------------------------------------------------------------
+// Workspace layout
+// ---------------------------------------------------------------------------
+
+// Arrays of one design.
+struct DesignLayout {
+    size_t ctl, FL, kq, cm, dk, dc, dinv_f, dinv_c, mask, qt, zero;
+    size_t Gk, Gn, Gk_th, Gn_th, F_th, Uprev, Uprev_th, Ubuf, Ubuf_th, acc, accG;
+    // multi-design cycles keep the cycle's state here
+    size_t S, uT, uth, lam, gT, gth, gL;
+};
+
+void carve_design(Carver &c, const pt_problem *p, DesignLayout &L, bool batched) {
     const size_t Nn = (size_t)(p->nx + 1) * (p->ny + 1);
     const size_t Ne = (size_t)p->nx * p->ny;
     const size_t EP = (size_t)(p->nx + 2) * (p->ny + 2);
     const size_t Nt1 = (size_t)p->n_slices + 1;
-    L.max_lanes = 2 * p->n_slices + 2;
-    L.max_grid = 1024;
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-        size_t at = o;
-        o = align_up(o + bytes);
-        return at;
-    };
-    L.ctl = take(sizeof(Control));
-    L.bar = take(sizeof(unsigned) * kMaxLanes);
-    L.flags = take(sizeof(unsigned) * kMaxFlags);
-    L.partials = take(sizeof(double) * (size_t)L.max_lanes * 2 * kMaxGroup * 4);
-    L.wg_group = take(sizeof(int) * L.max_grid);
-    L.groups = take(sizeof(Group) * kMaxLanes);
-    L.lanes = take(sizeof(Lane) * L.max_lanes);
-    L.FL = take(sizeof(double) * Nt1 * Nn);
-    L.kq = take(sizeof(double) * EP);
-    L.cm = take(sizeof(double) * EP);
-    L.dk = take(sizeof(double) * Ne);
-    L.dc = take(sizeof(double) * Ne);
-    L.dinv_f = take(sizeof(double) * Nn);
-    L.dinv_c = take(sizeof(double) * Nn);
-    L.mask = take(Nn);
-    L.qt = take(sizeof(double) * (p->n_steps + 1));
-    L.zero = take(sizeof(double) * Nn);
-    L.Gk = take(sizeof(double) * Nt1 * Nn);
-    L.Gn = take(sizeof(double) * Nt1 * Nn);
-    L.Gk_th = take(sizeof(double) * Nt1);
-    L.Gn_th = take(sizeof(double) * Nt1);
-    L.F_th = take(sizeof(double) * Nt1);
-    L.Uprev = take(sizeof(double) * Nt1 * Nn);
-    L.Uprev_th = take(sizeof(double) * Nt1);
-    L.Ubuf = take(sizeof(double) * Nt1 * Nn);
-    L.Ubuf_th = take(sizeof(double) * Nt1);
-    L.Lprev = L.Uprev;  // adjoint reuses the primal scratch
-    L.Lbuf = L.Ubuf;
-    L.acc = take(sizeof(double) * (size_t)p->n_slices * Ne);
-    L.accG = take(sizeof(double) * Ne);
-    L.pool = take(sizeof(double) * (size_t)L.max_lanes * kVecsPerLane * Nn);
-    L.trace_stride = TR_HDR + std::max(p->n_steps / p->n_slices, p->n_slices);
-    L.trace = take(sizeof(unsigned long long) * (size_t)L.max_lanes * L.trace_stride);
-    L.xch = take(sizeof(double) * (size_t)L.max_grid * 12 * (p->nx + 2));
-    L.total = o;
+    const size_t d = sizeof(double);
+    L.ctl = c.take(sizeof(Control));
+    L.FL = c.take(d * Nt1 * Nn);
+    L.kq = c.take(d * EP);
+    L.cm = c.take(d * EP);
+    L.dk = c.take(d * Ne);
+    L.dc = c.take(d * Ne);
+    L.dinv_f = c.take(d * Nn);
+    L.dinv_c = c.take(d * Nn);
+    L.mask = c.take(Nn);
+    L.qt = c.take(d * (p->n_steps + 1));
+    L.zero = c.take(d * Nn);
+    L.Gk = c.take(d * Nt1 * Nn);
+    L.Gn = c.take(d * Nt1 * Nn);
+    L.Gk_th = c.take(d * Nt1);
+    L.Gn_th = c.take(d * Nt1);
+    L.F_th = c.take(d * Nt1);
+    L.acc = c.take(d * (size_t)p->n_slices * Ne);
+    L.accG = c.take(d * Ne);
+    if (!batched) {
+        L.Uprev = c.take(d * Nt1 * Nn);
+        L.Uprev_th = c.take(d * Nt1);
+        L.Ubuf = c.take(d * Nt1 * Nn);
+        L.Ubuf_th = c.take(d * Nt1);
+    } else {
+        L.S = c.take(d * (size_t)p->n_steps * Nn);
+        L.uT = c.take(d * Nt1 * Nn);
+        L.uth = c.take(d * Nt1);
+        L.lam = c.take(d * Nt1 * Nn);
+        L.gT = c.take(d * Nt1 * Nn);
+        L.gth = c.take(d * Nt1);
+        L.gL = c.take(d * Nt1 * Nn);
+    }
+}
+
+// Launch-wide arrays of an engine launch.
+struct SharedLayout {
+    size_t desc, bar, flags, partials, wg_group, groups, lanes, qhead, qslot, pool, trace, xch;
+    int max_lanes, max_groups, trace_stride, xch_stride;
+    size_t pool_stride;
+};
+
+void carve_shared(Carver &c, SharedLayout &S, int n_designs, int max_lanes, int max_groups,
+                  size_t pool_stride, int trace_stride, int xch_stride) {
+    S.max_lanes = max_lanes;
+    S.max_groups = max_groups;
+    S.trace_stride = trace_stride;
+    S.xch_stride = xch_stride;
+    S.pool_stride = pool_stride;
+    S.desc = c.take(sizeof(EngineDesc) * n_designs);
+    S.bar = c.take(sizeof(unsigned) * kMaxGroups);
+    S.flags = c.take(sizeof(unsigned) * kMaxFlags * (size_t)n_designs);
+    S.partials = c.take(sizeof(double) * (size_t)max_groups * 2 * kMaxGroup * 4);
+    S.wg_group = c.take(sizeof(int) * kMaxGrid);
+    S.groups = c.take(sizeof(Group) * kMaxGroups);
+    S.lanes = c.take(sizeof(Lane) * (size_t)max_lanes);
+    S.qhead = c.take(sizeof(unsigned) * 2);
+    S.qslot = c.take(sizeof(int) * kMaxGroups);
+    S.pool = c.take(sizeof(double) * (size_t)max_groups * kVecsPerLane * pool_stride);
+    S.trace = c.take(sizeof(unsigned long long) * (size_t)max_lanes * trace_stride);
+    S.xch = c.take(sizeof(double) * (size_t)kMaxGrid * 12 * xch_stride);
+}
+
+int trace_stride_of(const pt_problem *p) {
+    return TR_HDR + std::max(p->n_steps / p->n_slices, p->n_slices);
+}
+
+// Single-design workspace: the design's status block comes first (offset 0).
+struct Layout {
+    DesignLayout d;
+    SharedLayout s;
+    size_t total;
+};
+
+Layout layout(const pt_problem *p) {
+    Layout L{};
+    Carver c;
+    carve_design(c, p, L.d, false);
+    const int max_lanes = 2 * p->n_slices + 2;
+    carve_shared(c, L.s, 1, max_lanes, max_lanes, (size_t)(p->nx + 1) * (p->ny + 1),
+                 trace_stride_of(p), p->nx + 2);
+    L.total = c.o;
+    return L;
+}
+
+// Multi-design workspace.
+struct BatchLayout {
+    std::vector<DesignLayout> d;
+    SharedLayout s;
+    size_t total;
+    size_t max_nn;
+};
+
+BatchLayout batch_layout(int n, const pt_problem *probs) {
+    BatchLayout L{};
+    L.d.resize(n);
+    Carver c;
+    int lanes = 0, tstride = TR_HDR, xs = 2;
+    size_t max_nn = 1;
+    for (int k = 0; k < n; ++k) {
+        carve_design(c, &probs[k], L.d[k], true);
+        lanes += 2 * probs[k].n_slices + 2;
+        tstride = std::max(tstride, trace_stride_of(&probs[k]));
+        xs = std::max(xs, probs[k].nx + 2);
+        max_nn = std::max(max_nn, (size_t)(probs[k].nx + 1) * (probs[k].ny + 1));
+    }
+    carve_shared(c, L.s, n, lanes, kMaxBatchGroups, max_nn, tstride, xs);
+    L.max_nn = max_nn;
+    L.total = c.o;
     return L;
 }
 
@@ -147,6 +227,15 @@ Consts make_consts(const pt_problem *p) {
     if (const char *e = getenv("PT_WAIT_TIMEOUT_S")) tmo = atof(e);
     if (!(tmo > 0.0)) tmo = 20.0;
     C.timeout_ticks = (long long)(tmo * 1e8);
+    C.k0 = p->k0;
+    C.kmin = p->kmin;
+    C.pk = p->pk;
+    C.c0 = p->c0;
+    C.cmin = p->cmin;
+    C.pc = p->pc;
+    C.q = p->q;
+    C.bc_rule = p->bc;
+    C.has_qt = p->q_t ? 1 : 0;
     return C;
 }
 
@@ -155,17 +244,13 @@ T *at(void *ws, size_t off) {
     return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
 }
 
-Bufs make_bufs(void *ws, const Layout &L) {
+Bufs make_bufs(void *ws, const DesignLayout &L, const SharedLayout &S, int design) {
     Bufs B{};
     B.ctl = at<Control>(ws, L.ctl);
-    B.bar = at<unsigned>(ws, L.bar);
-    B.flags = at<unsigned>(ws, L.flags);
-    B.partials = at<double>(ws, L.partials);
-    B.wg_group = at<int>(ws, L.wg_group);
-    B.groups = at<Group>(ws, L.groups);
-    B.lanes = at<Lane>(ws, L.lanes);
+    B.flags = at<unsigned>(ws, S.flags) + (size_t)design * kMaxFlags;
+    B.pool = at<double>(ws, S.pool);
+    B.pool_stride = S.pool_stride;
     B.FL = at<double>(ws, L.FL);
-    B.pool = at<double>(ws, L.pool);
     B.kq = at<double>(ws, L.kq);
     B.cm = at<double>(ws, L.cm);
     B.dk = at<double>(ws, L.dk);
@@ -182,10 +267,25 @@ Bufs make_bufs(void *ws, const Layout &L) {
     B.F_th = at<double>(ws, L.F_th);
     B.acc = at<double>(ws, L.acc);
     B.accG = at<double>(ws, L.accG);
-    B.trace = at<unsigned long long>(ws, L.trace);
-    B.xch = at<double>(ws, L.xch);
-    B.trace_stride = L.trace_stride;
     return B;
+}
+
+Launch make_launch(void *ws, const SharedLayout &S, Control *ctl0, long long timeout_ticks) {
+    Launch X{};
+    X.wg_group = at<int>(ws, S.wg_group);
+    X.groups = at<Group>(ws, S.groups);
+    X.lanes = at<Lane>(ws, S.lanes);
+    X.bar = at<unsigned>(ws, S.bar);
+    X.partials = at<double>(ws, S.partials);
+    X.xch = at<double>(ws, S.xch);
+    X.xch_stride = S.xch_stride;
+    X.qhead = at<unsigned>(ws, S.qhead);
+    X.qslot = at<int>(ws, S.qslot);
+    X.trace = at<unsigned long long>(ws, S.trace);
+    X.trace_stride = S.trace_stride;
+    X.ctl0 = ctl0;
+    X.timeout_ticks = timeout_ticks;
+    return X;
 }
 
 int hip_ok(hipError_t e) { return e == hipSuccess ? PT_OK : PT_EHIP; }
@@ -198,48 +298,51 @@ int hip_ok(hipError_t e) { return e == hipSuccess ? PT_OK : PT_EHIP; }
 
 int launch_check() { return hip_ok(hipGetLastError()); }
 
-// Plan of one engine launch, built on the host and passed as a kernel
-// argument (so no host buffer must outlive the call). Groups come in runs of
-// identical shape: group r of a run gets the lanes with slices
-// s0 + r*gstride + k*lstride, k = 0..nlanes-1, kept if within [smin, smax].
-struct Run {
-    int kind, ngroups, nwg, tile, s0, gstride, lstride, nlanes, smin, smax;
-};
+bool capturing(hipStream_t stream) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return false;
+    return cs != hipStreamCaptureStatusNone;
+}
 
-struct PlanArgs {
-    int grid;
-    int nruns;
-    Run run[6];
-};
-
-__global__ void k_build_plan(PlanArgs P, Group *groups, Lane *lanes, int *wg_group) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    int gidx = 0, lidx = 0, w = 0;
-    for (int r = 0; r < P.nruns; ++r) {
-        const Run R = P.run[r];
-        for (int q = 0; q < R.ngroups; ++q) {
-            Group G;
-            G.wg0 = w;
-            G.nwg = R.nwg;
-            G.tile = R.tile;
-            G.vec = gidx;
-            G.lane0 = lidx;
-            int n = 0;
-            for (int k = 0; k < R.nlanes; ++k) {
-                const int sl = R.s0 + q * R.gstride + k * R.lstride;
-                if (sl < R.smin || sl > R.smax) continue;
-                lanes[lidx + n].kind = R.kind;
-                lanes[lidx + n].slice = sl;
-                ++n;
-            }
-            G.nlanes = n;
-            lidx += n;
-            groups[gidx] = G;
-            for (int k = 0; k < R.nwg; ++k) wg_group[w++] = gidx;
-            ++gidx;
-        }
+// Writes host descriptors to device memory with by-value kernel arguments (so
+// the upload is stream-ordered and can be captured in a graph).
+int upload_descs(const std::vector<EngineDesc> &hd, EngineDesc *dst, hipStream_t stream) {
+    for (size_t k = 0; k < hd.size(); k += kDescPerCopy) {
+        DescChunk ch;
+        memset(&ch, 0, sizeof(ch));
+        const int m = (int)std::min<size_t>(kDescPerCopy, hd.size() - k);
+        for (int q = 0; q < m; ++q) ch.d[q] = hd[k + q];
+        hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(256), 0, stream, ch, m, dst + k);
+        PT_TRY(launch_check());
     }
-    for (; w < P.grid; ++w) wg_group[w] = -1;
+    return PT_OK;
+}
+
+// Per-design host copies (caller mask, q(t)), then material and diagonals of
+// every design of D. Host copies cannot be captured in a graph.
+int setup_designs(int n, const pt_problem *probs, const std::vector<EngineDesc> &hd,
+                  EngineDesc *D, int keep_markers, hipStream_t stream) {
+    hipLaunchKernelGGL(k_reset_ctl, dim3(n), dim3(64), 0, stream, D, keep_markers);
+    PT_TRY(launch_check());
+    bool copied = false;
+    for (int k = 0; k < n; ++k) {
+        const pt_problem *p = &probs[k];
+        if (p->bc == PT_BC_MASK || p->q_t) {
+            if (capturing(stream)) return PT_EINVAL;
+            copied = true;
+        }
+        if (p->bc == PT_BC_MASK)
+            PT_TRY(hip_ok(hipMemcpyAsync(hd[k].B.mask, p->dirichlet_mask, (size_t)hd[k].C.Nn,
+                                         hipMemcpyHostToDevice, stream)));
+        if (p->q_t)
+            PT_TRY(hip_ok(hipMemcpyAsync(hd[k].B.qt, p->q_t, sizeof(double) * (p->n_steps + 1),
+                                         hipMemcpyHostToDevice, stream)));
+    }
+    // the caller's host arrays may be released once the call returns
+    if (copied) PT_TRY(hip_ok(hipStreamSynchronize(stream)));
+    hipLaunchKernelGGL(k_setup_design, dim3(256, n), dim3(256), 0, stream, D);
+    hipLaunchKernelGGL(k_diag, dim3(256, n), dim3(256), 0, stream, D);
+    return launch_check();
 }
 
 struct Device {
@@ -272,13 +375,127 @@ size_t engine_lds_doubles(int ts, int W) {
     return 2 * ((size_t)ts + 2 * H) + 2 * ((size_t)(ts - 1) / W + 3) * (W + 1);
 }
 
-int tile_for(int Nn, int nwg, int H, int lds_cap_doubles) {
+int lds_cap_doubles(const Device &dev) {
+    return (std::min(dev.lds_max, 160 * 1024) - 1024) / 8;
+}
+
+// Streaming-mode tile: the group's share of the nodes, cut to what fits LDS.
+int tile_for(int Nn, int nwg, int H, int cap_doubles) {
     int ts = (Nn + nwg - 1) / nwg;
     ts = (ts + 255) / 256 * 256;
-    while (ts > 256 && engine_lds_doubles(ts, H - 1) > (size_t)lds_cap_doubles) ts -= 256;
+    while (ts > 256 && engine_lds_doubles(ts, H - 1) > (size_t)cap_doubles) ts -= 256;
     ts = std::min(ts, std::max(256, env_int("PT_TILE_MAX", 4096)));
     ts = std::max(ts, 256);
     return ts;
+}
+
+const void *engine_kernel(bool fp32, int npt) {
+    if (fp32)
+        return npt == 0   ? (const void *)k_engine<0, float>
+               : npt == 1 ? (const void *)k_engine<1, float>
+               : npt == 2 ? (const void *)k_engine<2, float>
+               : npt == 4 ? (const void *)k_engine<4, float>
+                          : (const void *)k_engine<8, float>;
+    return npt == 0   ? (const void *)k_engine<0, double>
+           : npt == 1 ? (const void *)k_engine<1, double>
+           : npt == 2 ? (const void *)k_engine<2, double>
+           : npt == 4 ? (const void *)k_engine<4, double>
+                      : (const void *)k_engine<8, double>;
+}
+
+// Workgroups of the engine that fit on the device at once.
+int engine_capacity(bool fp32, int npt, size_t lds_bytes, const Device &dev, int &cap) {
+    const void *kern = engine_kernel(fp32, npt);
+    PT_TRY(hip_ok(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds_bytes)));
+    int occ = 0;
+    PT_TRY(hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, lds_bytes)));
+    cap = occ * dev.cus;
+    return PT_OK;
+}
+
+// One persistent launch of the engine. Every workgroup must be resident at
+// once (groups spin on each other): the grid is checked against the
+// occupancy bound, and the launch is cooperative unless the stream is being
+// captured into a graph, where a plain launch of the same checked grid is used.
+int launch_engine(bool fp32, int npt, const EngineDesc *D, const Launch &X, int grid,
+                  size_t lds_bytes, const Device &dev, hipStream_t stream) {
+    int cap = 0;
+    PT_TRY(engine_capacity(fp32, npt, lds_bytes, dev, cap));
+    if (cap < grid || grid > kMaxGrid) return PT_EHIP;
+    const void *kern = engine_kernel(fp32, npt);
+    Launch Xv = X;
+    const EngineDesc *Dv = D;
+    void *args[] = {(void *)&Dv, (void *)&Xv};
+    if (capturing(stream))
+        PT_TRY(hip_ok(hipLaunchKernel(kern, dim3(grid), dim3(kThreads), args, (unsigned)lds_bytes,
+                                      stream)));
+    else
+        PT_TRY(hip_ok(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kThreads), args,
+                                                 (unsigned)lds_bytes, stream)));
+    return launch_check();
+}
+
+int reset_launch_state(void *ws, const SharedLayout &S, int n_designs, hipStream_t stream) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream, at<unsigned>(ws, S.bar),
+                       (size_t)kMaxGroups, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream, at<unsigned>(ws, S.flags),
+                       (size_t)kMaxFlags * n_designs, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, at<unsigned>(ws, S.qhead),
+                       (size_t)2, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream,
+                       at<unsigned>(ws, S.trace), (size_t)S.max_lanes * S.trace_stride * 2, 0u);
+    return launch_check();
+}
+
+// ---------------------------------------------------------------------------
+// Single-design plan: groups with private lane lists
+// ---------------------------------------------------------------------------
+
+// Groups come in runs of identical shape: group r of a run gets the lanes
+// with slices s0 + r*gstride + k*lstride, k = 0..nlanes-1, kept if within
+// [smin, smax]. Built on the device from this kernel argument, so no host
+// buffer must outlive the call.
+struct Run {
+    int kind, ngroups, nwg, tile, s0, gstride, lstride, nlanes, smin, smax;
+};
+
+struct PlanArgs {
+    int grid;
+    int nruns;
+    Run run[6];
+};
+
+__global__ void k_build_plan(PlanArgs P, Group *groups, Lane *lanes, int *wg_group) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int gidx = 0, lidx = 0, w = 0;
+    for (int r = 0; r < P.nruns; ++r) {
+        const Run R = P.run[r];
+        for (int q = 0; q < R.ngroups; ++q) {
+            Group G;
+            G.wg0 = w;
+            G.nwg = R.nwg;
+            G.vec = gidx;
+            G.queue = -1;
+            G.lane0 = lidx;
+            int n = 0;
+            for (int k = 0; k < R.nlanes; ++k) {
+                const int sl = R.s0 + q * R.gstride + k * R.lstride;
+                if (sl < R.smin || sl > R.smax) continue;
+                lanes[lidx + n].kind = R.kind;
+                lanes[lidx + n].slice = sl;
+                lanes[lidx + n].design = 0;
+                lanes[lidx + n].tile = R.tile;
+                ++n;
+            }
+            G.nlanes = n;
+            lidx += n;
+            groups[gidx] = G;
+            for (int k = 0; k < R.nwg; ++k) wg_group[w++] = gidx;
+            ++gidx;
+        }
+    }
+    for (; w < P.grid; ++w) wg_group[w] = -1;
 }
 
 // One kind of lane and how its lanes are queued on groups.
@@ -292,14 +509,13 @@ struct LanePlan {
     int queues = 0;   // groups (0: one lane per group)
 };
 
-// Runs one engine launch.
-int run_engine(const Consts &C, Bufs B, const LaunchInfo &I, std::vector<LanePlan> &plans,
-               void *ws, const Layout &Lay, hipStream_t stream) {
+// Runs one single-design engine launch with descriptor D (already uploaded).
+int run_engine(const Consts &C, const EngineDesc *D, std::vector<LanePlan> &plans, void *ws,
+               const Layout &Lay, Control *ctl, hipStream_t stream) {
     Device dev;
     PT_TRY(device_info(dev));
     const int H = C.W + 1;
-    const int lds_cap = std::min(dev.lds_max, 160 * 1024) - 1024;
-    const int lds_cap_d = lds_cap / 8;
+    const int lds_cap_d = lds_cap_doubles(dev);
     int grid = dev.cus * std::max(1, env_int("PT_WG_PER_CU", 1));
     const int sweep_wgs = env_int("PT_SWEEP_WGS", 32);
 
@@ -316,7 +532,6 @@ int run_engine(const Consts &C, Bufs B, const LaunchInfo &I, std::vector<LanePla
     if (resident) {
         // one tile of <= NT*npt nodes per workgroup; every group holds a whole lane
         int lat_wgs = 0;
-        double wF = 0.0;
         int nq = 0;
         for (size_t k = 0; k < plans.size(); ++k) {
             auto &p = plans[k];
@@ -327,7 +542,6 @@ int run_engine(const Consts &C, Bufs B, const LaunchInfo &I, std::vector<LanePla
                 lat_wgs += nwg[k] * p.count;
             } else {
                 nwg[k] = g_min;
-                wF += p.weight * p.count;
                 ++nq;
             }
         }
@@ -384,7 +598,7 @@ int run_engine(const Consts &C, Bufs B, const LaunchInfo &I, std::vector<LanePla
             if (p.latency) fixed += std::max(1, std::min(sweep_wgs, grid / 2)) * q;
             else wsum += p.weight * per_group[k] * q;
         }
-        if (total_groups > kMaxLanes) return PT_EINVAL;
+        if (total_groups > Lay.s.max_groups) return PT_EINVAL;
         if (total_groups > grid) grid = total_groups;
         const int rest = std::max(grid - fixed, 0);
         for (size_t k = 0; k < plans.size(); ++k) {
@@ -401,9 +615,9 @@ int run_engine(const Consts &C, Bufs B, const LaunchInfo &I, std::vector<LanePla
         total_groups += ngroups[k];
         max_tile = std::max(max_tile, tile[k]);
     }
-    if (total_groups > kMaxLanes) return PT_EINVAL;
+    if (total_groups > Lay.s.max_groups) return PT_EINVAL;
     if (used > grid) grid = used;
-    if (grid > Lay.max_grid) return PT_EINVAL;
+    if (grid > kMaxGrid) return PT_EINVAL;
     int npt = 0;
     if (resident) {
         npt = 1;
@@ -431,71 +645,12 @@ int run_engine(const Consts &C, Bufs B, const LaunchInfo &I, std::vector<LanePla
         R.smin = std::min(p.slice0, p.slice0 + p.dir * (p.count - 1));
         R.smax = std::max(p.slice0, p.slice0 + p.dir * (p.count - 1));
     }
-    hipLaunchKernelGGL(k_build_plan, dim3(1), dim3(64), 0, stream, P, at<Group>(ws, Lay.groups),
-                       at<Lane>(ws, Lay.lanes), at<int>(ws, Lay.wg_group));
+    hipLaunchKernelGGL(k_build_plan, dim3(1), dim3(64), 0, stream, P, at<Group>(ws, Lay.s.groups),
+                       at<Lane>(ws, Lay.s.lanes), at<int>(ws, Lay.s.wg_group));
     PT_TRY(launch_check());
-    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream, B.bar, (size_t)kMaxLanes, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream, B.flags, (size_t)kMaxFlags, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream, (unsigned *)B.trace,
-                       (size_t)Lay.max_lanes * Lay.trace_stride * 2, 0u);
-    PT_TRY(launch_check());
-
-    const void *kern;
-    if (C.fp32)
-        kern = npt == 0   ? (const void *)k_engine<0, float>
-               : npt == 1 ? (const void *)k_engine<1, float>
-               : npt == 2 ? (const void *)k_engine<2, float>
-               : npt == 4 ? (const void *)k_engine<4, float>
-                          : (const void *)k_engine<8, float>;
-    else
-        kern = npt == 0   ? (const void *)k_engine<0, double>
-               : npt == 1 ? (const void *)k_engine<1, double>
-               : npt == 2 ? (const void *)k_engine<2, double>
-               : npt == 4 ? (const void *)k_engine<4, double>
-                          : (const void *)k_engine<8, double>;
-    PT_TRY(hip_ok(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)lds_bytes)));
-    int occ = 0;
-    PT_TRY(hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, lds_bytes)));
-    if ((long long)occ * dev.cus < grid) return PT_EHIP;
-    void *args[] = {(void *)&C, (void *)&B, (void *)&I};
-    PT_TRY(hip_ok(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kThreads), args,
-                                             (unsigned)lds_bytes, stream)));
-    return launch_check();
-}
-
-int setup_design(const pt_problem *p, const Consts &C, const Bufs &B, const double *rho,
-                 void *ws, const Layout &Lay, hipStream_t stream) {
-    const int blocks = 512;
-    // Dirichlet mask
-    if (p->bc == PT_BC_MASK) {
-        PT_TRY(hip_ok(hipMemcpyAsync(at<unsigned char>(ws, Lay.mask), p->dirichlet_mask,
-                                     (size_t)C.Nn, hipMemcpyHostToDevice, stream)));
-        PT_TRY(hip_ok(hipStreamSynchronize(stream)));
-    } else {
-        const int rule = p->bc == PT_BC_LEFT_CENTRE ? 0 : (p->bc == PT_BC_BOTTOM_CENTRE ? 1 : 2);
-        hipLaunchKernelGGL(k_mask_rule, dim3(blocks), dim3(256), 0, stream, C, rule,
-                           at<unsigned char>(ws, Lay.mask));
-    }
-    // source history
-    if (p->q_t) {
-        PT_TRY(hip_ok(hipMemcpyAsync(at<double>(ws, Lay.qt), p->q_t,
-                                     sizeof(double) * (p->n_steps + 1), hipMemcpyHostToDevice,
-                                     stream)));
-        PT_TRY(hip_ok(hipStreamSynchronize(stream)));
-    } else {
-        hipLaunchKernelGGL(k_fill_f64, dim3(8), dim3(256), 0, stream, at<double>(ws, Lay.qt),
-                           (size_t)(p->n_steps + 1), p->q);
-    }
-    hipLaunchKernelGGL(k_fill_f64, dim3(blocks), dim3(256), 0, stream, at<double>(ws, Lay.zero),
-                       (size_t)C.Nn, 0.0);
-    hipLaunchKernelGGL(k_material, dim3(blocks), dim3(256), 0, stream, C, rho,
-                       at<double>(ws, Lay.kq), at<double>(ws, Lay.cm), at<double>(ws, Lay.dk),
-                       at<double>(ws, Lay.dc), p->k0, p->kmin, p->pk, p->c0, p->cmin, p->pc,
-                       B.ctl);
-    hipLaunchKernelGGL(k_diag, dim3(blocks), dim3(256), 0, stream, C, B.kq, B.cm, B.mask,
-                       at<double>(ws, Lay.dinv_f), at<double>(ws, Lay.dinv_c));
-    return launch_check();
+    PT_TRY(reset_launch_state(ws, Lay.s, 1, stream));
+    const Launch X = make_launch(ws, Lay.s, ctl, C.timeout_ticks);
+    return launch_engine(C.fp32 != 0, npt, D, X, grid, lds_bytes, dev, stream);
 }
 
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
@@ -504,18 +659,194 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
     return pa < pb + nb && pb < pa + na;
 }
 
-__global__ void k_reset_ctl(Control *ctl, int keep_markers) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const int f = ctl->fwd_done, a = ctl->adj_done;
-        ctl->status = 0;
-        ctl->abort = 0;
-        ctl->max_iters = 0;
-        ctl->iters_fine = ctl->iters_coarse = ctl->solves_fine = ctl->solves_coarse = 0;
-        ctl->max_relres_bits = 0;
-        ctl->fwd_done = keep_markers ? f : 0;
-        ctl->adj_done = 0;
-        (void)a;
+// ---------------------------------------------------------------------------
+// Multi-design plan: worker groups sharing two lane queues
+// ---------------------------------------------------------------------------
+
+// Lanes of every design (blockIdx.x = design) in queue order. Queue 0 holds
+// the fine lanes F_n interleaved with the batched coarse lanes G(u^k_n) in the
+// order the design's sweep consumes them; queue 1 holds the cold sweeps of all
+// designs, then their correction sweeps. With designs in the order the host
+// chose, the lanes have a global order (all cold sweeps; then per design its
+// fine lanes and its correction sweep) that both queues follow and in which
+// every lane waits only on earlier lanes; as each queue hands out lanes in
+// that order, a waiting lane's producers have all been taken by running
+// groups, so the launch cannot deadlock.
+__global__ void k_build_lanes(const EngineDesc *__restrict__ D, Lane *lanes) {
+    if (threadIdx.x != 0) return;
+    const int d = blockIdx.x;
+    const EngineDesc &E = D[d];
+    const DesignPlan &P = E.plan;
+    const int Ntau = E.C.Ntau;
+    const bool gk = E.I.gk_lanes != 0;
+    int k = P.q0_lane0;
+    auto put = [&](int pos, int kind, int slice, int tile) {
+        lanes[pos].kind = kind;
+        lanes[pos].slice = slice;
+        lanes[pos].design = d;
+        lanes[pos].tile = tile;
+    };
+    if (!P.adjoint) {
+        for (int n = 0; n < Ntau; ++n) {
+            put(k++, F_PRI, n, P.tile0);
+            if (gk && n >= 1) put(k++, GK_PRI, n, P.tile0);
+        }
+    } else {
+        for (int n = Ntau; n >= 1; --n) {
+            put(k++, F_ADJ, n, P.tile0);
+            if (gk && n <= Ntau - 1) put(k++, GK_ADJ, n, P.tile0);
+        }
     }
+    if (P.q1_cold >= 0) put(P.q1_cold, P.adjoint ? COLD_ADJ : COLD_PRI, 0, P.tile1);
+    if (P.q1_sweep >= 0) put(P.q1_sweep, P.adjoint ? SWEEP_ADJ : SWEEP_PRI, 0, P.tile1);
+}
+
+struct GroupArgs {
+    int grid;
+    int n0, wgs0, lane0_0, nlanes0;  // queue 0 workers
+    int n1, wgs1, lane0_1, nlanes1;  // queue 1 workers
+};
+
+__global__ void k_build_groups(GroupArgs A, Group *groups, int *wg_group) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int w = 0, gidx = 0;
+    // sweep workers first: their lanes are the longest sequential chains
+    for (int q = 0; q < A.n1; ++q, ++gidx) {
+        Group G;
+        G.wg0 = w;
+        G.nwg = A.wgs1;
+        G.lane0 = A.lane0_1;
+        G.nlanes = A.nlanes1;
+        G.vec = gidx;
+        G.queue = 1;
+        groups[gidx] = G;
+        for (int k = 0; k < A.wgs1; ++k) wg_group[w++] = gidx;
+    }
+    for (int q = 0; q < A.n0; ++q, ++gidx) {
+        Group G;
+        G.wg0 = w;
+        G.nwg = A.wgs0;
+        G.lane0 = A.lane0_0;
+        G.nlanes = A.nlanes0;
+        G.vec = gidx;
+        G.queue = 0;
+        groups[gidx] = G;
+        for (int k = 0; k < A.wgs0; ++k) wg_group[w++] = gidx;
+    }
+    for (; w < A.grid; ++w) wg_group[w] = -1;
+}
+
+pt_batch_tuning default_tuning(int n) {
+    pt_batch_tuning t{};
+    t.fine_wgs = env_int("PT_BATCH_FINE_WGS", 2);
+    t.sweep_wgs = env_int("PT_BATCH_SWEEP_WGS", 16);
+    t.sweep_groups = env_int("PT_BATCH_SWEEP_GROUPS", std::max(1, std::min(n, 8)));
+    t.resident = env_int("PT_BATCH_RESIDENT", 0);
+    t.grid = env_int("PT_BATCH_GRID", 0);
+    return t;
+}
+
+bool valid_tuning(const pt_batch_tuning *t) {
+    return t->fine_wgs >= 1 && t->fine_wgs <= kMaxGroup && t->sweep_wgs >= 1 &&
+           t->sweep_wgs <= kMaxGroup && t->sweep_groups >= 1 &&
+           t->sweep_groups < kMaxBatchGroups && (t->resident == 0 || t->resident == 1) &&
+           t->grid >= 0 && t->grid <= kMaxGrid;
+}
+
+// Plans and runs one multi-design engine launch. `hd` holds the designs'
+// descriptors (C, B, I set); their DesignPlan is filled here and the
+// descriptors are uploaded.
+int run_batched_engine(std::vector<EngineDesc> &hd, const pt_batch_tuning &T, bool adjoint,
+                       void *ws, const BatchLayout &Lay, hipStream_t stream) {
+    const int n = (int)hd.size();
+    Device dev;
+    PT_TRY(device_info(dev));
+    const bool fp32 = hd[0].C.fp32 != 0;
+    const int npt = T.resident ? 8 : 0;
+    const int cap_d = lds_cap_doubles(dev);
+    // tiles and LDS of every design on both kinds of worker
+    size_t lds_d = 0;
+    for (auto &E : hd) {
+        const Consts &C = E.C;
+        const int H = C.W + 1;
+        int t0, t1;
+        if (T.resident) {
+            t0 = (C.Nn + T.fine_wgs - 1) / T.fine_wgs;
+            t1 = (C.Nn + T.sweep_wgs - 1) / T.sweep_wgs;
+            if (t0 < H || t1 < H || t0 > kThreads * npt || t1 > kThreads * npt) return PT_EINVAL;
+            // every workgroup of a resident group owns a non-empty tile
+            if ((C.Nn + t0 - 1) / t0 != T.fine_wgs || (C.Nn + t1 - 1) / t1 != T.sweep_wgs)
+                return PT_EINVAL;
+        } else {
+            t0 = tile_for(C.Nn, T.fine_wgs, H, cap_d);
+            t1 = tile_for(C.Nn, T.sweep_wgs, H, cap_d);
+        }
+        E.plan.tile0 = t0;
+        E.plan.tile1 = t1;
+        E.plan.adjoint = adjoint ? 1 : 0;
+        lds_d = std::max(lds_d, engine_lds_doubles(std::max(t0, t1), C.W));
+    }
+    const size_t lds_bytes = lds_d * sizeof(double);
+    if (lds_bytes > (size_t)dev.lds_max) return PT_EINVAL;
+    // designs with the longest sweeps first (N_tau solves of N_n nodes)
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (double)hd[a].C.Ntau * hd[a].C.Nn > (double)hd[b].C.Ntau * hd[b].C.Nn;
+    });
+    int q0 = 0, q1 = 0;
+    for (int d : order) {
+        auto &E = hd[d];
+        const int Ntau = E.C.Ntau;
+        E.plan.q0_lane0 = q0;
+        E.plan.q0_count = Ntau + (E.I.gk_lanes ? Ntau - 1 : 0);
+        q0 += E.plan.q0_count;
+    }
+    for (int d : order) {
+        auto &E = hd[d];
+        E.plan.q1_cold = E.I.cold ? q0 + q1++ : -1;
+    }
+    for (int d : order) {
+        auto &E = hd[d];
+        E.plan.q1_sweep = E.C.Ntau > 1 ? q0 + q1++ : -1;
+    }
+    if (q0 + q1 > Lay.s.max_lanes) return PT_EINVAL;
+    int cap = 0;
+    PT_TRY(engine_capacity(fp32, npt, lds_bytes, dev, cap));
+    int grid = std::min(cap, kMaxGrid);
+    if (T.grid > 0) grid = std::min(grid, T.grid);
+    GroupArgs A{};
+    A.n1 = q1 > 0 ? std::min(T.sweep_groups, q1) : 0;
+    A.wgs1 = T.sweep_wgs;
+    A.lane0_1 = q0;
+    A.nlanes1 = q1;
+    A.wgs0 = T.fine_wgs;
+    A.lane0_0 = 0;
+    A.nlanes0 = q0;
+    const int left = grid - A.n1 * A.wgs1;
+    if (left < A.wgs0) return PT_EINVAL;
+    A.n0 = std::min(std::min(left / A.wgs0, q0), kMaxBatchGroups - A.n1);
+    if (A.n0 < 1) return PT_EINVAL;
+    A.grid = A.n1 * A.wgs1 + A.n0 * A.wgs0;
+    EngineDesc *D = at<EngineDesc>(ws, Lay.s.desc);
+    PT_TRY(upload_descs(hd, D, stream));
+    hipLaunchKernelGGL(k_build_lanes, dim3(n), dim3(64), 0, stream, D, at<Lane>(ws, Lay.s.lanes));
+    hipLaunchKernelGGL(k_build_groups, dim3(1), dim3(64), 0, stream, A,
+                       at<Group>(ws, Lay.s.groups), at<int>(ws, Lay.s.wg_group));
+    PT_TRY(launch_check());
+    PT_TRY(reset_launch_state(ws, Lay.s, n, stream));
+    const Launch X = make_launch(ws, Lay.s, hd[0].B.ctl, hd[0].C.timeout_ticks);
+    return launch_engine(fp32, npt, D, X, A.grid, lds_bytes, dev, stream);
+}
+
+bool valid_batch(int n, const pt_problem *probs) {
+    if (n < 1 || n > 4096 || !probs) return false;
+    for (int k = 0; k < n; ++k) {
+        if (!valid_problem(&probs[k])) return false;
+        if (probs[k].iterations != 1) return false;
+        if (probs[k].precision != probs[0].precision) return false;
+    }
+    return true;
 }
 
 }  // namespace
@@ -563,20 +894,28 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
     }
     if (overlaps(S, sz_S, ws, ws_bytes) || overlaps(uT_out, sz_U, ws, ws_bytes)) return PT_EINVAL;
 
-    Bufs B = make_bufs(ws, Lay);
-    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, stream, B.ctl, 0);
-    PT_TRY(setup_design(prob, C, B, rho, ws, Lay, stream));
+    std::vector<EngineDesc> hd(1);
+    memset(hd.data(), 0, sizeof(EngineDesc));
+    EngineDesc &E = hd[0];
+    E.C = C;
+    E.B = make_bufs(ws, Lay.d, Lay.s, 0);
+    E.B.rho = rho;
+    EngineDesc *D = at<EngineDesc>(ws, Lay.s.desc);
+    PT_TRY(upload_descs(hd, D, stream));
+    PT_TRY(setup_designs(1, prob, hd, D, 0, stream));
 
-    double *outT = uT_out ? uT_out : at<double>(ws, Lay.Ubuf);
-    double *outth = utheta_out ? utheta_out : at<double>(ws, Lay.Ubuf_th);
-    double *Uprev = at<double>(ws, Lay.Uprev);
-    double *Uprev_th = at<double>(ws, Lay.Uprev_th);
-    double *Ga = at<double>(ws, Lay.Gk), *Gb = at<double>(ws, Lay.Gn);
-    double *Ga_th = at<double>(ws, Lay.Gk_th), *Gb_th = at<double>(ws, Lay.Gn_th);
+    double *outT = uT_out ? uT_out : at<double>(ws, Lay.d.Ubuf);
+    double *outth = utheta_out ? utheta_out : at<double>(ws, Lay.d.Ubuf_th);
+    double *Uprev = at<double>(ws, Lay.d.Uprev);
+    double *Uprev_th = at<double>(ws, Lay.d.Uprev_th);
+    double *Ga = at<double>(ws, Lay.d.Gk), *Gb = at<double>(ws, Lay.d.Gn);
+    double *Ga_th = at<double>(ws, Lay.d.Gk_th), *Gb_th = at<double>(ws, Lay.d.Gn_th);
     const bool cold = guess_T == nullptr;
     const int Ntau = C.Ntau;
+    Bufs &B = E.B;
     for (int it = 0; it < prob->iterations; ++it) {
-        LaunchInfo I{};
+        LaunchInfo &I = E.I;
+        I = LaunchInfo{};
         I.cold = (cold && it == 0) ? 1 : 0;
         I.gk_lanes = (!cold && it == 0 && Ntau > 1) ? 1 : 0;
         I.has_dc = (prob->c0 != prob->cmin) ? 1 : 0;
@@ -590,6 +929,8 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
         B.Gk_th = Ga_th;
         B.Gn = Gb;
         B.Gn_th = Gb_th;
+        B.Theta_out = Theta_out;
+        PT_TRY(upload_descs(hd, D, stream));
         std::vector<LanePlan> plans;
         plans.push_back({F_PRI, Ntau, 0, +1, (double)C.M, false, env_int("PT_FQUEUES", 0)});
         if (I.gk_lanes)
@@ -597,7 +938,7 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
                              env_int("PT_GQUEUES", 0)});
         if (I.cold) plans.push_back({COLD_PRI, 1, 0, +1, 0.0, true, 0});
         if (Ntau > 1) plans.push_back({SWEEP_PRI, 1, 0, +1, 0.0, true, 0});
-        PT_TRY(run_engine(C, B, I, plans, ws, Lay, stream));
+        PT_TRY(run_engine(C, D, plans, ws, Lay, B.ctl, stream));
         if (it + 1 < prob->iterations) {
             hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Uprev, outT, Nt1 * Nn);
             hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(256), 0, stream, Uprev_th, outth, Nt1);
@@ -606,9 +947,7 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
             std::swap(Ga_th, Gb_th);
         }
     }
-    B.out_T = outT;
-    B.out_th = outth;
-    hipLaunchKernelGGL(k_finalize_fwd, dim3(256), dim3(256), 0, stream, C, B, Theta_out);
+    hipLaunchKernelGGL(k_finalize_fwd, dim3(256, 1), dim3(256), 0, stream, D);
     return launch_check();
 }
 
@@ -628,17 +967,25 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
             return PT_EINVAL;
     }
     if (overlaps(lambda_out, sz_U, ws, ws_bytes)) return PT_EINVAL;
-    Bufs B = make_bufs(ws, Lay);
-    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, stream, B.ctl, 1);
-    PT_TRY(setup_design(prob, C, B, rho, ws, Lay, stream));
+    std::vector<EngineDesc> hd(1);
+    memset(hd.data(), 0, sizeof(EngineDesc));
+    EngineDesc &E = hd[0];
+    E.C = C;
+    E.B = make_bufs(ws, Lay.d, Lay.s, 0);
+    E.B.rho = rho;
+    EngineDesc *D = at<EngineDesc>(ws, Lay.s.desc);
+    PT_TRY(upload_descs(hd, D, stream));
+    PT_TRY(setup_designs(1, prob, hd, D, 1, stream));
 
-    double *outL = lambda_out ? lambda_out : at<double>(ws, Lay.Lbuf);
-    double *Lprev = at<double>(ws, Lay.Lprev);
-    double *Ga = at<double>(ws, Lay.Gk), *Gb = at<double>(ws, Lay.Gn);
+    double *outL = lambda_out ? lambda_out : at<double>(ws, Lay.d.Ubuf);
+    double *Lprev = at<double>(ws, Lay.d.Uprev);
+    double *Ga = at<double>(ws, Lay.d.Gk), *Gb = at<double>(ws, Lay.d.Gn);
     const bool cold = guess_lambda == nullptr;
     const int Ntau = C.Ntau;
+    Bufs &B = E.B;
     for (int it = 0; it < prob->iterations; ++it) {
-        LaunchInfo I{};
+        LaunchInfo &I = E.I;
+        I = LaunchInfo{};
         I.cold = (cold && it == 0) ? 1 : 0;
         I.gk_lanes = (!cold && it == 0 && Ntau > 1) ? 1 : 0;
         I.has_dc = (prob->c0 != prob->cmin) ? 1 : 0;
@@ -649,6 +996,7 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
         B.out_L = outL;
         B.Gk = Ga;
         B.Gn = Gb;
+        PT_TRY(upload_descs(hd, D, stream));
         std::vector<LanePlan> plans;
         // the reversed sweep consumes slices from N_tau downwards
         plans.push_back({F_ADJ, Ntau, Ntau, -1, (double)C.M, false, env_int("PT_FQUEUES", 0)});
@@ -657,15 +1005,14 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
                              false, env_int("PT_GQUEUES", 0)});
         if (I.cold) plans.push_back({COLD_ADJ, 1, 0, +1, 0.0, true, 0});
         if (Ntau > 1) plans.push_back({SWEEP_ADJ, 1, 0, +1, 0.0, true, 0});
-        PT_TRY(run_engine(C, B, I, plans, ws, Lay, stream));
+        PT_TRY(run_engine(C, D, plans, ws, Lay, B.ctl, stream));
         if (it + 1 < prob->iterations) {
             hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Lprev, outL, Nt1 * Nn);
             PT_TRY(launch_check());
             std::swap(Ga, Gb);
         }
     }
-    B.out_L = outL;
-    hipLaunchKernelGGL(k_finalize_adj, dim3(256), dim3(256), 0, stream, C, B);
+    hipLaunchKernelGGL(k_finalize_adj, dim3(256, 1), dim3(256), 0, stream, D);
     return launch_check();
 }
 
@@ -675,10 +1022,16 @@ int pt_sensitivities(const pt_problem *prob, const double *rho, const void *ws, 
     if (!rho || !ws || !dTheta_drho) return PT_EINVAL;
     const Layout Lay = layout(prob);
     if (ws_bytes < Lay.total) return PT_ENOMEM;
-    const Consts C = make_consts(prob);
     void *w = const_cast<void *>(ws);
-    hipLaunchKernelGGL(k_sensitivities, dim3(512), dim3(256), 0, stream, C, at<double>(w, Lay.acc),
-                       at<double>(w, Lay.accG), dTheta_drho);
+    std::vector<EngineDesc> hd(1);
+    memset(hd.data(), 0, sizeof(EngineDesc));
+    hd[0].C = make_consts(prob);
+    hd[0].B = make_bufs(w, Lay.d, Lay.s, 0);
+    hd[0].B.rho = rho;
+    hd[0].B.grad = dTheta_drho;
+    EngineDesc *D = at<EngineDesc>(w, Lay.s.desc);
+    PT_TRY(upload_descs(hd, D, stream));
+    hipLaunchKernelGGL(k_sensitivities, dim3(512, 1), dim3(256), 0, stream, D);
     return launch_check();
 }
 
@@ -687,20 +1040,18 @@ int pt_query_trace(const pt_problem *prob, const void *ws, hipStream_t stream,
     if (!valid_problem(prob) || !ws || !out || !n_lanes || !stride) return PT_EINVAL;
     const Layout Lay = layout(prob);
     PT_TRY(hip_ok(hipStreamSynchronize(stream)));
-    const size_t words = (size_t)Lay.max_lanes * Lay.trace_stride;
+    const size_t words = (size_t)Lay.s.max_lanes * Lay.s.trace_stride;
     const size_t n = std::min(words, out_words);
-    PT_TRY(hip_ok(hipMemcpy(out, static_cast<const char *>(ws) + Lay.trace,
+    PT_TRY(hip_ok(hipMemcpy(out, static_cast<const char *>(ws) + Lay.s.trace,
                             n * sizeof(unsigned long long), hipMemcpyDeviceToHost)));
-    *n_lanes = Lay.max_lanes;
-    *stride = Lay.trace_stride;
+    *n_lanes = Lay.s.max_lanes;
+    *stride = Lay.s.trace_stride;
     return PT_OK;
 }
 
-int pt_query_status(const void *ws, hipStream_t stream, pt_stats *out) {
-    if (!ws || !out) return PT_EINVAL;
-    PT_TRY(hip_ok(hipStreamSynchronize(stream)));
+static int read_status(const void *ctl_dev, pt_stats *out) {
     Control c;
-    PT_TRY(hip_ok(hipMemcpy(&c, ws, sizeof(Control), hipMemcpyDeviceToHost)));
+    PT_TRY(hip_ok(hipMemcpy(&c, ctl_dev, sizeof(Control), hipMemcpyDeviceToHost)));
     memset(out, 0, sizeof(*out));
     out->status = c.status;
     out->max_cg_iters = c.max_iters;
@@ -711,6 +1062,174 @@ int pt_query_status(const void *ws, hipStream_t stream, pt_stats *out) {
     double r;
     memcpy(&r, &c.max_relres_bits, sizeof(double));
     out->max_rel_residual = r;
+    return PT_OK;
+}
+
+int pt_query_status(const void *ws, hipStream_t stream, pt_stats *out) {
+    if (!ws || !out) return PT_EINVAL;
+    PT_TRY(hip_ok(hipStreamSynchronize(stream)));
+    return read_status(ws, out);
+}
+
+size_t pt_batched_workspace_bytes(int n, const pt_problem *probs) {
+    if (!valid_batch(n, probs)) return 0;
+    return batch_layout(n, probs).total;
+}
+
+int pt_batch_default_tuning(int n, pt_batch_tuning *out) {
+    if (n < 1 || !out) return PT_EINVAL;
+    *out = default_tuning(n);
+    return PT_OK;
+}
+
+int pt_parareal_batched(int n, const pt_problem *probs, const double *const *rho, int warm,
+                        const pt_batch_tuning *tuning, double *Theta_out,
+                        double *const *dTheta_drho, void *ws, size_t ws_bytes,
+                        hipStream_t stream) {
+    if (!valid_batch(n, probs)) return PT_EINVAL;
+    if (!rho || !Theta_out || !dTheta_drho || !ws || (warm != 0 && warm != 1)) return PT_EINVAL;
+    for (int k = 0; k < n; ++k)
+        if (!rho[k] || !dTheta_drho[k]) return PT_EINVAL;
+    const pt_batch_tuning T = tuning ? *tuning : default_tuning(n);
+    if (!valid_tuning(&T)) return PT_EINVAL;
+    const BatchLayout Lay = batch_layout(n, probs);
+    if (ws_bytes < Lay.total) return PT_ENOMEM;
+    if (overlaps(Theta_out, sizeof(double) * n, ws, ws_bytes)) return PT_EINVAL;
+    for (int k = 0; k < n; ++k)
+        if (overlaps(dTheta_drho[k], sizeof(double) * probs[k].nx * probs[k].ny, ws, ws_bytes))
+            return PT_EINVAL;
+
+    std::vector<EngineDesc> hd(n);
+    memset(hd.data(), 0, sizeof(EngineDesc) * n);
+    for (int k = 0; k < n; ++k) {
+        EngineDesc &E = hd[k];
+        const DesignLayout &L = Lay.d[k];
+        E.C = make_consts(&probs[k]);
+        // lanes of later designs may wait seconds for the shared sweep workers
+        if (!getenv("PT_WAIT_TIMEOUT_S")) E.C.timeout_ticks = (long long)(60.0 * 1e8);
+        E.B = make_bufs(ws, L, Lay.s, k);
+        E.B.rho = rho[k];
+        E.B.S = at<double>(ws, L.S);
+        E.B.out_T = at<double>(ws, L.uT);
+        E.B.out_th = at<double>(ws, L.uth);
+        E.B.out_L = at<double>(ws, L.lam);
+        E.B.Theta_out = Theta_out + k;
+        E.B.Theta = Theta_out + k;
+        E.B.grad = dTheta_drho[k];
+        E.B.save_T = at<double>(ws, L.gT);
+        E.B.save_th = at<double>(ws, L.gth);
+        E.B.save_L = at<double>(ws, L.gL);
+        E.I.cold = warm ? 0 : 1;
+        E.I.gk_lanes = (warm && E.C.Ntau > 1) ? 1 : 0;
+        E.I.has_dc = (probs[k].c0 != probs[k].cmin) ? 1 : 0;
+        E.I.epoch = 1;
+    }
+    EngineDesc *D = at<EngineDesc>(ws, Lay.s.desc);
+    PT_TRY(upload_descs(hd, D, stream));
+    PT_TRY(setup_designs(n, probs, hd, D, 0, stream));
+    // primal pass of every design in one launch
+    for (int k = 0; k < n; ++k) {
+        Bufs &B = hd[k].B;
+        B.in_T = warm ? at<double>(ws, Lay.d[k].gT) : nullptr;
+        B.in_th = warm ? at<double>(ws, Lay.d[k].gth) : nullptr;
+        B.Gk = at<double>(ws, Lay.d[k].Gk);
+        B.Gk_th = at<double>(ws, Lay.d[k].Gk_th);
+        B.Gn = at<double>(ws, Lay.d[k].Gn);
+        B.Gn_th = at<double>(ws, Lay.d[k].Gn_th);
+    }
+    PT_TRY(run_batched_engine(hd, T, false, ws, Lay, stream));
+    hipLaunchKernelGGL(k_finalize_fwd, dim3(64, n), dim3(256), 0, stream, D);
+    PT_TRY(launch_check());
+    // adjoint pass of every design in one launch
+    for (int k = 0; k < n; ++k) {
+        Bufs &B = hd[k].B;
+        B.in_L = warm ? at<double>(ws, Lay.d[k].gL) : nullptr;
+    }
+    PT_TRY(run_batched_engine(hd, T, true, ws, Lay, stream));
+    hipLaunchKernelGGL(k_finalize_adj, dim3(64, n), dim3(256), 0, stream, D);
+    hipLaunchKernelGGL(k_sensitivities, dim3(128, n), dim3(256), 0, stream, D);
+    hipLaunchKernelGGL(k_save_guess, dim3(128, n), dim3(256), 0, stream, D);
+    return launch_check();
+}
+
+int pt_batched_status(int n, const pt_problem *probs, const void *ws, hipStream_t stream,
+                      pt_stats *out) {
+    if (!valid_batch(n, probs) || !ws || !out) return PT_EINVAL;
+    const BatchLayout Lay = batch_layout(n, probs);
+    PT_TRY(hip_ok(hipStreamSynchronize(stream)));
+    for (int k = 0; k < n; ++k)
+        PT_TRY(read_status(static_cast<const char *>(ws) + Lay.d[k].ctl, &out[k]));
+    return PT_OK;
+}
+
+int pt_autotune_batched(int n, const pt_problem *probs, const double *const *rho,
+                        double *Theta_out, double *const *dTheta_drho, void *ws,
+                        size_t ws_bytes, hipStream_t stream, pt_batch_tuning *best,
+                        double *best_ms) {
+    if (!valid_batch(n, probs) || !best) return PT_EINVAL;
+    if (capturing(stream)) return PT_EINVAL;
+    pt_batch_tuning cur = default_tuning(n);
+    // the guesses every timed cycle restarts from
+    PT_TRY(pt_parareal_batched(n, probs, rho, 0, &cur, Theta_out, dTheta_drho, ws, ws_bytes,
+                               stream));
+    PT_TRY(hip_ok(hipStreamSynchronize(stream)));
+    hipEvent_t e0, e1;
+    PT_TRY(hip_ok(hipEventCreate(&e0)));
+    PT_TRY(hip_ok(hipEventCreate(&e1)));
+    std::vector<pt_stats> st(n);
+    auto time_cycle = [&](const pt_batch_tuning &t, double &ms) -> int {
+        PT_TRY(hip_ok(hipEventRecord(e0, stream)));
+        int rc = pt_parareal_batched(n, probs, rho, 1, &t, Theta_out, dTheta_drho, ws, ws_bytes,
+                                     stream);
+        if (rc != PT_OK) return rc;
+        PT_TRY(hip_ok(hipEventRecord(e1, stream)));
+        PT_TRY(hip_ok(hipEventSynchronize(e1)));
+        float f = 0.0f;
+        PT_TRY(hip_ok(hipEventElapsedTime(&f, e0, e1)));
+        PT_TRY(pt_batched_status(n, probs, ws, stream, st.data()));
+        for (const auto &s : st)
+            if (s.status != PT_OK && s.status != PT_ENOCONV) return s.status;
+        ms = f;
+        return PT_OK;
+    };
+    double best_t = 1e30;
+    int rc0 = time_cycle(cur, best_t);
+    if (rc0 != PT_OK) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return rc0;
+    }
+    // coordinate descent over the worker shapes
+    const int fine_opts[] = {1, 2, 4, 8};
+    const int sweep_opts[] = {8, 16, 32};
+    const int group_opts[] = {std::max(1, n / 8), std::max(1, n / 4), std::max(1, n / 2), n};
+    auto consider = [&](pt_batch_tuning t) {
+        double ms = 0.0;
+        if (!valid_tuning(&t)) return;
+        if (time_cycle(t, ms) == PT_OK && ms < best_t) {
+            best_t = ms;
+            cur = t;
+        }
+    };
+    for (int f : fine_opts) {
+        pt_batch_tuning t = cur;
+        t.fine_wgs = f;
+        if (f != cur.fine_wgs) consider(t);
+    }
+    for (int s : sweep_opts) {
+        pt_batch_tuning t = cur;
+        t.sweep_wgs = s;
+        if (s != cur.sweep_wgs) consider(t);
+    }
+    for (int g : group_opts) {
+        pt_batch_tuning t = cur;
+        t.sweep_groups = std::min(g, kMaxBatchGroups - 1);
+        if (t.sweep_groups != cur.sweep_groups) consider(t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *best = cur;
+    if (best_ms) *best_ms = best_t;
     return PT_OK;
 }
 

@@ -9,7 +9,8 @@
 namespace pt {
 
 constexpr int kThreads = 512;       // threads per workgroup of the lane engine
-constexpr int kMaxLanes = 512;      // lanes per engine launch
+constexpr int kMaxLanes = 512;      // lanes per single-design engine launch
+constexpr int kMaxGroups = 1024;    // groups per engine launch
 constexpr int kMaxGroup = 1024;     // workgroups per lane group (partials slots)
 constexpr int kVecsPerLane = 10;    // x, p, r[2], w[2], s[2], tp, tq
 constexpr int kMaxFlags = 4 * 4096; // dependency flags per launch
@@ -33,15 +34,20 @@ enum FlagKind : int { FL_F = 0, FL_GK = 1, FL_COLD = 2, FL_SWEEP = 3 };
 struct Lane {
     int kind;
     int slice;      // n for F/GK lanes; unused for sweeps
+    int design;     // index into the launch's design descriptors
+    int tile;       // nodes per workgroup tile for this lane on its group
 };
 
 // A group of workgroups runs a queue of lanes one after another; its
 // workgroups share one barrier counter, one partial-sum slot and one vector set.
+// queue < 0: the group owns lanes [lane0, lane0 + nlanes) in order.
+// queue >= 0: the group shares queue `queue` (lanes [lane0, lane0 + nlanes))
+// with other groups and takes the next untaken lane whenever it is free.
 struct Group {
-    int wg0, nwg;     // workgroup range
-    int lane0, nlanes;  // lanes [lane0, lane0 + nlanes) in queue order
-    int tile;         // nodes per tile
-    int vec;          // vector set index in the pool
+    int wg0, nwg;       // workgroup range
+    int lane0, nlanes;  // lane range of the group's (or its queue's) list
+    int vec;            // vector set index in the pool
+    int queue;          // shared queue index, -1 for a private list
 };
 
 // Device-side control/status block at the start of the workspace.
@@ -73,27 +79,28 @@ struct Consts {
     double rtol;
     double inv_NtNe, inv_NtauNe, inv_p;
     long long timeout_ticks;         // s_memrealtime ticks before a wait gives up
+    // material law and source of the setup kernels (Eq. 2.5-2.6)
+    double k0, kmin, pk, c0, cmin, pc, q;
+    int bc_rule;  // 0 centre of left edge, 1 centre of bottom edge, 2 none, 3 caller mask
+    int has_qt;   // q(t) was copied in by the host
 };
 
-// Pointers into the workspace and the caller's arrays for one engine launch.
+// Pointers of one design: its workspace arrays and the caller's arrays.
 struct Bufs {
     Control *ctl;
-    unsigned *bar;         // [kMaxLanes] group barrier counters (one per group)
-    unsigned *flags;       // [kMaxFlags]
-    double *partials;      // [kMaxLanes][2][kMaxGroup][4] (one block per group)
-    const int *wg_group;   // [grid] group of each workgroup (-1: idle)
-    const Group *groups;   // [n_groups]
-    const Lane *lanes;     // [n_lanes]
-    double *pool;          // group vectors [n_groups][kVecsPerLane][Nn]
+    unsigned *flags;       // [kMaxFlags] dependency flags of this design
+    double *pool;          // group vectors, slot (vec * kVecsPerLane + which) * pool_stride
+    size_t pool_stride;    // >= Nn of every design sharing the pool
     double *FL;            // fine adjoint outputs F_adj(v^k_n), lambda part [Ntau+1][Nn]
-    const double *kq;      // padded k/6   [(ny+2)(nx+2)]
-    const double *cm;      // padded c*hx*hy/36
-    const double *dk;      // k'(rho) per element [Ne]
-    const double *dc;      // c'(rho) per element [Ne]
-    const double *dinv_f;  // 1/diag of C/dt + K (0 on Dirichlet nodes) [Nn]
-    const double *dinv_c;  // 1/diag of C/dtau + K
-    const unsigned char *mask;  // Dirichlet mask [Nn]
-    const double *qt;      // q(t_n), n = 0..Nt
+    const double *rho;     // design densities [Ne]
+    double *kq;            // padded k/6   [(ny+2)(nx+2)]
+    double *cm;            // padded c*hx*hy/36
+    double *dk;            // k'(rho) per element [Ne]
+    double *dc;            // c'(rho) per element [Ne]
+    double *dinv_f;        // 1/diag of C/dt + K (0 on Dirichlet nodes) [Nn]
+    double *dinv_c;        // 1/diag of C/dtau + K
+    unsigned char *mask;   // Dirichlet mask [Nn]
+    double *qt;            // q(t_n), n = 0..Nt
     // primal
     const double *in_T;    // guess u^k (warm) [Ntau+1][Nn]
     const double *in_th;   // [Ntau+1]
@@ -105,16 +112,60 @@ struct Bufs {
     double *Gn;            // G(u^{k+1}_n) written by the sweep [Ntau+1][Nn]
     double *Gn_th;
     double *F_th;          // theta part of F(u^k_n) [Ntau]
+    double *Theta_out;     // device scalar written by the forward finalize
     // adjoint
     const double *Theta;   // device scalar
     const double *in_L;    // guess lambda [Ntau+1][Nn]
     double *out_L;         // [Ntau+1][Nn]
     double *acc;           // per fine adjoint slice sensitivity sums [Ntau][Ne]
     double *accG;          // coarse correction sensitivity sums [Ne]
-    const double *zero;    // Nn zeros
-    double *xch;           // resident-mode halo exchange [grid][2 parities][2 sides][3][W+2]
+    double *grad;          // dTheta/drho [Ne] (sensitivity kernel output)
+    double *zero;          // Nn zeros
+    // multi-design cycles: where the corrected u and lambda are kept as the
+    // next cycle's guesses
+    double *save_T, *save_th, *save_L;
+};
+
+struct LaunchInfo {
+    int cold;        // inputs of this iteration come from the cold sweep lane
+    int gk_lanes;    // batched G(u^k_n) lanes are present (warm first iteration)
+    int has_dc;      // dC/drho is not identically zero
+    unsigned epoch;  // value a set flag holds in this launch
+};
+
+// Lane runs of one design in a multi-design launch: the fine lanes (F and, if
+// present, G(u^k_n)) go to queue 0, the cold and correction sweeps to queue 1
+// (the cold sweeps of all designs ahead of every correction sweep).
+struct DesignPlan {
+    int q0_lane0, q0_count;  // first lane index and count in the fine queue
+    int q1_cold, q1_sweep;   // lane index of the cold / correction sweep (-1: none)
+    int tile0, tile1;        // tile of this design's lanes on queue 0 / queue 1 groups
+    int adjoint;             // lane kinds of the adjoint pass
+};
+
+// Everything a workgroup needs about one design, read from device memory.
+struct EngineDesc {
+    Consts C;
+    Bufs B;
+    LaunchInfo I;
+    DesignPlan plan;
+};
+
+// Launch-wide arrays shared by every design of one engine launch.
+struct Launch {
+    const int *wg_group;   // [grid] group of each workgroup (-1: idle)
+    const Group *groups;   // [n_groups]
+    const Lane *lanes;     // [n_lanes]
+    unsigned *bar;         // [kMaxGroups] group barrier counters
+    double *partials;      // [kMaxGroups][2][kMaxGroup][4]
+    double *xch;           // resident-mode halo exchange [grid][2][2][3][xch_stride]
+    int xch_stride;        // >= W + 1 of every design
+    unsigned *qhead;       // [2] next untaken position of each shared queue
+    int *qslot;            // [kMaxGroups] lane position a group leader took
     unsigned long long *trace;  // per-lane record [n_lanes][trace_stride]
-    int trace_stride;           // 8 header words + one timestamp per step
+    int trace_stride;           // TR_HDR words + one timestamp per step
+    Control *ctl0;         // status block for failures outside any lane
+    long long timeout_ticks;
 };
 
 // Trace record of one lane (written by its leader): kind, slice, nwg, tile,
@@ -127,13 +178,6 @@ enum {
     TR_T_RED,     // ticks reading partial sums after barriers
     TR_T_FLAG,    // ticks waiting on other lanes' flags
     TR_HDR = 12
-};
-
-struct LaunchInfo {
-    int cold;        // inputs of this iteration come from the cold sweep lane
-    int gk_lanes;    // batched G(u^k_n) lanes are present (warm first iteration)
-    int has_dc;      // dC/drho is not identically zero
-    unsigned epoch;  // value a set flag holds in this launch
 };
 
 }  // namespace pt

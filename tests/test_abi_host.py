@@ -117,3 +117,60 @@ def test_struct_layout_matches_header():
     assert offs["cg_rtol"] == 96 and offs["max_iter"] == 104
     assert offs["dirichlet_mask"] == 128
     assert ctypes.sizeof(PtProblem) == 136
+
+
+def _batch(lib, probs, rho=None, grads=None, theta=0x3000, ws=0x10000000, nbytes=None,
+           warm=0, tuning=None):
+    arr = (PtProblem * len(probs))(*[p.to_c() for p in probs])
+    n = len(probs)
+    rho = rho if rho is not None else [0x1000 + 0x100 * k for k in range(n)]
+    grads = grads if grads is not None else [0x8000 + 0x100 * k for k in range(n)]
+    rp = (ctypes.c_void_p * n)(*rho)
+    gp = (ctypes.c_void_p * n)(*grads)
+    if nbytes is None:
+        nbytes = lib.pt_batched_workspace_bytes(n, arr)
+    t = ctypes.byref(tuning) if tuning is not None else None
+    return lib.pt_parareal_batched(n, arr, rp, warm, t, theta, gp, ws, nbytes, None)
+
+
+def test_batched_workspace_and_validation(lib):
+    a, b = base(), base(nx=12, ny=6, n_steps=30, n_slices=5)
+    arr = (PtProblem * 2)(a.to_c(), b.to_c())
+    one = (PtProblem * 1)(a.to_c())
+    nb2 = lib.pt_batched_workspace_bytes(2, arr)
+    nb1 = lib.pt_batched_workspace_bytes(1, one)
+    assert nb2 > nb1 > 0
+    # mixed precision, several Parareal iterations, invalid members: no workspace
+    for bad in (base(precision=1), base(iterations=2), base(pnorm=3)):
+        arr_bad = (PtProblem * 2)(a.to_c(), bad.to_c())
+        assert lib.pt_batched_workspace_bytes(2, arr_bad) == 0
+    assert lib.pt_batched_workspace_bytes(0, arr) == 0
+
+
+def test_batched_argument_errors_before_any_device_work(lib):
+    a, b = base(), base(nx=12, ny=6, n_steps=30, n_slices=5)
+    assert _batch(lib, [a, b], rho=[0x1000, None]) == _pt.PT_EINVAL
+    assert _batch(lib, [a, b], grads=[None, 0x9000]) == _pt.PT_EINVAL
+    assert _batch(lib, [a, b], theta=None) == _pt.PT_EINVAL
+    assert _batch(lib, [a, b], ws=None) == _pt.PT_EINVAL
+    assert _batch(lib, [a, b], warm=2) == _pt.PT_EINVAL
+    assert _batch(lib, [a, b], nbytes=64) == _pt.PT_ENOMEM
+    assert _batch(lib, [a, base(iterations=3)]) == _pt.PT_EINVAL
+    # Theta output inside the workspace
+    assert _batch(lib, [a, b], theta=0x10000000 + 256) == _pt.PT_EINVAL
+    bad = _pt.PtBatchTuning.from_dict(dict(fine_wgs=0, sweep_wgs=16, sweep_groups=2))
+    assert _batch(lib, [a, b], tuning=bad) == _pt.PT_EINVAL
+    bad = _pt.PtBatchTuning.from_dict(dict(fine_wgs=2, sweep_wgs=16, sweep_groups=1,
+                                           resident=3))
+    assert _batch(lib, [a, b], tuning=bad) == _pt.PT_EINVAL
+
+
+def test_batch_default_tuning(lib):
+    t = _pt.PtBatchTuning()
+    assert lib.pt_batch_default_tuning(64, ctypes.byref(t)) == _pt.PT_OK
+    assert t.fine_wgs >= 1 and t.sweep_wgs >= 1 and 1 <= t.sweep_groups <= 64
+    assert lib.pt_batch_default_tuning(0, ctypes.byref(t)) == _pt.PT_EINVAL
+
+
+def test_batch_tuning_layout():
+    assert ctypes.sizeof(_pt.PtBatchTuning) == 32

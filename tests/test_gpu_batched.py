@@ -1,0 +1,228 @@
+"""Many designs in one cycle (pt_parareal_batched) against the FP64 oracle.
+
+Each design of a batch is an independent problem with its own grid, slice
+count and density. One call runs the primal passes of all designs in one
+persistent launch and the adjoint passes in a second, so every design must
+match the oracle exactly as the single-design calls do:
+- FP64 at cg_rtol 1e-13: 1e-10 relative (Theta, dTheta/drho);
+- FP32 inner CG with FP64 refinement: 1e-5 relative, Theta 1e-6.
+
+Warm cycles restart from the state the previous call left in the workspace.
+On the oracle side, the guesses are the oracle's own cold outputs.
+
+The full 64-design workload (sides 64..512, 16..64 slices, 16 steps per slice,
+FP32 + refinement) runs in the same launch shape as the benchmark. The designs
+the oracle can afford in seconds (side 64) are checked against it one by one;
+every design is checked for a finite positive Theta and an OK status.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import grad_scale, oracle_problem
+from workloads import batch_designs, density_uniform_noise
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [(16, 16, 32, 4), (24, 12, 30, 5), (9, 9, 16, 16), (32, 32, 64, 8), (1, 1, 6, 3),
+         (20, 20, 40, 1), (40, 24, 48, 6)]
+
+
+def _oracle(cfg, rho, guess=None):
+    d = O.Discretisation(oracle_problem(cfg), rho)
+    if guess is None:
+        fw = O.parareal_forward(d, 1)
+        ad = O.parareal_adjoint(d, fw["S"], fw["Theta"], 1)
+    else:
+        fw = O.parareal_forward(d, 1, guess[0], guess[1])
+        ad = O.parareal_adjoint(d, fw["S"], fw["Theta"], 1, guess[2])
+    return dict(Theta=fw["Theta"], grad=ad["grad"], guess=(fw["uT"], fw["utheta"], ad["lam"]))
+
+
+def _problems(shapes, **kw):
+    from paper_2411_19030_amd import Problem
+    return [Problem(nx=nx, ny=ny, n_steps=nt, n_slices=ns, pnorm=8, **kw)
+            for nx, ny, nt, ns in shapes]
+
+
+def _errors(theta, grad, o):
+    et = abs(theta - o["Theta"]) / abs(o["Theta"])
+    eg = np.linalg.norm(grad - o["grad"]) / grad_scale(o["Theta"], o["grad"])
+    return et, eg
+
+
+def _run(cyc, rhos, warm, gpu):
+    import torch
+    rt = [torch.tensor(r, dtype=torch.float64, device=gpu) for r in rhos]
+    th, gr = cyc.run(rt, warm=warm)
+    torch.cuda.synchronize()
+    return th.cpu().numpy().copy(), [g.cpu().numpy().copy() for g in gr]
+
+
+def _check_batch(gpu, shapes, tol_theta, tol_grad, tuning=None, **kw):
+    from paper_2411_19030_amd.batched import BatchedCycle
+    probs = _problems(shapes, **kw)
+    cyc = BatchedCycle(probs, gpu)
+    cyc.tuning = tuning
+    rhos = [density_uniform_noise(nx, ny, 100 + k) for k, (nx, ny, _, _) in enumerate(shapes)]
+    cfgs = [dict(nx=nx, ny=ny, n_steps=nt, n_slices=ns, pnorm=8) for nx, ny, nt, ns in shapes]
+    th, gr = _run(cyc, rhos, False, gpu)
+    assert all(s["status"] == 0 for s in cyc.status())
+    refs = []
+    for k, cfg in enumerate(cfgs):
+        o = _oracle(cfg, rhos[k])
+        refs.append(o)
+        et, eg = _errors(th[k], gr[k], o)
+        print("cold", shapes[k], et, eg, flush=True)
+        assert et <= tol_theta and eg <= tol_grad
+    # a warm cycle on slightly changed designs (the next optimisation cycle)
+    rhos2 = [np.clip(r + 0.01 * density_uniform_noise(len(r), 1, 7 + k, 0.0, 1.0), 0, 1)
+             for k, r in enumerate(rhos)]
+    th2, gr2 = _run(cyc, rhos2, True, gpu)
+    assert all(s["status"] == 0 for s in cyc.status())
+    for k, cfg in enumerate(cfgs):
+        o = _oracle(cfg, rhos2[k], refs[k]["guess"])
+        et, eg = _errors(th2[k], gr2[k], o)
+        print("warm", shapes[k], et, eg, flush=True)
+        assert et <= tol_theta and eg <= tol_grad
+    return th, gr, th2, gr2
+
+
+def test_batched_fp64_mixed_designs(gpu):
+    _check_batch(gpu, SMALL, 1e-10, 1e-10, cg_rtol=1e-13, max_iter=20000)
+
+
+def test_batched_fp32_refine_mixed_designs(gpu):
+    _check_batch(gpu, SMALL, 1e-6, 1e-5, cg_rtol=1e-12, max_iter=20000, precision=1)
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(fine_wgs=1, sweep_wgs=8, sweep_groups=1),
+    dict(fine_wgs=4, sweep_wgs=32, sweep_groups=7),
+    dict(fine_wgs=3, sweep_wgs=5, sweep_groups=2, grid=40),
+])
+def test_batched_worker_shapes(gpu, tuning):
+    """Other worker shapes (one sweep worker for all designs, tiny grids) give the
+    oracle's results too."""
+    shapes = [s for s in SMALL if s[0] >= 9]
+    _check_batch(gpu, shapes, 1e-10, 1e-10, tuning=tuning, cg_rtol=1e-13, max_iter=20000)
+
+
+def test_batched_resident_mode(gpu):
+    """Vectors in registers: every tile of every design must fit one workgroup."""
+    shapes = [(16, 16, 32, 4), (24, 12, 30, 5), (32, 32, 64, 8), (40, 24, 48, 6)]
+    _check_batch(gpu, shapes, 1e-10, 1e-10,
+                 tuning=dict(fine_wgs=2, sweep_wgs=4, sweep_groups=2, resident=1),
+                 cg_rtol=1e-13, max_iter=20000)
+
+
+def test_batched_is_deterministic(gpu):
+    """Lanes go to whichever worker is free, yet each lane's arithmetic only
+    depends on its tiles: two cold cycles agree bit for bit."""
+    import torch
+
+    from paper_2411_19030_amd.batched import BatchedCycle
+    probs = _problems(SMALL, cg_rtol=1e-12, max_iter=20000)
+    rhos = [torch.tensor(density_uniform_noise(nx, ny, 5 + k), device=gpu)
+            for k, (nx, ny, _, _) in enumerate(SMALL)]
+    outs = []
+    for _ in range(2):
+        cyc = BatchedCycle(probs, gpu)
+        th, gr = cyc.run(rhos, warm=False)
+        torch.cuda.synchronize()
+        outs.append((th.cpu().numpy().copy(), [g.cpu().numpy().copy() for g in gr]))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b)
+
+
+def test_batched_graph_replay_matches_eager(gpu):
+    """One warm cycle of a batch captured in a graph and replayed three times,
+    with eager work and synchronisations in between, gives the same results as
+    three eager warm cycles from the same state."""
+    import torch
+
+    from paper_2411_19030_amd.batched import BatchedCycle
+    shapes = [(16, 16, 32, 4), (24, 12, 30, 5), (32, 32, 64, 8)]
+    probs = _problems(shapes, cg_rtol=1e-12, max_iter=20000)
+    rhos = [torch.tensor(density_uniform_noise(nx, ny, 50 + k), device=gpu)
+            for k, (nx, ny, _, _) in enumerate(shapes)]
+    eager = BatchedCycle(probs, gpu)
+    eager.run(rhos, warm=False)
+    ref = []
+    for _ in range(3):
+        th, gr = eager.run(rhos, warm=True)
+        torch.cuda.synchronize()
+        ref.append((th.cpu().numpy().copy(), [g.cpu().numpy().copy() for g in gr]))
+    cyc = BatchedCycle(probs, gpu)
+    cyc.run(rhos, warm=False)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        cyc.run(rhos, warm=True)
+    for k in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device=gpu).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        th = cyc.Theta.cpu().numpy()
+        assert np.array_equal(th, ref[k][0]), (k, th, ref[k][0])
+        for a, b in zip([g.cpu().numpy() for g in cyc.grads], ref[k][1]):
+            assert np.array_equal(a, b)
+    assert all(st["status"] == 0 for st in cyc.status())
+
+
+def test_batched_autograd(gpu):
+    """thetas = obj(rhos); sum(w_k theta_k).backward() gives w_k dTheta_k/drho_k."""
+    import torch
+
+    from paper_2411_19030_amd.batched import BatchedOneShot
+    shapes = [(16, 16, 32, 4), (24, 12, 30, 5)]
+    probs = _problems(shapes, cg_rtol=1e-13, max_iter=20000)
+    obj = BatchedOneShot(probs, gpu, warm=True)
+    rhos_np = [density_uniform_noise(nx, ny, 70 + k) for k, (nx, ny, _, _) in enumerate(shapes)]
+    rhos = [torch.tensor(r, device=gpu, requires_grad=True) for r in rhos_np]
+    th = obj(rhos)
+    w = torch.tensor([0.5, 2.0], dtype=torch.float64, device=gpu)
+    (w * th).sum().backward()
+    for k, (nx, ny, nt, ns) in enumerate(shapes):
+        o = _oracle(dict(nx=nx, ny=ny, n_steps=nt, n_slices=ns, pnorm=8), rhos_np[k])
+        assert abs(float(th[k]) - o["Theta"]) <= 1e-10 * o["Theta"]
+        g = rhos[k].grad.cpu().numpy()
+        assert np.linalg.norm(g - float(w[k]) * o["grad"]) <= 1e-10 * abs(float(w[k])) * \
+            np.linalg.norm(o["grad"])
+
+
+def test_batch_fp32_64_designs_full_size(gpu):
+    """The 64-design workload in one call (default worker shapes): designs of
+    side 64 against the oracle, every design finite with an OK status."""
+    import torch
+
+    from paper_2411_19030_amd.batched import BatchedCycle
+    ds = batch_designs()
+    shapes = [(d["nx"], d["ny"], d["n_steps"], d["n_slices"]) for d in ds]
+    probs = _problems(shapes, cg_rtol=1e-10, max_iter=20000, precision=1)
+    cyc = BatchedCycle(probs, gpu)
+    rhos = [torch.tensor(d["rho"], device=gpu) for d in ds]
+    th, gr = cyc.run(rhos, warm=False)
+    torch.cuda.synchronize()
+    th = th.cpu().numpy()
+    st = cyc.status()
+    assert all(s["status"] == 0 for s in st), [s["status"] for s in st]
+    assert np.all(np.isfinite(th)) and np.all(th > 0)
+    checked = 0
+    for k, d in enumerate(ds):
+        g = gr[k].cpu().numpy()
+        assert np.all(np.isfinite(g))
+        if d["nx"] != 64:
+            continue
+        o = _oracle(dict(nx=64, ny=64, n_steps=d["n_steps"], n_slices=d["n_slices"], pnorm=8),
+                    d["rho"])
+        et, eg = _errors(th[k], g, o)
+        print("design", k, d["n_slices"], et, eg, flush=True)
+        assert et <= 1e-6 and eg <= 1e-5
+        checked += 1
+    assert checked >= 5
