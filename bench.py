@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-compare", action="store_true",
                     help="skip the FP32+refine vs FP64 comparison at equal objective accuracy")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-design batch (batched FP32+refine vs plain FP64)")
     ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (counter calibration)")
@@ -162,6 +164,89 @@ def precision_compare(prob, rho, gT, gth, gl, accuracy=1e-6, repeats=3) -> dict:
         out["speedup_fp32_refine_over_fp64"] = (out["fp64"]["ms_per_cycle"]
                                                 / out["fp32_refine"]["ms_per_cycle"])
     return out
+
+
+# Worker shapes of the 64-design batch chosen by pt_autotune_batched on the
+# MI355X (coordinate descent over fine/sweep workgroups and sweep workers).
+BATCH_TUNING = {"fine_wgs": 4, "sweep_wgs": 8, "sweep_groups": 8, "resident": 0, "grid": 0}
+
+
+def batch_compare(rtol=1e-7, ref_rtol=1e-12, accuracy=1e-6) -> dict:
+    """The 64-design workload (sides 64..512, 16..64 slices of 16 steps, seeded
+    densities): one cycle of every design. Forms, each timed on a warm cycle
+    after a cold one:
+    * batched FP32 + FP64 refinement: all designs in one launch per pass;
+    * plain FP64: one design after another through the single-design calls;
+    * reference: batched FP64 at cg_rtol 1e-12 (the accuracy yardstick).
+    The objective accuracy of a form is max over designs of |Theta - Theta_ref| /
+    Theta_ref on the warm cycle."""
+    import torch
+
+    from paper_2411_19030_amd import Problem
+    from paper_2411_19030_amd.batched import BatchedCycle
+    from paper_2411_19030_amd.cycle import Cycle
+    from workloads import batch_designs
+
+    dev = torch.device("cuda:0")
+    ds = batch_designs()
+    rhos = [torch.tensor(d["rho"], device=dev) for d in ds]
+    cells = sum(d["nx"] * d["ny"] * d["n_steps"] for d in ds)
+
+    def probs(prec, tol):
+        return [Problem(nx=d["nx"], ny=d["ny"], n_steps=d["n_steps"], n_slices=d["n_slices"],
+                        pnorm=8, cg_rtol=tol, max_iter=20000, precision=prec) for d in ds]
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def batched(prec, tol, tuning):
+        cyc = BatchedCycle(probs(prec, tol), dev)
+        cyc.tuning = tuning
+        cyc.run(rhos, warm=False)
+        t = timed(lambda: cyc.run(rhos, warm=True))
+        th = cyc.Theta.cpu().numpy().copy()
+        st = [s_["status"] for s_ in cyc.status()]
+        del cyc
+        torch.cuda.empty_cache()
+        return t, th, st
+
+    t_ref, th_ref, st_ref = batched(0, ref_rtol, BATCH_TUNING)
+    t32, th32, st32 = batched(1, rtol, BATCH_TUNING)
+    th64 = []
+    t64 = 0.0
+    st64 = []
+    for k, d in enumerate(ds):
+        cyc = Cycle(probs(0, rtol)[k], dev)
+        cyc.run(rhos[k])
+        gT, gth, gl = cyc.uT.clone(), cyc.utheta.clone(), cyc.lam.clone()
+        t64 += timed(lambda: cyc.run(rhos[k], gT, gth, gl))
+        th64.append(float(cyc.Theta))
+        st64.append(cyc.status()["status"])
+        del cyc
+    import numpy as np
+    th64 = np.array(th64)
+    err32 = float(np.max(np.abs(th32 - th_ref) / th_ref))
+    err64 = float(np.max(np.abs(th64 - th_ref) / th_ref))
+    return {
+        "workload": "batch_fp32_64",
+        "designs": len(ds),
+        "cells_per_cycle": cells,
+        "accuracy_target": accuracy,
+        "fp32_refine_batched": {"cg_rtol": rtol, "s_per_cycle": t32,
+                                "cell_updates_per_s": cells / t32, "max_Theta_rel_err": err32,
+                                "tuning": BATCH_TUNING, "status_ok": all(v == 0 for v in st32)},
+        "fp64_plain_per_design": {"cg_rtol": rtol, "s_per_cycle": t64,
+                                  "cell_updates_per_s": cells / t64, "max_Theta_rel_err": err64,
+                                  "status_ok": all(v == 0 for v in st64)},
+        "reference": {"form": "fp64 batched", "cg_rtol": ref_rtol, "s_per_cycle": t_ref,
+                      "status_ok": all(v == 0 for v in st_ref)},
+        "speedup_batched_fp32_refine_over_plain_fp64": t64 / t32,
+        "both_meet_accuracy": err32 <= accuracy and err64 <= accuracy,
+    }
 
 
 def main():
@@ -271,6 +356,10 @@ def main():
     }
     if not args.no_precision_compare:
         out["vs_fp64"] = precision_compare(prob, rho, gT, gth, gl)
+    if not args.no_batch:
+        del cyc
+        torch.cuda.empty_cache()
+        out["batch"] = batch_compare()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
