@@ -79,7 +79,8 @@ typedef struct pt_problem {
     int32_t max_iter;          /* CG iteration cap per solve, >= 1                                */
     int32_t precision;         /* PT_FP64, or PT_FP32_REFINE: FP32 CG (stencil, vectors, halo)    */
                                /* with FP64 dot products, FP64 x and FP64 residual refinement     */
-    int32_t precond;           /* PT_JACOBI (only value accepted by this build)                   */
+    int32_t precond;           /* PT_JACOBI, or PT_GMG: geometric multigrid V(1,1) cycle (Galerkin */
+                               /* coarse operators, bilinear transfer, damped Jacobi smoothing)   */
     int32_t storage;           /* PT_STORE_ALL (only value accepted by this build)                */
     int32_t bc;                /* PT_BC_*                                                         */
     const uint8_t *dirichlet_mask; /* HOST, (nx+1)(ny+1) bytes, read when bc == PT_BC_MASK        */

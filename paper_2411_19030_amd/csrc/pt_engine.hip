@@ -530,6 +530,8 @@ __device__ __forceinline__ double sens_term(const Consts &C, const Bufs &B, cons
 
 }  // namespace
 
+#include "pt_gmg.hip"
+
 // ---------------------------------------------------------------------------
 // Setup kernels
 // ---------------------------------------------------------------------------
@@ -776,6 +778,135 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
             }
             return r;
         };
+
+        // One preconditioned round of CG with the multigrid preconditioner B
+        // (streaming engine): with `update`, first the pointwise CG update
+        // s = w + be s, p = u + be p, x += al p, r -= al s; then u = B r by a
+        // V(1,1) cycle over the levels (group passes with a barrier between
+        // dependent passes, the small levels by workgroup 0 alone), then
+        // w = A u and the partial dot products (r,u), (u,w)[, (r,r)].
+        auto gmg_round = [&](const StepInfo &st, bool update, bool first, double al, double be,
+                             double *loc, int nloc) -> bool {
+            const int op = st.fine ? 0 : 1;
+            const double *dinv0 = st.fine ? B.dinv_f : B.dinv_c;
+            Real *R = Rb[0], *Wv = Wb[0], *Sv = Sb[0], *U = Rb[1], *UB0 = Wb[1];
+            Real *GV = reinterpret_cast<Real *>(B.gvec) + (size_t)G.vec * B.gvec_stride;
+            const size_t gn = (size_t)C.gmg_nodes;
+            auto lr = [&](int l) -> Real * { return l == 0 ? R : GV + C.gmg_off[l]; };
+            auto la = [&](int l) -> Real * { return l == 0 ? U : GV + gn + C.gmg_off[l]; };
+            auto lb = [&](int l) -> Real * { return l == 0 ? UB0 : GV + 2 * gn + C.gmg_off[l]; };
+            auto omega = [&](int l) -> Real { return (Real)B.gmg_w[op * kMaxLevels + l]; };
+            // D^{-1} of level l at id: level 0 from the Jacobi arrays (0 on
+            // Dirichlet nodes), coarse levels from the stencil centre
+            auto dinv_at = [&](int l, int id) -> Real {
+                if (l == 0) return (Real)dinv0[id];
+                const Real c = reinterpret_cast<const Real *>(B.gA)[(size_t)op * 9 * gn +
+                                                                     C.gmg_off[l] + id];
+                return c != (Real)0 ? (Real)1 / c : (Real)0;
+            };
+            auto own = [&](int l, auto &&f) {
+                const int Nl = gmg_level(C, l).Nn;
+                const int ts = (Nl + g - 1) / g;
+                const int a = min(rank * ts, Nl), b = min(a + ts, Nl);
+                for (int id = a + threadIdx.x; id < b; id += kThreads) f(id);
+            };
+            auto whole = [&](int l, auto &&f) {
+                const int Nl = gmg_level(C, l).Nn;
+                for (int id = threadIdx.x; id < Nl; id += kThreads) f(id);
+            };
+            // passes of one level
+            auto resid = [&](int l, int id) {  // lb = r - A la
+                Real d;
+                const Real Au = gmg_apply<Real>(C, B, op, l, id, la(l), d);
+                const Real rr = (l == 0 && B.mask[id]) ? (Real)0 : ldc(lr(l) + id) - Au;
+                stc(lb(l) + id, rr);
+            };
+            auto restr = [&](int l, int I) {  // r_{l+1} = P^T lb_l, la_{l+1} = omega D^{-1} r_{l+1}
+                const Real rc = gmg_restrict<Real>(C, l, I, lb(l));
+                stc(lr(l + 1) + I, rc);
+                stc(la(l + 1) + I, omega(l + 1) * dinv_at(l + 1, I) * rc);
+            };
+            auto prolong = [&](int l, int id) {  // lb = la + P la_{l+1}
+                Real v = ldc(la(l) + id);
+                if (l + 1 < C.gmg_L) v += gmg_prolong<Real>(C, l, id, la(l + 1));
+                if (l == 0 && B.mask[id]) v = 0;
+                stc(lb(l) + id, v);
+            };
+            auto smooth = [&](int l, int id, const Real *src, Real *dst) {  // dst = src + omega D^{-1}(r - A src)
+                Real d;
+                const Real Au = gmg_apply<Real>(C, B, op, l, id, src, d);
+                const Real r = ldc(lr(l) + id);
+                stc(dst + id, ldc(src + id) + omega(l) * dinv_at(l, id) * (r - Au));
+            };
+
+            // pointwise CG update and the first smoothing step u1 = omega D^{-1} r
+            own(0, [&](int id) {
+                Real r = ldc(R + id);
+                if (update) {
+                    const Real w = ldc(Wv + id), u = ldc(U + id);
+                    const Real sn = first ? w : w + (Real)be * ldc(Sv + id);
+                    const Real pn = first ? u : u + (Real)be * ldc(P + id);
+                    stc(Sv + id, sn);
+                    stc(P + id, pn);
+                    stc(X + id, ldc(X + id) + al * (double)pn);
+                    r = r - (Real)al * sn;
+                    stc(R + id, r);
+                }
+                stc(U + id, omega(0) * (Real)dinv0[id] * r);
+            });
+            const int Lv = C.gmg_L, Lg = C.gmg_Lg;
+            for (int l = 0; l < Lg; ++l) {
+                if (!barrier(false)) return false;
+                own(l, [&](int id) { resid(l, id); });
+                if (l + 1 < Lv) {
+                    if (!barrier(false)) return false;
+                    own(l + 1, [&](int I) { restr(l, I); });
+                }
+            }
+            if (Lg < Lv) {
+                if (!barrier(false)) return false;
+                if (rank == 0) {
+                    for (int l = Lg; l < Lv - 1; ++l) {
+                        whole(l, [&](int id) { resid(l, id); });
+                        __syncthreads();
+                        whole(l + 1, [&](int I) { restr(l, I); });
+                        __syncthreads();
+                    }
+                    const int lc = Lv - 1;
+                    for (int k = 0; k < C.gmg_tail_sweeps; ++k) {
+                        const Real *src = (k & 1) ? lb(lc) : la(lc);
+                        Real *dst = (k & 1) ? la(lc) : lb(lc);
+                        whole(lc, [&](int id) { smooth(lc, id, src, dst); });
+                        __syncthreads();
+                    }
+                    for (int l = Lv - 2; l >= Lg; --l) {
+                        whole(l, [&](int id) { prolong(l, id); });
+                        __syncthreads();
+                        whole(l, [&](int id) { smooth(l, id, lb(l), la(l)); });
+                        __syncthreads();
+                    }
+                }
+            }
+            for (int l = min(Lg, Lv) - 1; l >= 0; --l) {
+                if (!barrier(false)) return false;
+                own(l, [&](int id) { prolong(l, id); });
+                if (!barrier(false)) return false;
+                own(l, [&](int id) { smooth(l, id, lb(l), la(l)); });
+            }
+            // w = A u and the dot products
+            if (!barrier(false)) return false;
+            own(0, [&](int id) {
+                Real d;
+                const Real w = gmg_apply<Real>(C, B, op, 0, id, U, d);
+                stc(Wv + id, w);
+                const double u = ldc(U + id), r = ldc(R + id);
+                loc[0] += r * u;
+                loc[1] += u * (double)w;
+                if (nloc > 2) loc[2] += r * r;
+            });
+            return true;
+        };
+        (void)gmg_round;
 
         const bool is_adj = L.kind >= F_ADJ;
         const bool tracer = (rank == 0 && threadIdx.x == 0);
@@ -1029,6 +1160,9 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
+                } else if (C.gmg) {
+                    ok = gmg_round(st, false, true, 0.0, 0.0, loc, 2);
+                    if (!ok) break;
                 } else {
                 for (int t = rank; t < ntiles; t += g) {
                     const int a = t * TS;
@@ -1171,6 +1305,9 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
+                } else if (C.gmg) {
+                    ok = gmg_round(st, true, first, al, be, loc, 3);
+                    if (!ok) break;
                 } else {
                 const int cur = i0 & 1, nxt = cur ^ 1;
                 Real *Rc = Rb[cur], *Rn = Rb[nxt], *Wc = Wb[cur], *Wn = Wb[nxt];
@@ -1510,10 +1647,11 @@ __global__ void k_save_guess(const EngineDesc *__restrict__ D) {
 }
 
 // Copies n descriptors given by value into device memory (n <= kDescPerCopy).
-constexpr int kDescPerCopy = 4;
+constexpr int kDescPerCopy = 3;
 struct DescChunk {
     EngineDesc d[kDescPerCopy];
 };
+static_assert(sizeof(DescChunk) + 16 <= 4096, "kernel argument limit");
 __global__ void k_put_desc(DescChunk chunk, int n, EngineDesc *dst) {
     const int words = (int)(sizeof(EngineDesc) / sizeof(unsigned));
     for (int k = 0; k < n; ++k) {

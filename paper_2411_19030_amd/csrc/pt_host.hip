@@ -22,6 +22,17 @@ constexpr int kMaxBatchGroups = 512;   // worker groups of a multi-design launch
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+int env_int(const char *name, int dflt) {
+    const char *e = getenv(name);
+    return e ? atoi(e) : dflt;
+}
+
+double env_double(const char *name, double dflt) {
+    const char *e = getenv(name);
+    return e ? atof(e) : dflt;
+}
+
+
 struct Carver {
     size_t o = 0;
     size_t take(size_t bytes) {
@@ -47,8 +58,8 @@ bool valid_problem(const pt_problem *p) {
     if (!(p->kmin > 0.0) || !(p->k0 > 0.0) || !(p->cmin > 0.0) || !(p->c0 > 0.0)) return false;
     if (p->pk < 1.0 || p->pc < 1.0) return false;
     if (!p->q_t && !isfinite(p->q)) return false;
-    if ((p->precision != PT_FP64 && p->precision != PT_FP32_REFINE) || p->precond != PT_JACOBI ||
-        p->storage != PT_STORE_ALL)
+    if ((p->precision != PT_FP64 && p->precision != PT_FP32_REFINE) ||
+        (p->precond != PT_JACOBI && p->precond != PT_GMG) || p->storage != PT_STORE_ALL)
         return false;
     if (p->bc < 0 || p->bc > 3) return false;
     if (p->bc == PT_BC_MASK && !p->dirichlet_mask) return false;
@@ -59,12 +70,39 @@ bool valid_problem(const pt_problem *p) {
 }
 
 // ---------------------------------------------------------------------------
+// Multigrid hierarchy
+// ---------------------------------------------------------------------------
+
+// Levels of the vertex-centred hierarchy: halve both sides while they stay
+// even and the coarse grid keeps at least 2 elements per side.
+struct Hierarchy {
+    int L = 1;
+    long long off[kMaxLevels] = {0};
+    long long nodes = 0;  // nodes of levels 1..L-1
+};
+
+Hierarchy hierarchy(const pt_problem *p) {
+    Hierarchy h;
+    if (p->precond != PT_GMG) return h;
+    int nx = p->nx, ny = p->ny;
+    while (h.L < kMaxLevels && nx % 2 == 0 && ny % 2 == 0 && nx >= 4 && ny >= 4) {
+        nx /= 2;
+        ny /= 2;
+        h.off[h.L] = h.nodes;
+        h.nodes += (long long)(nx + 1) * (ny + 1);
+        ++h.L;
+    }
+    return h;
+}
+
+// ---------------------------------------------------------------------------
 // Workspace layout
 // ---------------------------------------------------------------------------
 
 // Arrays of one design.
 struct DesignLayout {
     size_t ctl, FL, kq, cm, dk, dc, dinv_f, dinv_c, mask, qt, zero;
+    size_t gA64, gA, gmg_g, gmg_w;
     size_t Gk, Gn, Gk_th, Gn_th, F_th, Uprev, Uprev_th, Ubuf, Ubuf_th, acc, accG;
     // multi-design cycles keep the cycle's state here
     size_t S, uT, uth, lam, gT, gth, gL;
@@ -94,6 +132,11 @@ void carve_design(Carver &c, const pt_problem *p, DesignLayout &L, bool batched)
     L.F_th = c.take(d * Nt1);
     L.acc = c.take(d * (size_t)p->n_slices * Ne);
     L.accG = c.take(d * Ne);
+    const Hierarchy h = hierarchy(p);
+    L.gA64 = c.take(d * 2 * 9 * (size_t)h.nodes + d);
+    L.gA = c.take(d * 2 * 9 * (size_t)h.nodes + d);
+    L.gmg_g = c.take(d * 2 * kMaxLevels);
+    L.gmg_w = c.take(d * 2 * kMaxLevels);
     if (!batched) {
         L.Uprev = c.take(d * Nt1 * Nn);
         L.Uprev_th = c.take(d * Nt1);
@@ -113,12 +156,13 @@ void carve_design(Carver &c, const pt_problem *p, DesignLayout &L, bool batched)
 // Launch-wide arrays of an engine launch.
 struct SharedLayout {
     size_t desc, bar, flags, partials, wg_group, groups, lanes, qhead, qslot, pool, trace, xch;
+    size_t gvec, gvec_stride;
     int max_lanes, max_groups, trace_stride, xch_stride;
     size_t pool_stride;
 };
 
 void carve_shared(Carver &c, SharedLayout &S, int n_designs, int max_lanes, int max_groups,
-                  size_t pool_stride, int trace_stride, int xch_stride) {
+                  size_t pool_stride, int trace_stride, int xch_stride, size_t gmg_nodes) {
     S.max_lanes = max_lanes;
     S.max_groups = max_groups;
     S.trace_stride = trace_stride;
@@ -136,6 +180,9 @@ void carve_shared(Carver &c, SharedLayout &S, int n_designs, int max_lanes, int 
     S.pool = c.take(sizeof(double) * (size_t)max_groups * kVecsPerLane * pool_stride);
     S.trace = c.take(sizeof(unsigned long long) * (size_t)max_lanes * trace_stride);
     S.xch = c.take(sizeof(double) * (size_t)kMaxGrid * 12 * xch_stride);
+    // multigrid level vectors r, u_a, u_b of levels >= 1 per group
+    S.gvec_stride = 3 * gmg_nodes;
+    S.gvec = c.take(sizeof(double) * (size_t)max_groups * S.gvec_stride + sizeof(double));
 }
 
 int trace_stride_of(const pt_problem *p) {
@@ -155,7 +202,7 @@ Layout layout(const pt_problem *p) {
     carve_design(c, p, L.d, false);
     const int max_lanes = 2 * p->n_slices + 2;
     carve_shared(c, L.s, 1, max_lanes, max_lanes, (size_t)(p->nx + 1) * (p->ny + 1),
-                 trace_stride_of(p), p->nx + 2);
+                 trace_stride_of(p), p->nx + 2, (size_t)hierarchy(p).nodes);
     L.total = c.o;
     return L;
 }
@@ -173,15 +220,16 @@ BatchLayout batch_layout(int n, const pt_problem *probs) {
     L.d.resize(n);
     Carver c;
     int lanes = 0, tstride = TR_HDR, xs = 2;
-    size_t max_nn = 1;
+    size_t max_nn = 1, max_gn = 0;
     for (int k = 0; k < n; ++k) {
         carve_design(c, &probs[k], L.d[k], true);
+        max_gn = std::max(max_gn, (size_t)hierarchy(&probs[k]).nodes);
         lanes += 2 * probs[k].n_slices + 2;
         tstride = std::max(tstride, trace_stride_of(&probs[k]));
         xs = std::max(xs, probs[k].nx + 2);
         max_nn = std::max(max_nn, (size_t)(probs[k].nx + 1) * (probs[k].ny + 1));
     }
-    carve_shared(c, L.s, n, lanes, kMaxBatchGroups, max_nn, tstride, xs);
+    carve_shared(c, L.s, n, lanes, kMaxBatchGroups, max_nn, tstride, xs, max_gn);
     L.max_nn = max_nn;
     L.total = c.o;
     return L;
@@ -236,6 +284,19 @@ Consts make_consts(const pt_problem *p) {
     C.q = p->q;
     C.bc_rule = p->bc;
     C.has_qt = p->q_t ? 1 : 0;
+    const Hierarchy h = hierarchy(p);
+    C.gmg = p->precond == PT_GMG ? 1 : 0;
+    C.gmg_L = h.L;
+    for (int l = 0; l < kMaxLevels; ++l) C.gmg_off[l] = h.off[l];
+    C.gmg_nodes = h.nodes;
+    // levels with more nodes than this are smoothed by the whole group
+    const long long tail = env_int("PT_GMG_TAIL", 4096);
+    C.gmg_Lg = 0;
+    for (int l = 0; l < h.L; ++l)
+        if ((long long)((p->nx >> l) + 1) * ((p->ny >> l) + 1) > tail) C.gmg_Lg = l + 1;
+    C.gmg_tail_sweeps = 2 * std::max(1, env_int("PT_GMG_SWEEPS", 16));
+    C.gmg_omega = env_double("PT_GMG_OMEGA", 1.3);
+    if (C.gmg) C.extrap = 0;
     return C;
 }
 
@@ -267,6 +328,12 @@ Bufs make_bufs(void *ws, const DesignLayout &L, const SharedLayout &S, int desig
     B.F_th = at<double>(ws, L.F_th);
     B.acc = at<double>(ws, L.acc);
     B.accG = at<double>(ws, L.accG);
+    B.gA64 = at<double>(ws, L.gA64);
+    B.gA = at<void>(ws, L.gA);
+    B.gmg_g = at<double>(ws, L.gmg_g);
+    B.gmg_w = at<double>(ws, L.gmg_w);
+    B.gvec = at<void>(ws, S.gvec);
+    B.gvec_stride = S.gvec_stride;
     return B;
 }
 
@@ -342,6 +409,16 @@ int setup_designs(int n, const pt_problem *probs, const std::vector<EngineDesc> 
     if (copied) PT_TRY(hip_ok(hipStreamSynchronize(stream)));
     hipLaunchKernelGGL(k_setup_design, dim3(256, n), dim3(256), 0, stream, D);
     hipLaunchKernelGGL(k_diag, dim3(256, n), dim3(256), 0, stream, D);
+    int maxL = 1;
+    for (const auto &E : hd)
+        if (E.C.gmg) maxL = std::max(maxL, E.C.gmg_L);
+    if (maxL > 1 || std::any_of(hd.begin(), hd.end(), [](const EngineDesc &E) { return E.C.gmg; })) {
+        hipLaunchKernelGGL(k_gmg_reset, dim3(n), dim3(64), 0, stream, D);
+        hipLaunchKernelGGL(k_gmg_level0, dim3(256, n), dim3(256), 0, stream, D);
+        for (int l = 0; l + 1 < maxL; ++l)
+            hipLaunchKernelGGL(k_gmg_rap, dim3(256, n), dim3(128), 0, stream, D, l);
+        hipLaunchKernelGGL(k_gmg_omega, dim3(n), dim3(64), 0, stream, D);
+    }
     return launch_check();
 }
 
@@ -358,15 +435,6 @@ int device_info(Device &d) {
     return PT_OK;
 }
 
-int env_int(const char *name, int dflt) {
-    const char *e = getenv(name);
-    return e ? atoi(e) : dflt;
-}
-
-double env_double(const char *name, double dflt) {
-    const char *e = getenv(name);
-    return e ? atof(e) : dflt;
-}
 
 // LDS doubles of the engine for tile size ts: two node windows (ts + 2H) and
 // two element windows ((ts-1)/W + 3 rows of nx+2 elements).
@@ -523,7 +591,7 @@ int run_engine(const Consts &C, const EngineDesc *D, std::vector<LanePlan> &plan
     const int res_npt_max = std::max(1, std::min(8, env_int("PT_RES_NPT", 8)));
     const int g_min = (C.Nn + NT * res_npt_max - 1) / (NT * res_npt_max);
     bool resident = env_int("PT_RESIDENT", 1) != 0 && g_min <= grid / 4 &&
-                    (C.Nn + g_min - 1) / g_min >= H;
+                    (C.Nn + g_min - 1) / g_min >= H && !C.gmg;
     // a tile must be at least one halo (H nodes) long
     const int max_wg_per_lane = std::max(1, C.Nn / H);
 
@@ -770,6 +838,7 @@ int run_batched_engine(std::vector<EngineDesc> &hd, const pt_batch_tuning &T, bo
         const Consts &C = E.C;
         const int H = C.W + 1;
         int t0, t1;
+        if (T.resident && C.gmg) return PT_EINVAL;
         if (T.resident) {
             t0 = (C.Nn + T.fine_wgs - 1) / T.fine_wgs;
             t1 = (C.Nn + T.sweep_wgs - 1) / T.sweep_wgs;

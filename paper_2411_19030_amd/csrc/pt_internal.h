@@ -14,6 +14,7 @@ constexpr int kMaxGroups = 1024;    // groups per engine launch
 constexpr int kMaxGroup = 1024;     // workgroups per lane group (partials slots)
 constexpr int kVecsPerLane = 10;    // x, p, r[2], w[2], s[2], tp, tq
 constexpr int kMaxFlags = 4 * 4096; // dependency flags per launch
+constexpr int kMaxLevels = 16;      // multigrid levels (level 0 = the element grid)
 
 // Lane kinds: a lane is a sequence of linear solves executed by one group of
 // workgroups; lanes of one launch run concurrently and meet only through flags.
@@ -83,6 +84,13 @@ struct Consts {
     double k0, kmin, pk, c0, cmin, pc, q;
     int bc_rule;  // 0 centre of left edge, 1 centre of bottom edge, 2 none, 3 caller mask
     int has_qt;   // q(t) was copied in by the host
+    // geometric multigrid preconditioner (gmg != 0): levels l = 0..gmg_L-1 with
+    // nx >> l by ny >> l elements; levels < gmg_Lg are smoothed by the whole
+    // group, the rest (and the coarsest solve) by one workgroup
+    int gmg, gmg_L, gmg_Lg, gmg_tail_sweeps;
+    double gmg_omega;                 // smoother damping times the Gershgorin bound
+    long long gmg_off[kMaxLevels];    // node offset of level l >= 1 in the level arrays
+    long long gmg_nodes;              // sum of the nodes of levels 1..L-1
 };
 
 // Pointers of one design: its workspace arrays and the caller's arrays.
@@ -124,6 +132,15 @@ struct Bufs {
     // multi-design cycles: where the corrected u and lambda are kept as the
     // next cycle's guesses
     double *save_T, *save_th, *save_L;
+    // multigrid: Galerkin stencils of levels >= 1 for the fine (dt) and coarse
+    // (dtau) operators, [2][9][gmg_nodes] in FP64 and in the CG precision;
+    // per operator and level the Gershgorin bound of D^{-1} A and the damping
+    double *gA64;
+    void *gA;
+    double *gmg_g;         // [2][kMaxLevels]
+    double *gmg_w;         // [2][kMaxLevels]
+    void *gvec;            // group level vectors [groups][3][gmg_nodes] (CG precision)
+    size_t gvec_stride;    // elements per group
 };
 
 struct LaunchInfo {
