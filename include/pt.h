@@ -81,7 +81,10 @@ typedef struct pt_problem {
                                /* with FP64 dot products, FP64 x and FP64 residual refinement     */
     int32_t precond;           /* PT_JACOBI, or PT_GMG: geometric multigrid V(1,1) cycle (Galerkin */
                                /* coarse operators, bilinear transfer, damped Jacobi smoothing)   */
-    int32_t storage;           /* PT_STORE_ALL (only value accepted by this build)                */
+    int32_t storage;           /* PT_STORE_ALL: S holds every fine state T_1..T_{N_t}; or          */
+                               /* PT_CHECKPOINT: S holds T_{Mn} (rows 0..N_tau-1, n = row+1) and  */
+                               /* T_{Mn+1} (rows N_tau..2N_tau-1, n = row-N_tau) and the adjoint  */
+                               /* pass recomputes the other fine states of each slice             */
     int32_t bc;                /* PT_BC_*                                                         */
     const uint8_t *dirichlet_mask; /* HOST, (nx+1)(ny+1) bytes, read when bc == PT_BC_MASK        */
 } pt_problem;
@@ -103,6 +106,10 @@ size_t pt_workspace_bytes(const pt_problem *prob);
 /* Host-side argument check only; returns PT_OK or PT_EINVAL. */
 int pt_validate(const pt_problem *prob);
 
+/* Bytes of the state array S: N_t rows of N_n doubles (PT_STORE_ALL) or 2 N_tau
+ * rows (PT_CHECKPOINT); 0 if the problem is invalid. */
+size_t pt_state_bytes(const pt_problem *prob);
+
 /*
  * Primal pass: Parareal for u_n = (T_{Mn}, theta_{Mn}), n = 0..N_tau (Sec. 4.4,
  * Eq. 4.2 correction applied to T and theta; G_pri = Alg. 1 with dt -> dtau,
@@ -112,7 +119,8 @@ int pt_validate(const pt_problem *prob);
  *                                   coarse sweep u^0_{n+1} = G(u^0_n) (Sec. 5.2)
  *   guess_theta  [N_tau+1]          theta part of the guess; NULL iff guess_T is NULL
  *   S            [N_t][N_n]         out: T_1..T_{N_t}; coarse slots T_{Mn} corrected, the other
- *                                   slots the fine states of the last F sweep (Sec. 4.3)
+ *                                   slots the fine states of the last F sweep (Sec. 4.3);
+ *                                   with PT_CHECKPOINT [2 N_tau][N_n] as described at `storage`
  *   uT_out       [N_tau+1][N_n]     out: corrected T_{Mn} (the next cycle's guess); may be NULL
  *   utheta_out   [N_tau+1]          out: corrected theta_{Mn}; may be NULL
  *   Theta_out    [1]                out: Theta = theta_{N_t} estimate (device scalar)
@@ -199,7 +207,7 @@ typedef struct pt_batch_tuning {
 } pt_batch_tuning;
 
 /* Workspace bytes of a batch of n designs; 0 if any problem is invalid, the
- * precisions differ, or a design has iterations != 1. */
+ * precisions differ, or a design has iterations != 1 or storage != PT_STORE_ALL. */
 size_t pt_batched_workspace_bytes(int n, const pt_problem *probs);
 
 /* The built-in worker shapes for n designs (environment overrides included). */

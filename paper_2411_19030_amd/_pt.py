@@ -22,7 +22,7 @@ PT_FP64, PT_FP32_REFINE = 0, 1
 PT_JACOBI, PT_GMG = 0, 1
 PT_STORE_ALL, PT_CHECKPOINT = 0, 1
 
-EXPORTS = ["pt_workspace_bytes", "pt_validate", "pt_parareal_forward", "pt_parareal_adjoint",
+EXPORTS = ["pt_workspace_bytes", "pt_state_bytes", "pt_validate", "pt_parareal_forward", "pt_parareal_adjoint",
            "pt_sensitivities", "pt_query_status", "pt_query_trace", "pt_strerror",
            "pt_batched_workspace_bytes", "pt_batch_default_tuning", "pt_parareal_batched",
            "pt_batched_status", "pt_autotune_batched"]
@@ -90,6 +90,8 @@ def load_library(path: str = LIB_PATH):
     lib.pt_workspace_bytes.restype = ctypes.c_size_t
     lib.pt_validate.argtypes = [P]
     lib.pt_validate.restype = ctypes.c_int
+    lib.pt_state_bytes.argtypes = [P]
+    lib.pt_state_bytes.restype = ctypes.c_size_t
     lib.pt_parareal_forward.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.pt_parareal_forward.restype = ctypes.c_int
     lib.pt_parareal_adjoint.argtypes = [P, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
@@ -215,6 +217,10 @@ def pt_validate(prob: Problem) -> int:
 
 def pt_workspace_bytes(prob: Problem) -> int:
     return int(load_library().pt_workspace_bytes(ctypes.byref(prob.to_c())))
+
+
+def pt_state_bytes(prob: Problem) -> int:
+    return int(load_library().pt_state_bytes(ctypes.byref(prob.to_c())))
 
 
 def pt_parareal_forward(prob: Problem, rho, guess_T, guess_theta, S, uT_out, utheta_out,

@@ -327,6 +327,22 @@ __device__ __forceinline__ double elem_c(const Consts &C, double l0, double l1, 
     return C.cm_unit * (4.0 * self + 2.0 * adj + dg);
 }
 
+// Primal steps a fine adjoint lane recomputes before its adjoint steps when
+// only checkpoints are stored: T_{M(n-1)+2} .. T_{Mn-1} of its slice.
+__device__ __forceinline__ int ck_recompute(const Consts &C) {
+    return C.ckpt ? max(C.M - 2, 0) : 0;
+}
+
+// The stored state T_j (1 <= j <= N_t). With checkpoints, T_{Mn} lives in row
+// n-1 and T_{Mn+1} in row N_tau+n of S; the other states of a slice exist only
+// in the recomputing lane's scratch (nullptr elsewhere).
+__device__ __forceinline__ double *srow(const Consts &C, const Bufs &B, int j, double *scratch) {
+    if (!C.ckpt) return B.S + (size_t)(j - 1) * C.Nn;
+    if (j % C.M == 0) return B.S + (size_t)(j / C.M - 1) * C.Nn;
+    if ((j - 1) % C.M == 0) return B.S + (size_t)(C.Ntau + (j - 1) / C.M) * C.Nn;
+    return scratch ? scratch + (size_t)((j - 1) % C.M - 1) * C.Nn : nullptr;
+}
+
 // Per-lane, per-step description derived identically in every workgroup.
 struct StepInfo {
     bool fine;        // delta = dt (else dtau)
@@ -339,12 +355,14 @@ struct StepInfo {
     bool wait;        // a flag must be awaited before INIT
     int wait_idx;
     bool extrap;      // x0 = 2 x - tq (two previous states of a fine lane)
+    bool recompute;   // a primal step recomputed inside a fine adjoint lane
+    int s_adj;        // adjoint step index of a fine adjoint lane (step - recomputed steps)
 };
 
 __device__ __forceinline__ int lane_steps(const Consts &C, int kind) {
     switch (kind) {
-        case F_PRI:
-        case F_ADJ: return C.M;
+        case F_PRI: return C.M;
+        case F_ADJ: return C.M + ck_recompute(C);
         case GK_PRI:
         case GK_ADJ: return 1;
         case SWEEP_PRI:
@@ -367,6 +385,8 @@ __device__ StepInfo step_info(const Consts &C, const Bufs &B, const LaunchInfo &
     st.wait_idx = 0;
     st.jprev = 0;
     st.extrap = C.extrap && (L.kind == F_PRI || L.kind == F_ADJ) && s >= 2;
+    st.recompute = false;
+    st.s_adj = 0;
     switch (L.kind) {
         case F_PRI: {
             const int n = L.slice;
@@ -424,12 +444,32 @@ __device__ StepInfo step_info(const Consts &C, const Bufs &B, const LaunchInfo &
             st.adjoint = false;
             st.n = n;
             st.j = C.M * (n + 1);
-            st.tp_src = (n == 1) ? B.S + (size_t)(C.M - 1) * Nn : tpbuf;
+            st.tp_src = (n == 1) ? srow(C, B, C.M, nullptr) : tpbuf;
             st.x0_src = B.Gk + (size_t)n * Nn;
             break;
         }
         case F_ADJ: {
             const int n = L.slice;
+            const int rc = ck_recompute(C);
+            if (s < rc) {
+                // recompute T_{M(n-1)+s+2} from the stored first state of the slice
+                st.fine = true;
+                st.adjoint = false;
+                st.recompute = true;
+                st.n = n;
+                st.j = C.M * (n - 1) + s + 2;
+                if (s == 0) {
+                    const double *src = srow(C, B, st.j - 1, nullptr);
+                    st.tp_src = src;
+                    st.x0_src = src;
+                } else {
+                    st.tp_src = tpbuf;
+                    st.x0_src = nullptr;
+                }
+                break;
+            }
+            s -= rc;
+            st.s_adj = s;
             st.fine = true;
             st.adjoint = true;
             st.n = n;
@@ -508,19 +548,26 @@ struct Ctl {
 
 // Per-element sensitivity term lambda^T (dk K0 T + dc C0 (T - Tp)/delta) of the
 // element whose lower-left node is id (Eq. 4.8 summand for one element).
+// States written earlier in the same launch by other workgroups (recomputed
+// checkpoint states, coh = true) are read with device-coherent loads.
+__device__ __forceinline__ double ld_state(const double *row, int q, bool coh) {
+    return coh ? ldc(row + q) : row[q];
+}
+
 __device__ __forceinline__ double sens_term(const Consts &C, const Bufs &B, const LaunchInfo &I,
                                             int id, int e, double l0, double l1, double l2,
                                             double l3, const double *Tr, const double *Tp,
-                                            double inv_delta) {
-    const double t0 = Tr[id], t1 = Tr[id + 1], t2 = Tr[id + C.W + 1], t3 = Tr[id + C.W];
+                                            double inv_delta, bool coh) {
+    const double t0 = ld_state(Tr, id, coh), t1 = ld_state(Tr, id + 1, coh),
+                 t2 = ld_state(Tr, id + C.W + 1, coh), t3 = ld_state(Tr, id + C.W, coh);
     double term = B.dk[e] * elem_k(C, l0, l1, l2, l3, t0, t1, t2, t3);
     if (I.has_dc) {
         double p0 = 0, p1 = 0, p2 = 0, p3 = 0;
         if (Tp) {
-            p0 = Tp[id];
-            p1 = Tp[id + 1];
-            p2 = Tp[id + C.W + 1];
-            p3 = Tp[id + C.W];
+            p0 = ld_state(Tp, id, coh);
+            p1 = ld_state(Tp, id + 1, coh);
+            p2 = ld_state(Tp, id + C.W + 1, coh);
+            p3 = ld_state(Tp, id + C.W, coh);
         }
         term += B.dc[e] * inv_delta *
                 elem_c(C, l0, l1, l2, l3, t0 - p0, t1 - p1, t2 - p2, t3 - p3);
@@ -707,6 +754,8 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
         const int ntiles = (C.Nn + TS - 1) / TS;
 
         double *X = group_vec(B, G.vec, V_X);
+        // recomputed fine states of a checkpointed fine adjoint lane
+        double *LSc = (C.ckpt && L.kind == F_ADJ) ? B.ck + (size_t)G.vec * B.ck_stride : nullptr;
         Real *P = reinterpret_cast<Real *>(group_vec(B, G.vec, V_P));
         double *TP = group_vec(B, G.vec, V_TP);
         double *TQ = group_vec(B, G.vec, V_TQ);
@@ -789,6 +838,8 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                              double *loc, int nloc) -> bool {
             const int op = st.fine ? 0 : 1;
             const double *dinv0 = st.fine ? B.dinv_f : B.dinv_c;
+            // level 0: r = R, pre-smoothed u1 = U, the round's result u = UB0;
+            // levels >= 1 in the group slot of the level arrays
             Real *R = Rb[0], *Wv = Wb[0], *Sv = Sb[0], *U = Rb[1], *UB0 = Wb[1];
             Real *GV = reinterpret_cast<Real *>(B.gvec) + (size_t)G.vec * B.gvec_stride;
             const size_t gn = (size_t)C.gmg_nodes;
@@ -796,54 +847,146 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
             auto la = [&](int l) -> Real * { return l == 0 ? U : GV + gn + C.gmg_off[l]; };
             auto lb = [&](int l) -> Real * { return l == 0 ? UB0 : GV + 2 * gn + C.gmg_off[l]; };
             auto omega = [&](int l) -> Real { return (Real)B.gmg_w[op * kMaxLevels + l]; };
-            // D^{-1} of level l at id: level 0 from the Jacobi arrays (0 on
-            // Dirichlet nodes), coarse levels from the stencil centre
-            auto dinv_at = [&](int l, int id) -> Real {
-                if (l == 0) return (Real)dinv0[id];
-                const Real c = reinterpret_cast<const Real *>(B.gA)[(size_t)op * 9 * gn +
-                                                                     C.gmg_off[l] + id];
-                return c != (Real)0 ? (Real)1 / c : (Real)0;
+            Real *LV = reinterpret_cast<Real *>(lds);  // staged operand window
+            // assembled stencil row of level l (CG precision, zero rows on
+            // Dirichlet nodes of level 0)
+            auto row = [&](int l, int id, Real(&a)[9]) {
+                const Real *A = l == 0 ? reinterpret_cast<const Real *>(B.gA0) +
+                                             (size_t)op * 9 * C.Nn + id
+                                       : reinterpret_cast<const Real *>(B.gA) +
+                                             (size_t)op * 9 * gn + C.gmg_off[l] + id;
+                const size_t st9 = l == 0 ? (size_t)C.Nn : gn;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) a[k] = A[(size_t)k * st9];
             };
-            auto own = [&](int l, auto &&f) {
+            auto apply_lds = [&](const Real(&a)[9], int li, int W) -> Real {
+                return a[0] * LV[li] + a[1] * LV[li + 1] + a[2] * LV[li - 1] + a[3] * LV[li + W] +
+                       a[4] * LV[li - W] + a[5] * LV[li + W + 1] + a[6] * LV[li + W - 1] +
+                       a[7] * LV[li - W + 1] + a[8] * LV[li - W - 1];
+            };
+            auto dinv_row = [&](int l, int id, const Real(&a)[9]) -> Real {
+                if (l == 0) return (Real)dinv0[id];
+                return a[0] != (Real)0 ? (Real)1 / a[0] : (Real)0;
+            };
+            // Nodes [a, b) of level l in LDS-sized chunks. The chunk's operand
+            // window (one grid row and one node of halo on each side) is staged
+            // with coalesced device-coherent loads: value(id) = v[id], plus the
+            // bilinear prolongation of e when e is given (0 on Dirichlet nodes
+            // of level 0). Then, kU nodes per thread at a time, ld(id) issues a
+            // node's loads and op(id, li, W, vals) computes and stores.
+            auto staged = [&](int l, const Real *v, const Real *e, int a, int b, auto &&ld,
+                              auto &&opf) {
+                const Lvl Lv = gmg_level(C, l);
+                const int Hl = Lv.W + 1;
+                for (int c0 = a; c0 < b; c0 += C.gmg_chunk) {
+                    const int c1 = min(c0 + C.gmg_chunk, b);
+                    const int lo = c0 - Hl, len = (c1 - c0) + 2 * Hl;
+                    lds_sync();
+                    for (int q0 = threadIdx.x; q0 < len; q0 += kThreads * kU) {
+                        Real vv[kU];
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int q = q0 + u * kThreads;
+                            const int id = lo + q;
+                            Real x = 0;
+                            if (q < len && id >= 0 && id < Lv.Nn) {
+                                x = ldc(v + id);
+                                if (e) x += gmg_prolong<Real>(C, l, id, e);
+                                if (l == 0 && B.mask[id]) x = 0;
+                            }
+                            vv[u] = x;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int q = q0 + u * kThreads;
+                            if (q < len) LV[q] = vv[u];
+                        }
+                    }
+                    lds_sync();
+                    for (int id0 = c0 + threadIdx.x; id0 < c1; id0 += kThreads * kU) {
+                        decltype(ld(0)) vals[kU];
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int id = id0 + u * kThreads;
+                            if (id < c1) vals[u] = ld(id);
+                        }
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int id = id0 + u * kThreads;
+                            if (id < c1) opf(id, id - lo, Lv.W, vals[u]);
+                        }
+                    }
+                }
+            };
+            auto own_range = [&](int l, int &a, int &b) {
                 const int Nl = gmg_level(C, l).Nn;
                 const int ts = (Nl + g - 1) / g;
-                const int a = min(rank * ts, Nl), b = min(a + ts, Nl);
+                a = min(rank * ts, Nl);
+                b = min(a + ts, Nl);
+            };
+            auto own = [&](int l, auto &&f) {
+                int a, b;
+                own_range(l, a, b);
                 for (int id = a + threadIdx.x; id < b; id += kThreads) f(id);
             };
             auto whole = [&](int l, auto &&f) {
                 const int Nl = gmg_level(C, l).Nn;
                 for (int id = threadIdx.x; id < Nl; id += kThreads) f(id);
             };
-            // passes of one level
-            auto resid = [&](int l, int id) {  // lb = r - A la
-                Real d;
-                const Real Au = gmg_apply<Real>(C, B, op, l, id, la(l), d);
-                const Real rr = (l == 0 && B.mask[id]) ? (Real)0 : ldc(lr(l) + id) - Au;
-                stc(lb(l) + id, rr);
+            // between passes of the single-workgroup levels: every wave's
+            // device-coherent stores must have landed before another wave of
+            // the workgroup reads them back from L2
+            auto wg_sync = [&]() {
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                asm volatile("" ::: "memory");
+            };
+            struct RowR {
+                Real a[9];
+                Real r;
+            };
+            // lb_l = r_l - A_l la_l on nodes [a, b)
+            auto resid_pass = [&](int l, int a, int b) {
+                staged(l, la(l), nullptr, a, b,
+                       [&](int id) {
+                           RowR x;
+                           row(l, id, x.a);
+                           x.r = ldc(lr(l) + id);
+                           return x;
+                       },
+                       [&](int id, int li, int W, const RowR &x) {
+                           stc(lb(l) + id, x.r - apply_lds(x.a, li, W));
+                       });
+            };
+            // dst = v + omega D^{-1} (r - A v), v = src (+ P e) staged
+            auto smooth_pass = [&](int l, const Real *src, const Real *e, Real *dst, int a, int b) {
+                staged(l, src, e, a, b,
+                       [&](int id) {
+                           RowR x;
+                           row(l, id, x.a);
+                           x.r = ldc(lr(l) + id);
+                           return x;
+                       },
+                       [&](int id, int li, int W, const RowR &x) {
+                           stc(dst + id, LV[li] + omega(l) * dinv_row(l, id, x.a) *
+                                                      (x.r - apply_lds(x.a, li, W)));
+                       });
             };
             auto restr = [&](int l, int I) {  // r_{l+1} = P^T lb_l, la_{l+1} = omega D^{-1} r_{l+1}
                 const Real rc = gmg_restrict<Real>(C, l, I, lb(l));
                 stc(lr(l + 1) + I, rc);
-                stc(la(l + 1) + I, omega(l + 1) * dinv_at(l + 1, I) * rc);
-            };
-            auto prolong = [&](int l, int id) {  // lb = la + P la_{l+1}
-                Real v = ldc(la(l) + id);
-                if (l + 1 < C.gmg_L) v += gmg_prolong<Real>(C, l, id, la(l + 1));
-                if (l == 0 && B.mask[id]) v = 0;
-                stc(lb(l) + id, v);
-            };
-            auto smooth = [&](int l, int id, const Real *src, Real *dst) {  // dst = src + omega D^{-1}(r - A src)
-                Real d;
-                const Real Au = gmg_apply<Real>(C, B, op, l, id, src, d);
-                const Real r = ldc(lr(l) + id);
-                stc(dst + id, ldc(src + id) + omega(l) * dinv_at(l, id) * (r - Au));
+                const Real c = reinterpret_cast<const Real *>(B.gA)[(size_t)op * 9 * gn +
+                                                                     C.gmg_off[l + 1] + I];
+                stc(la(l + 1) + I, c != (Real)0 ? omega(l + 1) * rc / c : (Real)0);
             };
 
-            // pointwise CG update and the first smoothing step u1 = omega D^{-1} r
+            // pointwise CG update (u of the previous round is in UB0) and the
+            // first smoothing step u1 = omega D^{-1} r
             own(0, [&](int id) {
                 Real r = ldc(R + id);
                 if (update) {
-                    const Real w = ldc(Wv + id), u = ldc(U + id);
+                    const Real w = ldc(Wv + id), u = ldc(UB0 + id);
                     const Real sn = first ? w : w + (Real)be * ldc(Sv + id);
                     const Real pn = first ? u : u + (Real)be * ldc(P + id);
                     stc(Sv + id, sn);
@@ -857,7 +1000,11 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
             const int Lv = C.gmg_L, Lg = C.gmg_Lg;
             for (int l = 0; l < Lg; ++l) {
                 if (!barrier(false)) return false;
-                own(l, [&](int id) { resid(l, id); });
+                {
+                    int a, b;
+                    own_range(l, a, b);
+                    resid_pass(l, a, b);
+                }
                 if (l + 1 < Lv) {
                     if (!barrier(false)) return false;
                     own(l + 1, [&](int I) { restr(l, I); });
@@ -867,43 +1014,54 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                 if (!barrier(false)) return false;
                 if (rank == 0) {
                     for (int l = Lg; l < Lv - 1; ++l) {
-                        whole(l, [&](int id) { resid(l, id); });
-                        __syncthreads();
+                        resid_pass(l, 0, gmg_level(C, l).Nn);
+                        wg_sync();
                         whole(l + 1, [&](int I) { restr(l, I); });
-                        __syncthreads();
+                        wg_sync();
                     }
+                    // coarsest level: an odd number of damped Jacobi sweeps, the
+                    // result ends in lb
                     const int lc = Lv - 1;
                     for (int k = 0; k < C.gmg_tail_sweeps; ++k) {
                         const Real *src = (k & 1) ? lb(lc) : la(lc);
                         Real *dst = (k & 1) ? la(lc) : lb(lc);
-                        whole(lc, [&](int id) { smooth(lc, id, src, dst); });
-                        __syncthreads();
+                        smooth_pass(lc, src, nullptr, dst, 0, gmg_level(C, lc).Nn);
+                        wg_sync();
                     }
                     for (int l = Lv - 2; l >= Lg; --l) {
-                        whole(l, [&](int id) { prolong(l, id); });
-                        __syncthreads();
-                        whole(l, [&](int id) { smooth(l, id, lb(l), la(l)); });
-                        __syncthreads();
+                        smooth_pass(l, la(l), lb(l + 1), lb(l), 0, gmg_level(C, l).Nn);
+                        wg_sync();
                     }
                 }
             }
+            // up: lb_l = v + omega D^{-1}(r - A v) with v = la_l + P lb_{l+1}
             for (int l = min(Lg, Lv) - 1; l >= 0; --l) {
                 if (!barrier(false)) return false;
-                own(l, [&](int id) { prolong(l, id); });
-                if (!barrier(false)) return false;
-                own(l, [&](int id) { smooth(l, id, lb(l), la(l)); });
+                int a, b;
+                own_range(l, a, b);
+                smooth_pass(l, la(l), l + 1 < Lv ? lb(l + 1) : nullptr, lb(l), a, b);
             }
             // w = A u and the dot products
             if (!barrier(false)) return false;
-            own(0, [&](int id) {
-                Real d;
-                const Real w = gmg_apply<Real>(C, B, op, 0, id, U, d);
-                stc(Wv + id, w);
-                const double u = ldc(U + id), r = ldc(R + id);
-                loc[0] += r * u;
-                loc[1] += u * (double)w;
-                if (nloc > 2) loc[2] += r * r;
-            });
+            {
+                int a, b;
+                own_range(0, a, b);
+                staged(0, UB0, nullptr, a, b,
+                       [&](int id) {
+                           RowR x;
+                           row(0, id, x.a);
+                           x.r = ldc(R + id);
+                           return x;
+                       },
+                       [&](int id, int li, int W, const RowR &x) {
+                           const Real w = apply_lds(x.a, li, W);
+                           stc(Wv + id, w);
+                           const double u = LV[li], r = x.r;
+                           loc[0] += r * u;
+                           loc[1] += u * (double)w;
+                           if (nloc > 2) loc[2] += r * r;
+                       });
+            }
             return true;
         };
         (void)gmg_round;
@@ -982,7 +1140,99 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                 const bool x0copy = first_entry && (st.x0_src != nullptr || ext);
                 const double *xs = (first_entry && st.x0_src != nullptr) ? st.x0_src : X;
                 const double *ts = st.tp_src;
+                // first solve of the lane's own kind (a fine adjoint lane's first
+                // adjoint step follows its recomputed primal steps)
+                const bool lane_start =
+                    first_entry && (L.kind == F_ADJ ? (!st.recompute && st.s_adj == 0)
+                                                    : c.step == 0);
                 double loc[2] = {0.0, 0.0};  // ||b||^2, ||r0||^2
+                // first step of a lane: zero sensitivity sums, publish copies
+                // (tpv: the node's value of the C/delta operand, 0 on Dirichlet nodes)
+                auto lane_start_work = [&](int id, int i, int j, double tpv) {
+                    if (L.kind == F_ADJ) {
+                        if (i < C.nx && j < C.ny)
+                            B.acc[(size_t)(L.slice - 1) * C.Ne + j * C.nx + i] = 0.0;
+                    } else if (L.kind == SWEEP_ADJ) {
+                        if (i < C.nx && j < C.ny) B.accG[j * C.nx + i] = 0.0;
+                        B.out_L[(size_t)C.Ntau * C.Nn + id] = 0.0;
+                        B.out_L[(size_t)(C.Ntau - 1) * C.Nn + id] = tpv;
+                    } else if (L.kind == SWEEP_PRI) {
+                        B.out_T[(size_t)C.Nn + id] = tpv;
+                    }
+                };
+                if (NPT == 0 && C.gmg) {
+                    // multigrid lanes: the node ranges the multigrid rounds own, in
+                    // chunks whose operand windows (C/delta operand and x0, one
+                    // grid row of halo) are staged in LDS; rows of very wide
+                    // grids do not fit the LDS tiles of the Jacobi path
+                    const int ts0 = (C.Nn + g - 1) / g;
+                    const int a0 = min(rank * ts0, C.Nn), b0 = min(a0 + ts0, C.Nn);
+                    auto ldm = [&](const double *v, int q) -> double {
+                        return (q >= 0 && q < C.Nn && !B.mask[q]) ? ldc(v + q) : 0.0;
+                    };
+                    const int CHI = C.gmg_chunk_init;
+                    double *WT = lds;                       // C/delta operand window
+                    double *WX = lds + CHI + 2 * H;         // x0 window
+                    for (int c0 = a0; c0 < b0; c0 += CHI) {
+                        const int c1 = min(c0 + CHI, b0);
+                        const int lo = c0 - H, len = (c1 - c0) + 2 * H;
+                        lds_sync();
+                        for (int q0 = threadIdx.x; q0 < len; q0 += kThreads * kU) {
+                            double vt[kU], vx[kU];
+#pragma unroll
+                            for (int u = 0; u < kU; ++u) {
+                                const int q = q0 + u * kThreads;
+                                vt[u] = q < len ? ldm(ts, lo + q) : 0.0;
+                                vx[u] = q < len ? ldm(xs, lo + q) : 0.0;
+                            }
+#pragma unroll
+                            for (int u = 0; u < kU; ++u) {
+                                const int q = q0 + u * kThreads;
+                                if (q < len) {
+                                    WT[q] = vt[u];
+                                    WX[q] = vx[u];
+                                }
+                            }
+                        }
+                        lds_sync();
+                        for (int id = c0 + threadIdx.x; id < c1; id += kThreads) {
+                            const int li2 = id - lo;
+                            const int j = id / C.W, i = id - j * C.W;
+                            double bval = 0.0, r0 = 0.0;
+                            const double x0 = WX[li2];
+                            if (!B.mask[id]) {
+                                const Coef am = node_coef(C, B.kq, B.cm, i, j, ms, 0.0);
+                                const Coef ak = node_coef(C, B.kq, B.cm, i, j, 0.0, 1.0);
+                                double src;
+                                if (!st.adjoint) {
+                                    const int nex = (i > 0) + (i < C.nx), ney = (j > 0) + (j < C.ny);
+                                    src = B.qt[st.j] * C.quarter_area * (double)(nex * ney);
+                                } else {
+                                    const double T = ld_state(srow(C, B, st.j, LSc), id, C.ckpt != 0);
+                                    src = c.src_scale * ipow(T, C.p - 1);
+                                }
+                                bval = apply(am, WT, li2, C.W) + src;
+                                r0 = bval - (apply(am, WX, li2, C.W) + apply(ak, WX, li2, C.W));
+                            }
+                            if (x0copy) stc(X + id, x0);
+                            stc(Rb[0] + id, (Real)r0);
+                            loc[0] += bval * bval;
+                            loc[1] += r0 * r0;
+                        }
+                    }
+                    // the lane's sums are zeroed by the very threads that
+                    // accumulate them in the post-solve phase (same tiles, same
+                    // node-to-thread map): plain stores are only ordered within
+                    // a thread, and the L2 of another XCD may hold stale lines
+                    if (lane_start)
+                        for (int t = rank; t < ntiles; t += g) {
+                            const int a = t * TS, b = min(a + TS, C.Nn);
+                            for (int id = a + threadIdx.x; id < b; id += kThreads) {
+                                const int j = id / C.W, i = id - j * C.W;
+                                lane_start_work(id, i, j, ldm(ts, id));
+                            }
+                        }
+                } else
                 for (int t = rank; t < ntiles; t += g) {
                     const int a = t * TS;
                     const int b = min(a + TS, C.Nn);
@@ -1032,7 +1282,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                                 const int nex = (i > 0) + (i < C.nx), ney = (j > 0) + (j < C.ny);
                                 src = B.qt[st.j] * C.quarter_area * (double)(nex * ney);
                             } else {
-                                const double T = B.S[(size_t)(st.j - 1) * C.Nn + id];
+                                const double T = ld_state(srow(C, B, st.j, LSc), id, C.ckpt != 0);
                                 src = c.src_scale * ipow(T, C.p - 1);
                             }
                             bval = apply(am, LB, li2, C.W) + src;
@@ -1043,19 +1293,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                         stc(Rb[0] + id, (Real)r0);
                         loc[0] += bval * bval;
                         loc[1] += r0 * r0;
-                        // first step of a lane: zero sensitivity sums, publish copies
-                        if (first_entry && c.step == 0) {
-                            if (L.kind == F_ADJ) {
-                                if (i < C.nx && j < C.ny)
-                                    B.acc[(size_t)(L.slice - 1) * C.Ne + j * C.nx + i] = 0.0;
-                            } else if (L.kind == SWEEP_ADJ) {
-                                if (i < C.nx && j < C.ny) B.accG[j * C.nx + i] = 0.0;
-                                B.out_L[(size_t)C.Ntau * C.Nn + id] = 0.0;
-                                B.out_L[(size_t)(C.Ntau - 1) * C.Nn + id] = LB[li2];
-                            } else if (L.kind == SWEEP_PRI) {
-                                B.out_T[(size_t)C.Nn + id] = LB[li2];
-                            }
-                        }
+                        if (lane_start) lane_start_work(id, i, j, LB[li2]);
                     }
                 }
                 block_sum<2>(loc, red);
@@ -1432,7 +1670,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                         const double x = zx ? 0.0 : ldc(X + id);
                         switch (L.kind) {
                             case F_PRI: {
-                                B.S[(size_t)(st.j - 1) * C.Nn + id] = x;
+                                if (double *Sj = srow(C, B, st.j, nullptr)) Sj[id] = x;
                                 if (C.extrap) stc(TQ + id, ldc(TP + id));
                                 stc(TP + id, x);
                                 loc[0] += ipow(x, C.p);
@@ -1447,9 +1685,9 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                             }
                             case SWEEP_PRI: {
                                 const int n = st.n;
-                                const size_t srow = (size_t)(C.M * (n + 1) - 1) * C.Nn + id;
-                                const double u = x + B.S[srow] - B.Gk[(size_t)n * C.Nn + id];
-                                B.S[srow] = u;
+                                double *Sj = srow(C, B, C.M * (n + 1), nullptr);
+                                const double u = x + Sj[id] - B.Gk[(size_t)n * C.Nn + id];
+                                Sj[id] = u;
                                 B.out_T[(size_t)(n + 1) * C.Nn + id] = u;
                                 B.Gn[(size_t)n * C.Nn + id] = x;
                                 stc(TP + id, u);
@@ -1457,6 +1695,11 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                                 break;
                             }
                             case F_ADJ: {
+                                if (st.recompute) {
+                                    stc(srow(C, B, st.j, LSc) + id, x);
+                                    stc(TP + id, x);
+                                    break;
+                                }
                                 if (C.extrap) stc(TQ + id, ldc(TP + id));
                                 stc(TP + id, x);
                                 if (last) B.FL[(size_t)L.slice * C.Nn + id] = x;
@@ -1466,11 +1709,12 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                                     const double l1 = zx ? 0.0 : ldc(X + id + 1);
                                     const double l2 = zx ? 0.0 : ldc(X + id + C.W + 1);
                                     const double l3 = zx ? 0.0 : ldc(X + id + C.W);
-                                    const double *Tr = B.S + (size_t)(st.j - 1) * C.Nn;
+                                    const double *Tr = srow(C, B, st.j, LSc);
                                     const double *Tp =
-                                        st.jprev > 0 ? B.S + (size_t)(st.jprev - 1) * C.Nn : nullptr;
+                                        st.jprev > 0 ? srow(C, B, st.jprev, LSc) : nullptr;
                                     B.acc[(size_t)(L.slice - 1) * C.Ne + e] +=
-                                        sens_term(C, B, I, id, e, x, l1, l2, l3, Tr, Tp, C.inv_dt);
+                                        sens_term(C, B, I, id, e, x, l1, l2, l3, Tr, Tp, C.inv_dt,
+                                                  C.ckpt != 0);
                                 }
                                 break;
                             }
@@ -1492,12 +1736,12 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                                 if (i2 < C.nx && j2 < C.ny) {
                                     const int e = j2 * C.nx + i2;
                                     auto dl = [&](int k) { return (zx ? 0.0 : ldc(X + k)) - Gkn[k]; };
-                                    const double *Tr = B.S + (size_t)(st.j - 1) * C.Nn;
+                                    const double *Tr = srow(C, B, st.j, nullptr);
                                     const double *Tp =
-                                        st.jprev > 0 ? B.S + (size_t)(st.jprev - 1) * C.Nn : nullptr;
+                                        st.jprev > 0 ? srow(C, B, st.jprev, nullptr) : nullptr;
                                     B.accG[e] += sens_term(C, B, I, id, e, dl(id), dl(id + 1),
                                                            dl(id + C.W + 1), dl(id + C.W), Tr, Tp,
-                                                           C.inv_dtau);
+                                                           C.inv_dtau, false);
                                 }
                                 break;
                             }
@@ -1586,7 +1830,7 @@ __global__ void k_finalize_fwd(const EngineDesc *__restrict__ D) {
     for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < Nn;
          id += (size_t)gridDim.x * blockDim.x) {
         B.out_T[id] = 0.0;
-        if (C.Ntau == 1) B.out_T[Nn + id] = B.S[(size_t)(C.Nt - 1) * Nn + id];
+        if (C.Ntau == 1) B.out_T[Nn + id] = srow(C, B, C.Nt, nullptr)[id];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         B.out_th[0] = 0.0;

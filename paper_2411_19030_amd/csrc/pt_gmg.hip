@@ -169,6 +169,23 @@ __device__ __forceinline__ void atomic_max_pos(double *p, double v) {
     atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
 }
 
+// Level 0: the assembled stencil rows in the CG precision (zero rows on
+// Dirichlet nodes) and the Gershgorin bounds of both operators.
+template <typename Real>
+__device__ void gmg_level0_node(const Consts &C, const Bufs &B, int id, double (&g)[2]) {
+    for (int op = 0; op < 2; ++op) {
+        double a[9];
+        gmg_row64(C, B, op, 0, id, a);
+        Real *A = reinterpret_cast<Real *>(B.gA0) + (size_t)op * 9 * C.Nn + id;
+        double s = 0.0;
+        for (int k = 0; k < 9; ++k) {
+            A[(size_t)k * C.Nn] = (Real)a[k];
+            s += fabs(a[k]);
+        }
+        if (!B.mask[id]) g[op] = fmax(g[op], s / a[0]);
+    }
+}
+
 __global__ void k_gmg_level0(const EngineDesc *__restrict__ D) {
     const EngineDesc &E = D[blockIdx.y];
     const Consts &C = E.C;
@@ -176,14 +193,8 @@ __global__ void k_gmg_level0(const EngineDesc *__restrict__ D) {
     if (!C.gmg) return;
     double g[2] = {0.0, 0.0};
     for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < C.Nn; id += gridDim.x * blockDim.x) {
-        if (B.mask[id]) continue;
-        for (int op = 0; op < 2; ++op) {
-            double a[9];
-            gmg_row64(C, B, op, 0, id, a);
-            double s = 0.0;
-            for (int k = 0; k < 9; ++k) s += fabs(a[k]);
-            g[op] = fmax(g[op], s / a[0]);
-        }
+        if (C.fp32) gmg_level0_node<float>(C, B, id, g);
+        else gmg_level0_node<double>(C, B, id, g);
     }
     for (int op = 0; op < 2; ++op)
         if (g[op] > 0.0) atomic_max_pos(&B.gmg_g[op * kMaxLevels + 0], g[op]);

@@ -19,6 +19,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kMaxGrid = 1024;         // workgroups of one engine launch
 constexpr int kMaxBatchGroups = 512;   // worker groups of a multi-design launch
+constexpr long long kGmgLdsBytes = 158 * 1024;  // dynamic LDS of the multigrid lanes
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -59,7 +60,8 @@ bool valid_problem(const pt_problem *p) {
     if (p->pk < 1.0 || p->pc < 1.0) return false;
     if (!p->q_t && !isfinite(p->q)) return false;
     if ((p->precision != PT_FP64 && p->precision != PT_FP32_REFINE) ||
-        (p->precond != PT_JACOBI && p->precond != PT_GMG) || p->storage != PT_STORE_ALL)
+        (p->precond != PT_JACOBI && p->precond != PT_GMG) ||
+        (p->storage != PT_STORE_ALL && p->storage != PT_CHECKPOINT))
         return false;
     if (p->bc < 0 || p->bc > 3) return false;
     if (p->bc == PT_BC_MASK && !p->dirichlet_mask) return false;
@@ -95,6 +97,16 @@ Hierarchy hierarchy(const pt_problem *p) {
     return h;
 }
 
+// Checkpointed storage: fine adjoint lanes run on at most ck_slots groups,
+// each with scratch for the M-2 states its slice recomputes.
+int ck_slots(const pt_problem *p) {
+    return std::max(1, std::min(p->n_slices, env_int("PT_CK_SLOTS", 16)));
+}
+
+size_t state_rows(const pt_problem *p) {
+    return p->storage == PT_CHECKPOINT ? 2 * (size_t)p->n_slices : (size_t)p->n_steps;
+}
+
 // ---------------------------------------------------------------------------
 // Workspace layout
 // ---------------------------------------------------------------------------
@@ -102,7 +114,8 @@ Hierarchy hierarchy(const pt_problem *p) {
 // Arrays of one design.
 struct DesignLayout {
     size_t ctl, FL, kq, cm, dk, dc, dinv_f, dinv_c, mask, qt, zero;
-    size_t gA64, gA, gmg_g, gmg_w;
+    size_t gA64, gA, gA0, gmg_g, gmg_w, ck;
+    size_t ck_stride;
     size_t Gk, Gn, Gk_th, Gn_th, F_th, Uprev, Uprev_th, Ubuf, Ubuf_th, acc, accG;
     // multi-design cycles keep the cycle's state here
     size_t S, uT, uth, lam, gT, gth, gL;
@@ -135,8 +148,12 @@ void carve_design(Carver &c, const pt_problem *p, DesignLayout &L, bool batched)
     const Hierarchy h = hierarchy(p);
     L.gA64 = c.take(d * 2 * 9 * (size_t)h.nodes + d);
     L.gA = c.take(d * 2 * 9 * (size_t)h.nodes + d);
+    L.gA0 = c.take(p->precond == PT_GMG ? d * 2 * 9 * Nn : d);
     L.gmg_g = c.take(d * 2 * kMaxLevels);
     L.gmg_w = c.take(d * 2 * kMaxLevels);
+    const int M = p->n_steps / p->n_slices;
+    L.ck_stride = p->storage == PT_CHECKPOINT ? (size_t)std::max(M - 2, 0) * Nn : 0;
+    L.ck = c.take(d * (size_t)ck_slots(p) * L.ck_stride + d);
     if (!batched) {
         L.Uprev = c.take(d * Nt1 * Nn);
         L.Uprev_th = c.take(d * Nt1);
@@ -185,6 +202,14 @@ void carve_shared(Carver &c, SharedLayout &S, int n_designs, int max_lanes, int 
     S.gvec = c.take(sizeof(double) * (size_t)max_groups * S.gvec_stride + sizeof(double));
 }
 
+// Groups a single-design launch may use: one per lane at most, and no more
+// than keep the per-group CG vectors within about 16 GB.
+int max_groups_of(const pt_problem *p) {
+    const double nn = (double)(p->nx + 1) * (p->ny + 1);
+    const int by_memory = (int)std::max(32.0, 16e9 / (kVecsPerLane * 8.0 * nn));
+    return std::min(2 * p->n_slices + 2, std::min(by_memory, kMaxGroups));
+}
+
 int trace_stride_of(const pt_problem *p) {
     return TR_HDR + std::max(p->n_steps / p->n_slices, p->n_slices);
 }
@@ -201,7 +226,7 @@ Layout layout(const pt_problem *p) {
     Carver c;
     carve_design(c, p, L.d, false);
     const int max_lanes = 2 * p->n_slices + 2;
-    carve_shared(c, L.s, 1, max_lanes, max_lanes, (size_t)(p->nx + 1) * (p->ny + 1),
+    carve_shared(c, L.s, 1, max_lanes, max_groups_of(p), (size_t)(p->nx + 1) * (p->ny + 1),
                  trace_stride_of(p), p->nx + 2, (size_t)hierarchy(p).nodes);
     L.total = c.o;
     return L;
@@ -294,9 +319,23 @@ Consts make_consts(const pt_problem *p) {
     C.gmg_Lg = 0;
     for (int l = 0; l < h.L; ++l)
         if ((long long)((p->nx >> l) + 1) * ((p->ny >> l) + 1) > tail) C.gmg_Lg = l + 1;
-    C.gmg_tail_sweeps = 2 * std::max(1, env_int("PT_GMG_SWEEPS", 16));
+    // an odd count leaves the coarsest solution in the second buffer
+    C.gmg_tail_sweeps = 2 * std::max(1, env_int("PT_GMG_SWEEPS", 16)) + 1;
     C.gmg_omega = env_double("PT_GMG_OMEGA", 1.3);
-    if (C.gmg) C.extrap = 0;
+    C.ckpt = p->storage == PT_CHECKPOINT ? 1 : 0;
+    if (C.gmg || C.ckpt) C.extrap = 0;
+    // LDS-staged chunks of the multigrid rounds (one operand window in the CG
+    // precision) and of the FP64 set-up of a solve (two windows), within the
+    // 160 KB of LDS less the engine's static share
+    {
+        const long long avail = kGmgLdsBytes;
+        const long long halo = 2ll * (C.W + 1);
+        const long long rsz = C.fp32 ? 4 : 8;
+        long long ch = std::min(16384ll, avail / rsz - halo);
+        long long chi = std::min(8192ll, (avail / 8 - 2 * halo) / 2);
+        C.gmg_chunk = (int)std::max(0ll, ch / 256 * 256);
+        C.gmg_chunk_init = (int)std::max(0ll, chi / 256 * 256);
+    }
     return C;
 }
 
@@ -330,10 +369,13 @@ Bufs make_bufs(void *ws, const DesignLayout &L, const SharedLayout &S, int desig
     B.accG = at<double>(ws, L.accG);
     B.gA64 = at<double>(ws, L.gA64);
     B.gA = at<void>(ws, L.gA);
+    B.gA0 = at<void>(ws, L.gA0);
     B.gmg_g = at<double>(ws, L.gmg_g);
     B.gmg_w = at<double>(ws, L.gmg_w);
     B.gvec = at<void>(ws, S.gvec);
     B.gvec_stride = S.gvec_stride;
+    B.ck = at<double>(ws, L.ck);
+    B.ck_stride = L.ck_stride;
     return B;
 }
 
@@ -441,6 +483,13 @@ int device_info(Device &d) {
 size_t engine_lds_doubles(int ts, int W) {
     const size_t H = W + 1;
     return 2 * ((size_t)ts + 2 * H) + 2 * ((size_t)(ts - 1) / W + 3) * (W + 1);
+}
+
+// LDS of a multigrid lane: the larger of the round window and the two set-up windows.
+size_t gmg_lds_bytes(const Consts &C) {
+    const size_t halo = 2 * (size_t)(C.W + 1);
+    const size_t rsz = C.fp32 ? 4 : 8;
+    return std::max((C.gmg_chunk + halo) * rsz, 2 * (C.gmg_chunk_init + halo) * 8);
 }
 
 int lds_cap_doubles(const Device &dev) {
@@ -575,6 +624,7 @@ struct LanePlan {
     double weight;    // work per lane (relative)
     bool latency;     // sweep-like: fixed group size
     int queues = 0;   // groups (0: one lane per group)
+    int fixed_nwg = 0;  // workgroups per group if > 0 (same fine shape in both passes)
 };
 
 // Runs one single-design engine launch with descriptor D (already uploaded).
@@ -591,7 +641,7 @@ int run_engine(const Consts &C, const EngineDesc *D, std::vector<LanePlan> &plan
     const int res_npt_max = std::max(1, std::min(8, env_int("PT_RES_NPT", 8)));
     const int g_min = (C.Nn + NT * res_npt_max - 1) / (NT * res_npt_max);
     bool resident = env_int("PT_RESIDENT", 1) != 0 && g_min <= grid / 4 &&
-                    (C.Nn + g_min - 1) / g_min >= H && !C.gmg;
+                    (C.Nn + g_min - 1) / g_min >= H && !C.gmg && !C.ckpt;
     // a tile must be at least one halo (H nodes) long
     const int max_wg_per_lane = std::max(1, C.Nn / H);
 
@@ -655,24 +705,42 @@ int run_engine(const Consts &C, const EngineDesc *D, std::vector<LanePlan> &plan
         }
     }
     if (!resident) {
-        int total_groups = 0, fixed = 0;
+        // streaming: explicit shapes first (sweeps, fixed fine lanes), then the
+        // other lanes share the rest of the grid by weight, with at least
+        // kMinStreamWgs workgroups per group and within the group budget
+        constexpr int kMinStreamWgs = 4;
+        int fixed = 0, groups = 0;
         double wsum = 0.0;
         for (size_t k = 0; k < plans.size(); ++k) {
             auto &p = plans[k];
-            const int q = (p.queues <= 0 || p.queues > p.count) ? p.count : p.queues;
-            ngroups[k] = q;
-            per_group[k] = (p.count + q - 1) / q;
-            total_groups += q;
-            if (p.latency) fixed += std::max(1, std::min(sweep_wgs, grid / 2)) * q;
-            else wsum += p.weight * per_group[k] * q;
+            if (p.latency) {
+                ngroups[k] = p.count;
+                nwg[k] = std::max(1, std::min(sweep_wgs, grid / 2));
+            } else if (p.fixed_nwg > 0) {
+                ngroups[k] = (p.queues <= 0 || p.queues > p.count) ? p.count : p.queues;
+                nwg[k] = p.fixed_nwg;
+            } else {
+                wsum += p.weight * p.count;
+                continue;
+            }
+            fixed += nwg[k] * ngroups[k];
+            groups += ngroups[k];
         }
-        if (total_groups > Lay.s.max_groups) return PT_EINVAL;
-        if (total_groups > grid) grid = total_groups;
         const int rest = std::max(grid - fixed, 0);
+        int budget = Lay.s.max_groups - groups;
         for (size_t k = 0; k < plans.size(); ++k) {
             auto &p = plans[k];
-            if (p.latency) nwg[k] = std::max(1, std::min(sweep_wgs, grid / 2));
-            else nwg[k] = std::max(1, (int)floor(rest * p.weight * per_group[k] / wsum));
+            if (p.latency || p.fixed_nwg > 0) continue;
+            const double share = wsum > 0.0 ? rest * p.weight * p.count / wsum : 0.0;
+            int q = p.queues > 0 ? std::min(p.queues, p.count)
+                                 : std::min(p.count, std::max(1, (int)(share / kMinStreamWgs)));
+            q = std::max(1, std::min(q, budget));
+            budget -= q;
+            ngroups[k] = q;
+            nwg[k] = std::max(1, (int)floor(share / q));
+        }
+        for (size_t k = 0; k < plans.size(); ++k) {
+            per_group[k] = (plans[k].count + ngroups[k] - 1) / ngroups[k];
             tile[k] = tile_for(C.Nn, nwg[k], H, lds_cap_d);
         }
     }
@@ -691,7 +759,9 @@ int run_engine(const Consts &C, const EngineDesc *D, std::vector<LanePlan> &plan
         npt = 1;
         while (npt * NT < max_tile) npt *= 2;
     }
-    const size_t lds_bytes = engine_lds_doubles(max_tile, C.W) * sizeof(double);
+    if (C.gmg && (C.gmg_chunk < 256 || C.gmg_chunk_init < 256)) return PT_EINVAL;
+    const size_t lds_bytes =
+        C.gmg ? gmg_lds_bytes(C) : engine_lds_doubles(max_tile, C.W) * sizeof(double);
     if (lds_bytes > (size_t)dev.lds_max) return PT_EINVAL;
 
     PlanArgs P{};
@@ -719,6 +789,22 @@ int run_engine(const Consts &C, const EngineDesc *D, std::vector<LanePlan> &plan
     PT_TRY(reset_launch_state(ws, Lay.s, 1, stream));
     const Launch X = make_launch(ws, Lay.s, ctl, C.timeout_ticks);
     return launch_engine(C.fp32 != 0, npt, D, X, grid, lds_bytes, dev, stream);
+}
+
+// Fine lanes of a single-design pass. With checkpoints (or PT_FINE_WGS set)
+// they run on a fixed number of groups of a fixed size in both passes, so a
+// fine adjoint lane recomputes its slice's states with exactly the forward
+// pass's arithmetic, and its scratch slot (the group index) stays below
+// ck_slots.
+LanePlan fine_plan(int kind, int count, int slice0, int dir, const Consts &C,
+                   const pt_problem *p) {
+    LanePlan lp{kind, count, slice0, dir, (double)C.M, false, env_int("PT_FQUEUES", 0)};
+    const int fixed = env_int("PT_FINE_WGS", 0);
+    if (C.ckpt || fixed > 0) {
+        lp.queues = ck_slots(p);
+        lp.fixed_nwg = fixed > 0 ? fixed : 8;
+    }
+    return lp;
 }
 
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
@@ -853,7 +939,9 @@ int run_batched_engine(std::vector<EngineDesc> &hd, const pt_batch_tuning &T, bo
         E.plan.tile0 = t0;
         E.plan.tile1 = t1;
         E.plan.adjoint = adjoint ? 1 : 0;
-        lds_d = std::max(lds_d, engine_lds_doubles(std::max(t0, t1), C.W));
+        if (C.gmg && (C.gmg_chunk < 256 || C.gmg_chunk_init < 256)) return PT_EINVAL;
+        lds_d = std::max(lds_d, C.gmg ? (gmg_lds_bytes(C) + 7) / 8
+                                      : engine_lds_doubles(std::max(t0, t1), C.W));
     }
     const size_t lds_bytes = lds_d * sizeof(double);
     if (lds_bytes > (size_t)dev.lds_max) return PT_EINVAL;
@@ -912,6 +1000,7 @@ bool valid_batch(int n, const pt_problem *probs) {
     if (n < 1 || n > 4096 || !probs) return false;
     for (int k = 0; k < n; ++k) {
         if (!valid_problem(&probs[k])) return false;
+        if (probs[k].storage != PT_STORE_ALL) return false;
         if (probs[k].iterations != 1) return false;
         if (probs[k].precision != probs[0].precision) return false;
     }
@@ -927,6 +1016,11 @@ int pt_validate(const pt_problem *prob) { return valid_problem(prob) ? PT_OK : P
 size_t pt_workspace_bytes(const pt_problem *prob) {
     if (!valid_problem(prob)) return 0;
     return layout(prob).total;
+}
+
+size_t pt_state_bytes(const pt_problem *prob) {
+    if (!valid_problem(prob)) return 0;
+    return state_rows(prob) * (size_t)(prob->nx + 1) * (prob->ny + 1) * sizeof(double);
 }
 
 const char *pt_strerror(int code) {
@@ -952,7 +1046,7 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
     if (ws_bytes < Lay.total) return PT_ENOMEM;
     const Consts C = make_consts(prob);
     const size_t Nn = C.Nn, Nt1 = C.Ntau + 1;
-    const size_t sz_U = Nt1 * Nn * sizeof(double), sz_S = (size_t)C.Nt * Nn * sizeof(double);
+    const size_t sz_U = Nt1 * Nn * sizeof(double), sz_S = state_rows(prob) * Nn * sizeof(double);
     if (guess_T) {
         const void *outs[] = {S, uT_out, utheta_out, Theta_out, ws};
         const size_t lens[] = {sz_S, sz_U, Nt1 * sizeof(double), sizeof(double), ws_bytes};
@@ -1001,7 +1095,7 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
         B.Theta_out = Theta_out;
         PT_TRY(upload_descs(hd, D, stream));
         std::vector<LanePlan> plans;
-        plans.push_back({F_PRI, Ntau, 0, +1, (double)C.M, false, env_int("PT_FQUEUES", 0)});
+        plans.push_back(fine_plan(F_PRI, Ntau, 0, +1, C, prob));
         if (I.gk_lanes)
             plans.push_back({GK_PRI, Ntau - 1, 1, +1, env_double("PT_GK_WEIGHT", 4.0), false,
                              env_int("PT_GQUEUES", 0)});
@@ -1068,7 +1162,7 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
         PT_TRY(upload_descs(hd, D, stream));
         std::vector<LanePlan> plans;
         // the reversed sweep consumes slices from N_tau downwards
-        plans.push_back({F_ADJ, Ntau, Ntau, -1, (double)C.M, false, env_int("PT_FQUEUES", 0)});
+        plans.push_back(fine_plan(F_ADJ, Ntau, Ntau, -1, C, prob));
         if (I.gk_lanes)
             plans.push_back({GK_ADJ, Ntau - 1, Ntau - 1, -1, env_double("PT_GK_WEIGHT", 4.0),
                              false, env_int("PT_GQUEUES", 0)});

@@ -88,6 +88,11 @@ struct Consts {
     // nx >> l by ny >> l elements; levels < gmg_Lg are smoothed by the whole
     // group, the rest (and the coarsest solve) by one workgroup
     int gmg, gmg_L, gmg_Lg, gmg_tail_sweeps;
+    int gmg_chunk, gmg_chunk_init;    // nodes per LDS-staged chunk (rounds / FP64 set-up of a solve)
+    // checkpointed storage: S keeps the corrected coarse states T_{Mn} and
+    // every slice's first fine state T_{Mn+1}; fine adjoint lanes recompute
+    // the other states of their slice
+    int ckpt;
     double gmg_omega;                 // smoother damping times the Gershgorin bound
     long long gmg_off[kMaxLevels];    // node offset of level l >= 1 in the level arrays
     long long gmg_nodes;              // sum of the nodes of levels 1..L-1
@@ -137,10 +142,13 @@ struct Bufs {
     // per operator and level the Gershgorin bound of D^{-1} A and the damping
     double *gA64;
     void *gA;
+    void *gA0;             // level-0 stencil rows [2][9][Nn] in the CG precision
     double *gmg_g;         // [2][kMaxLevels]
     double *gmg_w;         // [2][kMaxLevels]
     void *gvec;            // group level vectors [groups][3][gmg_nodes] (CG precision)
     size_t gvec_stride;    // elements per group
+    double *ck;            // recomputed fine states per fine adjoint group [slots][M-2][Nn]
+    size_t ck_stride;      // elements per slot
 };
 
 struct LaunchInfo {

@@ -16,7 +16,7 @@ from ._pt import Problem
 class CycleResult:
     Theta: torch.Tensor       # 0-dim device tensor
     grad: torch.Tensor        # [N_e]
-    S: torch.Tensor           # [N_t, N_n]
+    S: torch.Tensor           # [N_t, N_n], or [2 N_tau, N_n] with checkpoints
     uT: torch.Tensor          # [N_tau+1, N_n]  next primal guess
     utheta: torch.Tensor      # [N_tau+1]
     lam: torch.Tensor         # [N_tau+1, N_n]  next adjoint guess
@@ -35,7 +35,9 @@ class Cycle:
         f64 = torch.float64
         Nn, Nt1 = prob.n_nodes, prob.n_slices + 1
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=d)
-        self.S = torch.empty((prob.n_steps, Nn), dtype=f64, device=d)
+        # every fine state, or the checkpoints of PT_CHECKPOINT (T_{Mn}, T_{Mn+1})
+        rows = _pt.pt_state_bytes(prob) // (8 * Nn)
+        self.S = torch.empty((rows, Nn), dtype=f64, device=d)
         self.uT = torch.empty((Nt1, Nn), dtype=f64, device=d)
         self.utheta = torch.empty(Nt1, dtype=f64, device=d)
         self.lam = torch.empty((Nt1, Nn), dtype=f64, device=d)

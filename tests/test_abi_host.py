@@ -174,3 +174,16 @@ def test_batch_default_tuning(lib):
 
 def test_batch_tuning_layout():
     assert ctypes.sizeof(_pt.PtBatchTuning) == 32
+
+
+def test_state_bytes_store_all_and_checkpoint(lib):
+    p = base(nx=8, ny=6, n_steps=24, n_slices=4)
+    nn = 9 * 7
+    assert _pt.pt_state_bytes(p) == 24 * nn * 8
+    assert _pt.pt_state_bytes(base(nx=8, ny=6, n_steps=24, n_slices=4, storage=1)) == 8 * nn * 8
+    assert _pt.pt_state_bytes(base(pnorm=3)) == 0
+    # multigrid and checkpoint settings are valid single-design problems
+    assert _pt.pt_validate(base(precond=1, storage=1)) == _pt.PT_OK
+    # a batch accepts only store-all designs
+    arr = (PtProblem * 2)(base().to_c(), base(storage=1).to_c())
+    assert lib.pt_batched_workspace_bytes(2, arr) == 0

@@ -106,3 +106,16 @@ def test_gmg_batched(gpu):
         eg = np.linalg.norm(gr[k].cpu().numpy() - ad["grad"]) / grad_scale(fw["Theta"], ad["grad"])
         print(shapes[k], et, eg, flush=True)
         assert et <= 1e-10 and eg <= 1e-10
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 64), (48, 40)])
+def test_gmg_bitwise_deterministic(gpu, nx, ny):
+    """Two runs agree bit for bit (fixed-order reductions; the single-workgroup
+    levels drain their stores before each intra-workgroup barrier)."""
+    import numpy as np
+    cfg = _cfg(nx=nx, ny=ny, n_steps=32, n_slices=4, cg_rtol=1e-10)
+    rho = density_uniform_noise(nx, ny, 77)
+    a = run_gpu(cfg, rho)
+    b = run_gpu(cfg, rho)
+    for key in ("Theta", "grad", "lam", "S", "uT"):
+        assert np.array_equal(np.asarray(a[key]), np.asarray(b[key])), key

@@ -14,6 +14,8 @@ optimised design field is not given, so seeded densities stand in for it):
 * ``diff_fp64_512``     512x512, N_t=1024 in 64 slices
 * ``batch_fp32``        64 designs of seeded side and slice count, M=16
 * ``large_2048``        2048x2048, N_t=2048 in 128 slices, smooth field
+* ``large_law_512``     the large design's density law and solver at 512x512,
+                        N_t=512 in 32 slices (small enough for the oracle)
 """
 from __future__ import annotations
 
@@ -35,6 +37,8 @@ WORKLOADS = {
                           rtol=1e-10, precision="fp64"),
     "large_2048": dict(nx=2048, ny=2048, n_steps=2048, n_slices=128, seed=4,
                        rtol=1e-10, precision="fp32_refine"),
+    "large_law_512": dict(nx=512, ny=512, n_steps=512, n_slices=32, seed=4,
+                          rtol=1e-10, precision="fp32_refine"),
 }
 
 
@@ -98,6 +102,6 @@ def workload(name: str) -> dict:
 
 def workload_density(name: str) -> np.ndarray:
     w = WORKLOADS[name]
-    if name == "large_2048":
+    if name in ("large_2048", "large_law_512"):
         return density_gaussians(w["nx"], w["ny"], w["seed"])
     return density_uniform_noise(w["nx"], w["ny"], w["seed"])
