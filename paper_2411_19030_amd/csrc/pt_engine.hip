@@ -683,8 +683,11 @@ __global__ void k_copy_f64(double *dst, const double *src, size_t n) {
 // ---------------------------------------------------------------------------
 // The engine
 // ---------------------------------------------------------------------------
-template <int NPT, typename Real>
-__global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restrict__ D, Launch S) {
+// MULTI: lanes of several designs read their descriptor from D; otherwise the
+// single design's descriptor E1 is a kernel argument (cheaper scalar access).
+template <int NPT, typename Real, bool MULTI>
+__global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restrict__ D, Launch S,
+                                                     EngineDesc E1) {
     extern __shared__ double lds[];
     __shared__ double red[kWaves * 4];
 
@@ -737,7 +740,10 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
             lane_id = G.lane0 + pos;
         }
         const Lane L = S.lanes[lane_id];
-        const EngineDesc &E = D[L.design];
+        const EngineDesc &E = [&]() -> const EngineDesc & {
+            if constexpr (MULTI) return D[L.design];
+            else return E1;
+        }();
         const Consts &C = E.C;
         const Bufs &B = E.B;
         const LaunchInfo &I = E.I;

@@ -506,23 +506,30 @@ int tile_for(int Nn, int nwg, int H, int cap_doubles) {
     return ts;
 }
 
-const void *engine_kernel(bool fp32, int npt) {
+const void *engine_kernel(bool fp32, int npt, bool multi) {
+    if (multi) {
+        if (fp32) return npt == 0 ? (const void *)k_engine<0, float, true>
+                                  : (const void *)k_engine<8, float, true>;
+        return npt == 0 ? (const void *)k_engine<0, double, true>
+                        : (const void *)k_engine<8, double, true>;
+    }
     if (fp32)
-        return npt == 0   ? (const void *)k_engine<0, float>
-               : npt == 1 ? (const void *)k_engine<1, float>
-               : npt == 2 ? (const void *)k_engine<2, float>
-               : npt == 4 ? (const void *)k_engine<4, float>
-                          : (const void *)k_engine<8, float>;
-    return npt == 0   ? (const void *)k_engine<0, double>
-           : npt == 1 ? (const void *)k_engine<1, double>
-           : npt == 2 ? (const void *)k_engine<2, double>
-           : npt == 4 ? (const void *)k_engine<4, double>
-                      : (const void *)k_engine<8, double>;
+        return npt == 0   ? (const void *)k_engine<0, float, false>
+               : npt == 1 ? (const void *)k_engine<1, float, false>
+               : npt == 2 ? (const void *)k_engine<2, float, false>
+               : npt == 4 ? (const void *)k_engine<4, float, false>
+                          : (const void *)k_engine<8, float, false>;
+    return npt == 0   ? (const void *)k_engine<0, double, false>
+           : npt == 1 ? (const void *)k_engine<1, double, false>
+           : npt == 2 ? (const void *)k_engine<2, double, false>
+           : npt == 4 ? (const void *)k_engine<4, double, false>
+                      : (const void *)k_engine<8, double, false>;
 }
 
 // Workgroups of the engine that fit on the device at once.
-int engine_capacity(bool fp32, int npt, size_t lds_bytes, const Device &dev, int &cap) {
-    const void *kern = engine_kernel(fp32, npt);
+int engine_capacity(bool fp32, int npt, bool multi, size_t lds_bytes, const Device &dev,
+                    int &cap) {
+    const void *kern = engine_kernel(fp32, npt, multi);
     PT_TRY(hip_ok(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds_bytes)));
     int occ = 0;
@@ -535,15 +542,25 @@ int engine_capacity(bool fp32, int npt, size_t lds_bytes, const Device &dev, int
 // once (groups spin on each other): the grid is checked against the
 // occupancy bound, and the launch is cooperative unless the stream is being
 // captured into a graph, where a plain launch of the same checked grid is used.
-int launch_engine(bool fp32, int npt, const EngineDesc *D, const Launch &X, int grid,
-                  size_t lds_bytes, const Device &dev, hipStream_t stream) {
+static_assert(sizeof(EngineDesc) + sizeof(Launch) + sizeof(void *) <= 4096,
+              "engine kernel arguments exceed the kernel argument segment");
+
+// single: the descriptor of a single-design launch (passed by value), or
+// nullptr for a multi-design launch that reads D.
+int launch_engine(bool fp32, int npt, const EngineDesc *D, const EngineDesc *single,
+                  const Launch &X, int grid, size_t lds_bytes, const Device &dev,
+                  hipStream_t stream) {
+    const bool multi = single == nullptr;
     int cap = 0;
-    PT_TRY(engine_capacity(fp32, npt, lds_bytes, dev, cap));
+    PT_TRY(engine_capacity(fp32, npt, multi, lds_bytes, dev, cap));
     if (cap < grid || grid > kMaxGrid) return PT_EHIP;
-    const void *kern = engine_kernel(fp32, npt);
+    const void *kern = engine_kernel(fp32, npt, multi);
     Launch Xv = X;
     const EngineDesc *Dv = D;
-    void *args[] = {(void *)&Dv, (void *)&Xv};
+    EngineDesc E1;
+    if (single) E1 = *single;
+    else memset(&E1, 0, sizeof(E1));
+    void *args[] = {(void *)&Dv, (void *)&Xv, (void *)&E1};
     if (capturing(stream))
         PT_TRY(hip_ok(hipLaunchKernel(kern, dim3(grid), dim3(kThreads), args, (unsigned)lds_bytes,
                                       stream)));
@@ -628,8 +645,10 @@ struct LanePlan {
 };
 
 // Runs one single-design engine launch with descriptor D (already uploaded).
-int run_engine(const Consts &C, const EngineDesc *D, std::vector<LanePlan> &plans, void *ws,
-               const Layout &Lay, Control *ctl, hipStream_t stream) {
+int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &plans, void *ws,
+               const Layout &Lay, hipStream_t stream) {
+    const Consts &C = E.C;
+    Control *ctl = E.B.ctl;
     Device dev;
     PT_TRY(device_info(dev));
     const int H = C.W + 1;
@@ -788,7 +807,7 @@ int run_engine(const Consts &C, const EngineDesc *D, std::vector<LanePlan> &plan
     PT_TRY(launch_check());
     PT_TRY(reset_launch_state(ws, Lay.s, 1, stream));
     const Launch X = make_launch(ws, Lay.s, ctl, C.timeout_ticks);
-    return launch_engine(C.fp32 != 0, npt, D, X, grid, lds_bytes, dev, stream);
+    return launch_engine(C.fp32 != 0, npt, D, &E, X, grid, lds_bytes, dev, stream);
 }
 
 // Fine lanes of a single-design pass. With checkpoints (or PT_FINE_WGS set)
@@ -969,7 +988,7 @@ int run_batched_engine(std::vector<EngineDesc> &hd, const pt_batch_tuning &T, bo
     }
     if (q0 + q1 > Lay.s.max_lanes) return PT_EINVAL;
     int cap = 0;
-    PT_TRY(engine_capacity(fp32, npt, lds_bytes, dev, cap));
+    PT_TRY(engine_capacity(fp32, npt, true, lds_bytes, dev, cap));
     int grid = std::min(cap, kMaxGrid);
     if (T.grid > 0) grid = std::min(grid, T.grid);
     GroupArgs A{};
@@ -993,7 +1012,7 @@ int run_batched_engine(std::vector<EngineDesc> &hd, const pt_batch_tuning &T, bo
     PT_TRY(launch_check());
     PT_TRY(reset_launch_state(ws, Lay.s, n, stream));
     const Launch X = make_launch(ws, Lay.s, hd[0].B.ctl, hd[0].C.timeout_ticks);
-    return launch_engine(fp32, npt, D, X, A.grid, lds_bytes, dev, stream);
+    return launch_engine(fp32, npt, D, nullptr, X, A.grid, lds_bytes, dev, stream);
 }
 
 bool valid_batch(int n, const pt_problem *probs) {
@@ -1101,7 +1120,7 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
                              env_int("PT_GQUEUES", 0)});
         if (I.cold) plans.push_back({COLD_PRI, 1, 0, +1, 0.0, true, 0});
         if (Ntau > 1) plans.push_back({SWEEP_PRI, 1, 0, +1, 0.0, true, 0});
-        PT_TRY(run_engine(C, D, plans, ws, Lay, B.ctl, stream));
+        PT_TRY(run_engine(E, D, plans, ws, Lay, stream));
         if (it + 1 < prob->iterations) {
             hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Uprev, outT, Nt1 * Nn);
             hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(256), 0, stream, Uprev_th, outth, Nt1);
@@ -1168,7 +1187,7 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
                              false, env_int("PT_GQUEUES", 0)});
         if (I.cold) plans.push_back({COLD_ADJ, 1, 0, +1, 0.0, true, 0});
         if (Ntau > 1) plans.push_back({SWEEP_ADJ, 1, 0, +1, 0.0, true, 0});
-        PT_TRY(run_engine(C, D, plans, ws, Lay, B.ctl, stream));
+        PT_TRY(run_engine(E, D, plans, ws, Lay, stream));
         if (it + 1 < prob->iterations) {
             hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Lprev, outL, Nt1 * Nn);
             PT_TRY(launch_check());
