@@ -34,8 +34,8 @@ WORKLOAD = "plain_fp64_256"
 # WRITE_SIZE runs (each scaled by what the counter reads for a 1 GiB device
 # copy: x2.0 and x1.0), averaged over the forward and adjoint launches of a warm
 # cycle; valid only for the kernel sources with this hash (see profiles/).
-TRAFFIC = {"sources_sha1": "ce7eca6a1a0b19359d1866ccf5cd0d5d350c5f12",
-           "bytes_per_launch": 0.5 * (42.34e9 + 43.27e9)}
+TRAFFIC = {"sources_sha1": "23b037b1acdf0b48169335a0536f2d5eb4025643",
+           "bytes_per_launch": 0.5 * (42.52e9 + 43.29e9)}
 
 
 def sources_sha1() -> str:
@@ -58,6 +58,10 @@ def parse():
                     help="skip the FP32+refine vs FP64 comparison at equal objective accuracy")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-design batch (batched FP32+refine vs plain FP64)")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    choices=[WORKLOAD, "batch_fp32_64", "large_2048", "large_law_512"],
+                    help="the headline workload (default), or one of the other workloads "
+                         "measured on its own")
     ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (counter calibration)")
@@ -249,6 +253,58 @@ def batch_compare(rtol=1e-7, ref_rtol=1e-12, accuracy=1e-6) -> dict:
     }
 
 
+def large_run(name: str, steps: int) -> dict:
+    """The large single design (2048 x 2048, 2048 steps in 128 slices, Gaussian-bump
+    density; the same law at 512 x 512 with 512 steps in 32 slices): geometric
+    multigrid PCG, FP32 inner CG with FP64 refinement, checkpointed storage. One
+    cold cycle, then `steps` timed warm cycles (forward + adjoint + sensitivities)."""
+    import torch
+
+    from paper_2411_19030_amd import Problem
+    from paper_2411_19030_amd.cycle import Cycle
+    from workloads import workload, workload_density
+
+    w = workload(name)
+    dev = torch.device("cuda:0")
+    prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
+                   pnorm=w["p"], cg_rtol=w["rtol"], max_iter=20000, precond=1, precision=1,
+                   storage=1)
+    cyc = Cycle(prob, dev)
+    rho = torch.tensor(workload_density(name), dtype=torch.float64, device=dev)
+    cyc.run(rho)
+    torch.cuda.synchronize()
+    st_cold = cyc.status()
+    gT, gth, gl = cyc.uT.clone(), cyc.utheta.clone(), cyc.lam.clone()
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        cyc.forward(rho, gT, gth)
+        ev[1].record(stream)
+        cyc.adjoint(rho, gl)
+        cyc.sensitivities(rho)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        times.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
+    st = cyc.status()
+    cells = prob.n_elem * prob.n_steps
+    ms = sum(a + b for a, b in times) / len(times)
+    return {"metric": "fine-step cell-updates/s (fwd+adjoint+sens per cycle)",
+            "value": cells / (ms * 1e-3), "unit": "cell-updates/s", "n_gpus": 1,
+            "steps": steps, "ms_per_step": ms, "higher_is_better": True, "dtype": "f32+f64",
+            "data": "synthetic",
+            "config": {"workload": name, "nx": prob.nx, "ny": prob.ny, "n_steps": prob.n_steps,
+                       "n_slices": prob.n_slices, "cg_rtol": prob.cg_rtol,
+                       "precision": "fp32_refine", "preconditioner": "gmg",
+                       "storage": "checkpoint"},
+            "phase_ms": {"forward": sum(a for a, _ in times) / len(times),
+                         "adjoint_and_sensitivities": sum(b for _, b in times) / len(times)},
+            "cold_status": st_cold["status"], "status": st["status"],
+            "Theta": float(cyc.Theta),
+            "workspace_gb": cyc.ws.numel() / 1e9, "state_gb": cyc.S.numel() * 8 / 1e9}
+
+
 def main():
     args = parse()
     if args.cpu_sample_only:
@@ -269,6 +325,12 @@ def main():
     from workloads import workload, workload_density
 
     load_library()
+    if args.workload in ("large_2048", "large_law_512"):
+        print(json.dumps(large_run(args.workload, max(1, min(args.steps, 3)))))
+        return
+    if args.workload == "batch_fp32_64":
+        print(json.dumps(batch_compare()))
+        return
     w = workload(WORKLOAD)
     prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
                    pnorm=w["p"], k0=w["k0"], kmin=w["kmin"], pk=w["pk"], c0=w["c0"],
