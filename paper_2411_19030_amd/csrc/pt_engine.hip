@@ -1072,6 +1072,46 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
         };
         (void)gmg_round;
 
+        // Resident rounds: the raw halo values (r, w, s of the neighbours'
+        // boundary nodes, and D^{-1} there) for the next round are loaded right
+        // after the barrier, together with the partial sums, so both round trips
+        // overlap; the halo z is formed once alpha and beta are known.
+        constexpr int kHP = 2;
+        Real hpr[kHP], hpw[kHP], hps[kHP], hpd[kHP];
+        bool hp_ok = false;
+        auto halo_prefetch = [&](const StepInfo &st, bool need_s) {
+            if constexpr (NPT > 0) {
+                const int a = min(rank * TS, C.Nn);
+                const int b = min(a + TS, C.Nn);
+                const int ppar = (nbar - 1) & 1;  // parity of the round just published
+                const double *dinv = st.fine ? B.dinv_f : B.dinv_c;
+                hp_ok = 2 * H <= kThreads * kHP;
+#pragma unroll
+                for (int u = 0; u < kHP; ++u) {
+                    const int q = threadIdx.x + u * kThreads;
+                    hpr[u] = hpw[u] = hps[u] = hpd[u] = (Real)0;
+                    if (hp_ok && q < 2 * H) {
+                        const bool left = q < H;
+                        const int id = left ? a - H + q : b + (q - H);
+                        if (id >= 0 && id < C.Nn) {
+                            const int nb = left ? blockIdx.x - 1 : blockIdx.x + 1;
+                            const int k = left ? q : q - H;
+                            const Real *base =
+                                XCH + (((size_t)nb * 2 + ppar) * 2 + (left ? 1 : 0)) * 3 * XS;
+                            hpr[u] = ldc(base + k);
+                            hpw[u] = ldc(base + XS + k);
+                            if (need_s) hps[u] = ldc(base + 2 * XS + k);
+                            hpd[u] = (Real)dinv[id];
+                        }
+                    }
+                }
+            } else {
+                (void)st;
+                (void)need_s;
+            }
+        };
+        (void)halo_prefetch;
+
         const bool is_adj = L.kind >= F_ADJ;
         const bool tracer = (rank == 0 && threadIdx.x == 0);
         unsigned long long *trec = S.trace + (size_t)lane_id * S.trace_stride;
@@ -1461,6 +1501,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                 }
                 ok = barrier(false);
                 if (!ok) break;
+                if constexpr (NPT > 0) halo_prefetch(st, false);
                 double tot[2];
                 group_sum<2>(all_part(par), g, tot, red);
                 mark_red();
@@ -1492,6 +1533,17 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                         xo[k] = id < b ? ldc(X + id) : 0.0;
                     }
                     lds_sync();
+                    if (hp_ok) {
+#pragma unroll
+                        for (int u = 0; u < kHP; ++u) {
+                            const int q = threadIdx.x + u * kThreads;
+                            if (q < 2 * H) {
+                                const Real sv = first ? hpw[u] : hpw[u] + (Real)be * hps[u];
+                                const Real z = hpd[u] * (hpr[u] - (Real)al * sv);
+                                LZ[q < H ? q : (b - lo) + (q - H)] = z;
+                            }
+                        }
+                    } else
                     for (int q = threadIdx.x; q < 2 * H; q += kThreads) {
                         const bool left = q < H;
                         const int id = left ? a - H + q : b + (q - H);
@@ -1628,6 +1680,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                 }
                 ok = barrier(false);
                 if (!ok) break;
+                if constexpr (NPT > 0) halo_prefetch(st, true);
                 double tot[3];
                 group_sum<3>(all_part(par), g, tot, red);
                 mark_red();
