@@ -357,6 +357,9 @@ struct StepInfo {
     bool extrap;      // x0 = 2 x - tq (two previous states of a fine lane)
     bool recompute;   // a primal step recomputed inside a fine adjoint lane
     int s_adj;        // adjoint step index of a fine adjoint lane (step - recomputed steps)
+    // x0 = x0_src + (d1 - d0) when d1 != nullptr: a correction sweep step starts
+    // from G(u^k_n) plus the correction u^{k+1}_n - u^k_n of its input
+    const double *d1, *d0;
 };
 
 __device__ __forceinline__ int lane_steps(const Consts &C, int kind) {
@@ -387,6 +390,7 @@ __device__ StepInfo step_info(const Consts &C, const Bufs &B, const LaunchInfo &
     st.extrap = C.extrap && (L.kind == F_PRI || L.kind == F_ADJ) && s >= 2;
     st.recompute = false;
     st.s_adj = 0;
+    st.d1 = st.d0 = nullptr;
     switch (L.kind) {
         case F_PRI: {
             const int n = L.slice;
@@ -446,6 +450,10 @@ __device__ StepInfo step_info(const Consts &C, const Bufs &B, const LaunchInfo &
             st.j = C.M * (n + 1);
             st.tp_src = (n == 1) ? srow(C, B, C.M, nullptr) : tpbuf;
             st.x0_src = B.Gk + (size_t)n * Nn;
+            if (C.sweep_x0 && I.gk_lanes) {
+                st.d1 = st.tp_src;
+                st.d0 = B.in_T + (size_t)n * Nn;
+            }
             break;
         }
         case F_ADJ: {
@@ -530,6 +538,10 @@ __device__ StepInfo step_info(const Consts &C, const Bufs &B, const LaunchInfo &
             st.jprev = st.j - C.M;
             st.tp_src = (n == C.Ntau - 1) ? B.FL + (size_t)C.Ntau * Nn : tpbuf;
             st.x0_src = B.Gk + (size_t)n * Nn;
+            if (C.sweep_x0 && I.gk_lanes) {
+                st.d1 = st.tp_src;
+                st.d0 = B.in_L + (size_t)n * Nn;
+            }
             break;
         }
     }
@@ -1230,6 +1242,8 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                                 const int q = q0 + u * kThreads;
                                 vt[u] = q < len ? ldm(ts, lo + q) : 0.0;
                                 vx[u] = q < len ? ldm(xs, lo + q) : 0.0;
+                                if (q < len && first_entry && st.d1)
+                                    vx[u] += ldm(st.d1, lo + q) - ldm(st.d0, lo + q);
                             }
 #pragma unroll
                             for (int u = 0; u < kU; ++u) {
@@ -1296,6 +1310,8 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                             const int id = lo + q;
                             const bool in = q < len && id >= 0 && id < C.Nn;
                             va[u] = in ? ldc(xs + id) : 0.0;
+                            if (in && first_entry && st.d1)
+                                va[u] += ldc(st.d1 + id) - ldc(st.d0 + id);
                             vb[u] = in ? ldc(ts + id) : 0.0;
                             vq[u] = (in && ext) ? ldc(TQ + id) : 0.0;
                         }

@@ -323,6 +323,7 @@ Consts make_consts(const pt_problem *p) {
     C.gmg_tail_sweeps = 2 * std::max(1, env_int("PT_GMG_SWEEPS", 16)) + 1;
     C.gmg_omega = env_double("PT_GMG_OMEGA", 1.3);
     C.ckpt = p->storage == PT_CHECKPOINT ? 1 : 0;
+    C.sweep_x0 = env_int("PT_SWEEP_X0", 1);
     if (C.gmg || C.ckpt) C.extrap = 0;
     // LDS-staged chunks of the multigrid rounds (one operand window in the CG
     // precision) and of the FP64 set-up of a solve (two windows), within the

@@ -93,6 +93,7 @@ struct Consts {
     // every slice's first fine state T_{Mn+1}; fine adjoint lanes recompute
     // the other states of their slice
     int ckpt;
+    int sweep_x0;  // correction sweeps start from G(u^k_n) + (u^{k+1}_n - u^k_n)
     double gmg_omega;                 // smoother damping times the Gershgorin bound
     long long gmg_off[kMaxLevels];    // node offset of level l >= 1 in the level arrays
     long long gmg_nodes;              // sum of the nodes of levels 1..L-1
