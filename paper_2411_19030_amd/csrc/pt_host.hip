@@ -655,7 +655,7 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
     const int H = C.W + 1;
     const int lds_cap_d = lds_cap_doubles(dev);
     int grid = dev.cus * std::max(1, env_int("PT_WG_PER_CU", 1));
-    const int sweep_wgs = env_int("PT_SWEEP_WGS", 32);
+    const int sweep_wgs = env_int("PT_SWEEP_WGS", 40);
 
     const int NT = kThreads;
     const int res_npt_max = std::max(1, std::min(8, env_int("PT_RES_NPT", 8)));
