@@ -7,9 +7,10 @@ common are the seeded arrays from ``workloads``.
 
 It is a plain, slow implementation written from the paper: assembled sparse
 Q1 matrices, a sparse direct solve per backward-Euler step, the sequential
-reference method, and the modified / time-reversed Parareal passes step by step
-in the paper's order. Pins against closed forms, invariants and finite
-differences live in ``tests/test_oracle_*.py``.
+reference method, the modified / time-reversed Parareal passes step by step
+in the paper's order, and the zero-coarse-propagator (PLT) form of Sec. 7.
+Pins against closed forms, invariants and finite differences live in
+``tests/test_oracle_*.py``.
 
 Every function is pinned; see the tests' docstrings for which property pins
 which part.
@@ -18,6 +19,7 @@ from .fem import (Discretisation, Problem, dirichlet_mask, element_matrices,
                   element_nodes, simp, simp_deriv)
 from .parareal import (F_adj, F_pri, G_adj, G_pri, one_cycle, parareal_adjoint,
                        parareal_forward)
+from .plt import F_adj_tilde, h_adj_tilde, plt_adjoint, plt_forward, plt_objective
 from .timestepping import (adjoint_sequential, adjoint_source, forward_sequential,
                            h_adj, h_pri, pnorm_p)
 
@@ -26,4 +28,5 @@ __all__ = [
     "element_nodes", "simp", "simp_deriv", "F_adj", "F_pri", "G_adj", "G_pri",
     "one_cycle", "parareal_adjoint", "parareal_forward", "adjoint_sequential",
     "adjoint_source", "forward_sequential", "h_adj", "h_pri", "pnorm_p",
+    "F_adj_tilde", "h_adj_tilde", "plt_adjoint", "plt_forward", "plt_objective",
 ]
