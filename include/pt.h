@@ -63,6 +63,9 @@ enum {
 enum { PT_FP64 = 0, PT_FP32_REFINE = 1 };
 enum { PT_JACOBI = 0, PT_GMG = 1 };
 enum { PT_STORE_ALL = 0, PT_CHECKPOINT = 1 };
+/* Coarse propagators: the method's G (Alg. 1-2 with dtau), or G = 0, the
+ * Parallel Local-in-Time form of Sec. 7 (see pt_parareal_forward). */
+enum { PT_PARAREAL = 0, PT_PLT = 1 };
 
 typedef struct pt_problem {
     int32_t nx, ny;            /* elements along x and y, >= 1                                   */
@@ -87,6 +90,7 @@ typedef struct pt_problem {
                                /* pass recomputes the other fine states of each slice             */
     int32_t bc;                /* PT_BC_*                                                         */
     const uint8_t *dirichlet_mask; /* HOST, (nx+1)(ny+1) bytes, read when bc == PT_BC_MASK        */
+    int32_t propagator;        /* PT_PARAREAL (0), or PT_PLT: zero coarse propagators (Sec. 7)    */
 } pt_problem;
 
 typedef struct pt_stats {
@@ -125,6 +129,15 @@ size_t pt_state_bytes(const pt_problem *prob);
  *   utheta_out   [N_tau+1]          out: corrected theta_{Mn}; may be NULL
  *   Theta_out    [1]                out: Theta = theta_{N_t} estimate (device scalar)
  * guess arrays must not overlap any output. Returns PT_OK once enqueued.
+ *
+ * With propagator == PT_PLT (Sec. 7, Eq. 7.1-7.2) the coarse propagators are
+ * zero: each iteration is u^{k+1}_{n+1} = F_pri(u^k_n), u^{k+1}_0 = 0, with u
+ * holding T only, and the cold guess is u^0 = 0. No sequential sweep runs.
+ * S holds the last iteration's fine trajectories (T_{M(n+1)} = F of u^k_n),
+ * uT_out = u^{K}; the objective is the modified Theta~ = Theta^p of Eq. 7.4,
+ * summed over those trajectories, and Theta_out = Theta~^{1/p} (Eq. 7.6);
+ * utheta_out[n] = (the part of Theta~ before tau_n)^{1/p}. guess_theta is
+ * ignored and may be NULL.
  */
 int pt_parareal_forward(const pt_problem *prob, const double *rho, const double *guess_T,
                         const double *guess_theta, double *S, double *uT_out,
@@ -142,13 +155,20 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
  *   lambda_out     [N_tau+1][N_n]  out: corrected lambda_{Mn+1}, row N_tau = 0; may be NULL
  * The g part of a guess cancels in the correction, so only lambda is taken.
  * Leaves the per-element sensitivity sums in ws for pt_sensitivities.
+ *
+ * With propagator == PT_PLT: v^{k+1}_{n-1} = F_adj(v^k_n), v_{N_tau} = 0, cold
+ * guess v^0 = 0, for the adjoint of Theta~: source p/N_e T^{o(p-1)} (Eq. 7.5),
+ * so lambda_out holds lambda~ = p Theta^{p-1} lambda. The first fine step of
+ * slice n takes T_{M(n-1)} from S (the end of slice n-1's trajectory). Theta
+ * (the forward's Theta_out) is kept for the back-transform of pt_sensitivities.
  */
 int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double *S,
                         const double *Theta, const double *guess_lambda, double *lambda_out,
                         void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
- * grad Theta = g-part of v_0 (Sec. 4.4 step 4):
+ * grad Theta = g-part of v_0 (Sec. 4.4 step 4); with PT_PLT the fine terms
+ * of Theta~ are summed and scaled by Theta^{1-p}/p (Eq. 7.7):
  *   dTheta_drho[e] = -(1/N_t) sum_fine lambda_j,e^T (dC/drho_e (T_j - T_{j-1})/dt + dK/drho_e T_j)
  *                    - (1/N_tau) (coarse-correction terms)          (Eq. 4.8, Eq. 4.10)
  *   dTheta_drho    [N_e] out
@@ -207,7 +227,8 @@ typedef struct pt_batch_tuning {
 } pt_batch_tuning;
 
 /* Workspace bytes of a batch of n designs; 0 if any problem is invalid, the
- * precisions differ, or a design has iterations != 1 or storage != PT_STORE_ALL. */
+ * precisions differ, or a design has iterations != 1, storage != PT_STORE_ALL or
+ * propagator != PT_PARAREAL. */
 size_t pt_batched_workspace_bytes(int n, const pt_problem *probs);
 
 /* The built-in worker shapes for n designs (environment overrides included). */

@@ -21,6 +21,7 @@ PT_BC = {"left_centre": 0, "bottom_centre": 1, "none": 2, "mask": 3}
 PT_FP64, PT_FP32_REFINE = 0, 1
 PT_JACOBI, PT_GMG = 0, 1
 PT_STORE_ALL, PT_CHECKPOINT = 0, 1
+PT_PARAREAL, PT_PLT = 0, 1
 
 EXPORTS = ["pt_workspace_bytes", "pt_state_bytes", "pt_validate", "pt_parareal_forward", "pt_parareal_adjoint",
            "pt_sensitivities", "pt_query_status", "pt_query_trace", "pt_strerror",
@@ -41,6 +42,7 @@ class PtProblem(ctypes.Structure):
         ("precision", ctypes.c_int32), ("precond", ctypes.c_int32),
         ("storage", ctypes.c_int32), ("bc", ctypes.c_int32),
         ("dirichlet_mask", ctypes.POINTER(ctypes.c_uint8)),
+        ("propagator", ctypes.c_int32),
     ]
 
 
@@ -153,6 +155,7 @@ class Problem:
     precond: int = PT_JACOBI
     storage: int = PT_STORE_ALL
     bc: object = "left_centre"  # name or boolean/uint8 node mask
+    propagator: int = PT_PARAREAL
     _keep: list = field(default_factory=list, repr=False, compare=False)
 
     @property
@@ -190,6 +193,7 @@ class Problem:
             self._keep.append(m)
             c.bc = PT_BC["mask"]
             c.dirichlet_mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        c.propagator = int(self.propagator)
         return c
 
 

@@ -407,7 +407,8 @@ __device__ StepInfo step_info(const Consts &C, const Bufs &B, const LaunchInfo &
                         st.wait_idx = flag_index(FL_COLD, n - 1);
                     }
                 } else {
-                    src = (n == 0) ? B.zero : B.in_T + (size_t)n * Nn;
+                    // with G = 0 a cold pass starts every slice from u^0_n = 0
+                    src = (n == 0 || B.in_T == nullptr) ? B.zero : B.in_T + (size_t)n * Nn;
                 }
                 st.tp_src = src;
                 st.x0_src = src;
@@ -492,7 +493,7 @@ __device__ StepInfo step_info(const Consts &C, const Bufs &B, const LaunchInfo &
                     st.wait = true;
                     st.wait_idx = flag_index(FL_COLD, n + 1);
                 } else {
-                    src = B.in_L + (size_t)n * Nn;
+                    src = B.in_L == nullptr ? B.zero : B.in_L + (size_t)n * Nn;
                 }
                 st.tp_src = src;
                 st.x0_src = src;
@@ -671,6 +672,7 @@ __global__ void k_reset_ctl(const EngineDesc *__restrict__ D, int keep_markers) 
         ctl->max_relres_bits = 0;
         ctl->fwd_done = keep_markers ? f : 0;
         ctl->adj_done = 0;
+        ctl->grad_scale = 1.0;
     }
 }
 
@@ -1154,12 +1156,13 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
         c.src_scale = 0.0;
         if (is_adj) {
             const double Th = *B.Theta;
-            c.src_scale = pow(Th, 1.0 - C.p) / (double)C.Ne;
+            // the source of Theta (Eq. 4.6), or of Theta~ = Theta^p (Eq. 7.5)
+            c.src_scale = C.plt ? (double)C.p / (double)C.Ne : pow(Th, 1.0 - C.p) / (double)C.Ne;
             if (!(Th > 0.0) || !isfinite(Th)) set_status(ctl, -5);
         }
         if (L.kind == F_PRI) {
             // a cold-started slice reads its theta after its flag wait (INIT)
-            if (L.slice > 0 && !I.cold) c.theta = B.in_th[L.slice];
+            if (L.slice > 0 && !I.cold && !C.plt) c.theta = B.in_th[L.slice];
         } else if (L.kind == GK_PRI) {
             c.theta = B.in_th[L.slice];
         }
@@ -1746,6 +1749,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                         switch (L.kind) {
                             case F_PRI: {
                                 if (double *Sj = srow(C, B, st.j, nullptr)) Sj[id] = x;
+                                if (C.plt && last) B.out_T[(size_t)(L.slice + 1) * C.Nn + id] = x;
                                 if (C.extrap) stc(TQ + id, ldc(TP + id));
                                 stc(TP + id, x);
                                 loc[0] += ipow(x, C.p);
@@ -1778,6 +1782,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                                 if (C.extrap) stc(TQ + id, ldc(TP + id));
                                 stc(TP + id, x);
                                 if (last) B.FL[(size_t)L.slice * C.Nn + id] = x;
+                                if (C.plt && last) B.out_L[(size_t)(L.slice - 1) * C.Nn + id] = x;
                                 const int j2 = id / C.W, i2 = id - j2 * C.W;
                                 if (i2 < C.nx && j2 < C.ny) {
                                     const int e = j2 * C.nx + i2;
@@ -1836,7 +1841,9 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                 // theta updates (Alg. 1, step 2) and lane outputs
                 if (!is_adj) {
                     const double inv = st.fine ? C.inv_NtNe : C.inv_NtauNe;
-                    const double thG = pow(ipow(c.theta, C.p) + tot[0] * inv, C.inv_p);
+                    // with G = 0 a fine lane keeps its slice's part of Theta~ instead
+                    const double thG = C.plt ? c.theta + tot[0] * inv
+                                             : pow(ipow(c.theta, C.p) + tot[0] * inv, C.inv_p);
                     if (L.kind == SWEEP_PRI) {
                         const int n = st.n;
                         const double thu = thG + B.F_th[n] - B.Gk_th[n];
@@ -1896,7 +1903,8 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
 }
 
 // After the primal engine (blockIdx.y = design): u_0 = 0, Theta, and the
-// N_tau = 1 case.
+// N_tau = 1 case. With G = 0, Theta~ is the sum of the slices' parts in slice
+// order (Eq. 7.4) and Theta = Theta~^{1/p} (Eq. 7.6).
 __global__ void k_finalize_fwd(const EngineDesc *__restrict__ D) {
     const EngineDesc &E = D[blockIdx.y];
     const Consts &C = E.C;
@@ -1905,11 +1913,19 @@ __global__ void k_finalize_fwd(const EngineDesc *__restrict__ D) {
     for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < Nn;
          id += (size_t)gridDim.x * blockDim.x) {
         B.out_T[id] = 0.0;
-        if (C.Ntau == 1) B.out_T[Nn + id] = srow(C, B, C.Nt, nullptr)[id];
+        if (C.Ntau == 1 && !C.plt) B.out_T[Nn + id] = srow(C, B, C.Nt, nullptr)[id];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         B.out_th[0] = 0.0;
-        if (C.Ntau == 1) B.out_th[1] = B.F_th[0];
+        if (C.plt) {
+            double run = 0.0;
+            for (int n = 0; n < C.Ntau; ++n) {
+                run += B.F_th[n];
+                B.out_th[n + 1] = pow(run, C.inv_p);
+            }
+        } else if (C.Ntau == 1) {
+            B.out_th[1] = B.F_th[0];
+        }
         const double Th = B.out_th[C.Ntau];
         *B.Theta_out = Th;
         if (!(Th > 0.0) || !isfinite(Th)) atomicCAS(&B.ctl->status, 0, -5);
@@ -1917,35 +1933,41 @@ __global__ void k_finalize_fwd(const EngineDesc *__restrict__ D) {
     }
 }
 
-// After the adjoint engine (blockIdx.y = design): lambda for N_tau = 1.
+// After the adjoint engine (blockIdx.y = design): lambda for N_tau = 1, the
+// last row and coarse sums with G = 0, and the back-transform factor of the
+// sensitivities (Eq. 7.7).
 __global__ void k_finalize_adj(const EngineDesc *__restrict__ D) {
     const EngineDesc &E = D[blockIdx.y];
     const Consts &C = E.C;
     const Bufs &B = E.B;
     const size_t Nn = C.Nn;
-    if (C.Ntau == 1) {
+    if (C.Ntau == 1 || C.plt) {
         for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < Nn;
              id += (size_t)gridDim.x * blockDim.x) {
-            B.out_L[id] = B.FL[Nn + id];
-            B.out_L[Nn + id] = 0.0;
+            if (!C.plt) B.out_L[id] = B.FL[Nn + id];
+            B.out_L[(size_t)C.Ntau * Nn + id] = 0.0;
         }
         for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)C.Ne;
              e += (size_t)gridDim.x * blockDim.x)
             B.accG[e] = 0.0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) B.ctl->adj_done = 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        B.ctl->grad_scale = C.plt ? pow(*B.Theta, 1.0 - C.p) / (double)C.p : 1.0;
+        B.ctl->adj_done = 1;
+    }
 }
 
 // grad_e = -(1/N_t) sum_n acc[n][e] - (1/N_tau) accG[e]  (Eq. 4.10 summed,
-// Sec. 4.4 step 4); blockIdx.y = design.
+// Sec. 4.4 step 4), times Theta^{1-p}/p with G = 0 (Eq. 7.7); blockIdx.y = design.
 __global__ void k_sensitivities(const EngineDesc *__restrict__ D) {
     const EngineDesc &E = D[blockIdx.y];
     const Consts &C = E.C;
     const Bufs &B = E.B;
+    const double scale = B.ctl->grad_scale;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < C.Ne; e += gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int n = 0; n < C.Ntau; ++n) s += B.acc[(size_t)n * C.Ne + e];
-        B.grad[e] = -s / (double)C.Nt - B.accG[e] / (double)C.Ntau;
+        B.grad[e] = (-s / (double)C.Nt - B.accG[e] / (double)C.Ntau) * scale;
     }
 }
 

@@ -65,6 +65,7 @@ bool valid_problem(const pt_problem *p) {
         return false;
     if (p->bc < 0 || p->bc > 3) return false;
     if (p->bc == PT_BC_MASK && !p->dirichlet_mask) return false;
+    if (p->propagator != PT_PARAREAL && p->propagator != PT_PLT) return false;
     if (p->q_t)
         for (int n = 0; n <= p->n_steps; ++n)
             if (!isfinite(p->q_t[n])) return false;
@@ -324,6 +325,7 @@ Consts make_consts(const pt_problem *p) {
     C.gmg_omega = env_double("PT_GMG_OMEGA", 1.3);
     C.ckpt = p->storage == PT_CHECKPOINT ? 1 : 0;
     C.sweep_x0 = env_int("PT_SWEEP_X0", 1);
+    C.plt = p->propagator == PT_PLT ? 1 : 0;
     if (C.gmg || C.ckpt) C.extrap = 0;
     // LDS-staged chunks of the multigrid rounds (one operand window in the CG
     // precision) and of the FP64 set-up of a solve (two windows), within the
@@ -1022,6 +1024,7 @@ bool valid_batch(int n, const pt_problem *probs) {
         if (!valid_problem(&probs[k])) return false;
         if (probs[k].storage != PT_STORE_ALL) return false;
         if (probs[k].iterations != 1) return false;
+        if (probs[k].propagator != PT_PARAREAL) return false;
         if (probs[k].precision != probs[0].precision) return false;
     }
     return true;
@@ -1061,7 +1064,9 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
                         double *Theta_out, void *ws, size_t ws_bytes, hipStream_t stream) {
     if (!valid_problem(prob)) return PT_EINVAL;
     if (!rho || !S || !Theta_out || !ws) return PT_EINVAL;
-    if ((guess_T == nullptr) != (guess_theta == nullptr)) return PT_EINVAL;
+    const bool plt = prob->propagator == PT_PLT;
+    if (plt) guess_theta = nullptr;  // u holds T only (Sec. 7)
+    else if ((guess_T == nullptr) != (guess_theta == nullptr)) return PT_EINVAL;
     const Layout Lay = layout(prob);
     if (ws_bytes < Lay.total) return PT_ENOMEM;
     const Consts C = make_consts(prob);
@@ -1099,8 +1104,9 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
     for (int it = 0; it < prob->iterations; ++it) {
         LaunchInfo &I = E.I;
         I = LaunchInfo{};
-        I.cold = (cold && it == 0) ? 1 : 0;
-        I.gk_lanes = (!cold && it == 0 && Ntau > 1) ? 1 : 0;
+        // with G = 0 there are no coarse lanes: a cold pass has in_T == NULL
+        I.cold = (cold && it == 0 && !plt) ? 1 : 0;
+        I.gk_lanes = (!cold && it == 0 && Ntau > 1 && !plt) ? 1 : 0;
         I.has_dc = (prob->c0 != prob->cmin) ? 1 : 0;
         I.epoch = 1;
         B.in_T = it == 0 ? guess_T : Uprev;
@@ -1120,11 +1126,12 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
             plans.push_back({GK_PRI, Ntau - 1, 1, +1, env_double("PT_GK_WEIGHT", 4.0), false,
                              env_int("PT_GQUEUES", 0)});
         if (I.cold) plans.push_back({COLD_PRI, 1, 0, +1, 0.0, true, 0});
-        if (Ntau > 1) plans.push_back({SWEEP_PRI, 1, 0, +1, 0.0, true, 0});
+        if (Ntau > 1 && !plt) plans.push_back({SWEEP_PRI, 1, 0, +1, 0.0, true, 0});
         PT_TRY(run_engine(E, D, plans, ws, Lay, stream));
         if (it + 1 < prob->iterations) {
             hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Uprev, outT, Nt1 * Nn);
-            hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(256), 0, stream, Uprev_th, outth, Nt1);
+            if (!plt)
+                hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(256), 0, stream, Uprev_th, outth, Nt1);
             PT_TRY(launch_check());
             std::swap(Ga, Gb);
             std::swap(Ga_th, Gb_th);
@@ -1150,6 +1157,7 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
             return PT_EINVAL;
     }
     if (overlaps(lambda_out, sz_U, ws, ws_bytes)) return PT_EINVAL;
+    const bool plt = prob->propagator == PT_PLT;
     std::vector<EngineDesc> hd(1);
     memset(hd.data(), 0, sizeof(EngineDesc));
     EngineDesc &E = hd[0];
@@ -1169,8 +1177,8 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
     for (int it = 0; it < prob->iterations; ++it) {
         LaunchInfo &I = E.I;
         I = LaunchInfo{};
-        I.cold = (cold && it == 0) ? 1 : 0;
-        I.gk_lanes = (!cold && it == 0 && Ntau > 1) ? 1 : 0;
+        I.cold = (cold && it == 0 && !plt) ? 1 : 0;
+        I.gk_lanes = (!cold && it == 0 && Ntau > 1 && !plt) ? 1 : 0;
         I.has_dc = (prob->c0 != prob->cmin) ? 1 : 0;
         I.epoch = 1;
         B.S = const_cast<double *>(S);
@@ -1187,7 +1195,7 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
             plans.push_back({GK_ADJ, Ntau - 1, Ntau - 1, -1, env_double("PT_GK_WEIGHT", 4.0),
                              false, env_int("PT_GQUEUES", 0)});
         if (I.cold) plans.push_back({COLD_ADJ, 1, 0, +1, 0.0, true, 0});
-        if (Ntau > 1) plans.push_back({SWEEP_ADJ, 1, 0, +1, 0.0, true, 0});
+        if (Ntau > 1 && !plt) plans.push_back({SWEEP_ADJ, 1, 0, +1, 0.0, true, 0});
         PT_TRY(run_engine(E, D, plans, ws, Lay, stream));
         if (it + 1 < prob->iterations) {
             hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Lprev, outL, Nt1 * Nn);

@@ -62,6 +62,7 @@ struct Control {
     int fwd_done, adj_done;              // call-order markers (written by finalize kernels)
     int epoch;
     int pad1;
+    double grad_scale;  // factor of the summed sensitivities: Theta^{1-p}/p with G = 0, else 1
 };
 
 struct Consts {
@@ -94,6 +95,7 @@ struct Consts {
     // the other states of their slice
     int ckpt;
     int sweep_x0;  // correction sweeps start from G(u^k_n) + (u^{k+1}_n - u^k_n)
+    int plt;       // zero coarse propagators (Sec. 7): fine lanes only, objective Theta^p
     double gmg_omega;                 // smoother damping times the Gershgorin bound
     long long gmg_off[kMaxLevels];    // node offset of level l >= 1 in the level arrays
     long long gmg_nodes;              // sum of the nodes of levels 1..L-1

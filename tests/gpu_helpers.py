@@ -21,7 +21,7 @@ def gpu_problem(cfg: dict):
     from paper_2411_19030_amd import Problem
     kw = {k: cfg[k] for k in ("nx", "ny", "n_steps", "n_slices")}
     for k in ("k0", "kmin", "pk", "c0", "cmin", "pc", "q", "t_final", "pnorm", "iterations",
-              "cg_rtol", "max_iter", "bc", "precision", "precond", "storage"):
+              "cg_rtol", "max_iter", "bc", "precision", "precond", "storage", "propagator"):
         if k in cfg:
             kw[k] = cfg[k]
     return Problem(**kw)
@@ -31,6 +31,11 @@ def run_oracle(cfg: dict, rho: np.ndarray, guess=None):
     """Oracle cycle; guess = (uT, utheta, lam) or None for the cold start."""
     d = O.Discretisation(oracle_problem(cfg), rho)
     it = cfg.get("iterations", 1)
+    if cfg.get("propagator", 0) == 1:   # zero coarse propagators (PLT form)
+        fw = O.plt_forward(d, it, None if guess is None else guess[0])
+        ad = O.plt_adjoint(d, fw["S"], fw["Theta"], it, None if guess is None else guess[2])
+        return dict(S=fw["S"], uT=fw["uT"], utheta=fw["utheta"], Theta=fw["Theta"],
+                    lam=ad["lam"], grad=ad["grad"])
     if guess is None:
         fw = O.parareal_forward(d, it)
         ad = O.parareal_adjoint(d, fw["S"], fw["Theta"], it)

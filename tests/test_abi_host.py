@@ -44,7 +44,8 @@ def base(**kw):
     dict(pnorm=7), dict(pnorm=0), dict(n_slices=5), dict(nx=0), dict(ny=-1),
     dict(cg_rtol=0.0), dict(cg_rtol=float("nan")), dict(max_iter=0), dict(iterations=0),
     dict(t_final=0.0), dict(kmin=0.0), dict(pk=0.5), dict(precision=7), dict(precond=9),
-    dict(storage=4), dict(n_steps=0), dict(q=float("inf")),
+    dict(storage=4), dict(n_steps=0), dict(q=float("inf")), dict(propagator=2),
+    dict(propagator=-1),
 ])
 def test_validate_rejects(lib, kw):
     p = base(**kw)
@@ -55,6 +56,7 @@ def test_validate_rejects(lib, kw):
 def test_validate_accepts_and_sizes(lib):
     p = base()
     assert _pt.pt_validate(p) == _pt.PT_OK
+    assert _pt.pt_validate(base(propagator=_pt.PT_PLT)) == _pt.PT_OK
     small = _pt.pt_workspace_bytes(p)
     big = _pt.pt_workspace_bytes(base(nx=64, ny=64))
     assert 0 < small < big
@@ -115,8 +117,8 @@ def test_struct_layout_matches_header():
     assert offs["nx"] == 0 and offs["ny"] == 4 and offs["k0"] == 8
     assert offs["q_t"] == 64 and offs["t_final"] == 72 and offs["n_steps"] == 80
     assert offs["cg_rtol"] == 96 and offs["max_iter"] == 104
-    assert offs["dirichlet_mask"] == 128
-    assert ctypes.sizeof(PtProblem) == 136
+    assert offs["dirichlet_mask"] == 128 and offs["propagator"] == 136
+    assert ctypes.sizeof(PtProblem) == 144
 
 
 def _batch(lib, probs, rho=None, grads=None, theta=0x3000, ws=0x10000000, nbytes=None,
@@ -140,8 +142,9 @@ def test_batched_workspace_and_validation(lib):
     nb2 = lib.pt_batched_workspace_bytes(2, arr)
     nb1 = lib.pt_batched_workspace_bytes(1, one)
     assert nb2 > nb1 > 0
-    # mixed precision, several Parareal iterations, invalid members: no workspace
-    for bad in (base(precision=1), base(iterations=2), base(pnorm=3)):
+    # mixed precision, several Parareal iterations, zero coarse propagators,
+    # invalid members: no workspace
+    for bad in (base(precision=1), base(iterations=2), base(pnorm=3), base(propagator=1)):
         arr_bad = (PtProblem * 2)(a.to_c(), bad.to_c())
         assert lib.pt_batched_workspace_bytes(2, arr_bad) == 0
     assert lib.pt_batched_workspace_bytes(0, arr) == 0
