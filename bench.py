@@ -56,10 +56,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-compare", action="store_true",
                     help="skip the FP32+refine vs FP64 comparison at equal objective accuracy")
+    ap.add_argument("--no-plt", action="store_true",
+                    help="skip the zero-coarse-propagator (PLT, Sec. 7) cycle on the workload")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-design batch (batched FP32+refine vs plain FP64)")
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=[WORKLOAD, "batch_fp32_64", "large_2048", "large_law_512"],
+                    choices=[WORKLOAD, "batch_fp32_64", "large_2048", "large_law_512",
+                             "paper_100"],
                     help="the headline workload (default), or one of the other workloads "
                          "measured on its own")
     ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
@@ -167,6 +170,169 @@ def precision_compare(prob, rho, gT, gth, gl, accuracy=1e-6, repeats=3) -> dict:
     if out["fp64"] and out["fp32_refine"]:
         out["speedup_fp32_refine_over_fp64"] = (out["fp64"]["ms_per_cycle"]
                                                 / out["fp32_refine"]["ms_per_cycle"])
+    return out
+
+
+def plt_compare(prob, rho, parareal_ms, parareal_theta, repeats=5) -> dict:
+    """Zero coarse propagators (the PLT form of Sec. 7) on the same workload.
+
+    Each PLT cycle carries information one slice further, so the PLT cycles
+    first run N_tau times on the fixed design, each restarting from the last.
+    The guesses are then the converged states, the steady state of a one-shot
+    run. The warm cycles from those guesses are timed (median of `repeats`):
+    FP64 at the workload's CG tolerance, and FP32 with FP64 refinement at
+    1e-7 (objective within 1e-6 of FP64). The converged Theta is the
+    sequential method's Theta to the CG tolerance, so it also measures the
+    objective error of the one-iteration Parareal estimate."""
+    import dataclasses
+
+    import torch
+
+    from paper_2411_19030_amd.cycle import Cycle
+    stream = torch.cuda.current_stream()
+    Nn, Nt = prob.n_nodes, prob.n_steps
+    out = {"guess": f"converged ({prob.n_slices} PLT cycles on the design)"}
+    th_ref = None
+    for name, prec, rtol in (("fp64", 0, prob.cg_rtol), ("fp32_refine", 1, 1e-7)):
+        cyc = Cycle(dataclasses.replace(prob, propagator=1, precision=prec, cg_rtol=rtol),
+                    rho.device)
+        cyc.run(rho)
+        for _ in range(prob.n_slices):
+            cyc.run(rho, cyc.uT.clone(), None, cyc.lam.clone())
+        torch.cuda.synchronize()
+        gT, gl = cyc.uT.clone(), cyc.lam.clone()
+        ts, tf = [], []
+        for _ in range(repeats):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record(stream)
+            cyc.forward(rho, gT)
+            ev[1].record(stream)
+            st_f = cyc.status()
+            ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev2[0].record(stream)
+            cyc.adjoint(rho, gl)
+            cyc.sensitivities(rho)
+            ev2[1].record(stream)
+            torch.cuda.synchronize()
+            tf.append((ev[0].elapsed_time(ev[1]), ev2[0].elapsed_time(ev2[1])))
+            ts.append(tf[-1][0] + tf[-1][1])
+        st = cyc.status()
+        k = sorted(range(repeats), key=lambda i: ts[i])[repeats // 2]
+        t_fwd, t_adj = tf[k]
+        it_f = st_f["cg_iters_fine"]
+        it_a = st["cg_iters_fine"]   # counters restart with each pass
+        w = 8.0
+        bytes_f = w * Nn * (12 * it_f + 4 * Nt)
+        bytes_a = w * Nn * (12 * it_a + 7 * Nt)
+        ach = (bytes_f + bytes_a) / ((t_fwd + t_adj) * 1e-3) / 1e9
+        th = float(cyc.Theta)
+        th_ref = th if th_ref is None else th_ref
+        out[name] = {"cg_rtol": rtol, "ms_per_cycle": ts[k],
+                     "phase_ms": {"forward": t_fwd, "adjoint+sens": t_adj},
+                     "cell_updates_per_s": prob.n_elem * Nt / (ts[k] * 1e-3),
+                     "speedup_over_parareal_fp64": parareal_ms / ts[k],
+                     "Theta": th, "Theta_rel_err_vs_fp64": abs(th - th_ref) / th_ref,
+                     "status": st["status"],
+                     "roofline_fp64_bytes": {"achieved": ach, "frac": ach / HBM_PEAK_GBS}}
+        if name == "fp64":
+            out["parareal_one_shot_Theta_rel_err"] = abs(parareal_theta - th) / th
+        del cyc
+    return out
+
+
+def sequential_reference(prob, rho, repeats=3) -> dict:
+    """The reference method of Sec. 5.2 on the GPU: one slice (N_tau = 1), where
+    one iteration is the sequential time stepping exactly (every step is a
+    fine step from the previous state). The paper measures both one-shot
+    methods as speedups over this reference."""
+    import dataclasses
+
+    import torch
+
+    from paper_2411_19030_amd.cycle import Cycle
+    stream = torch.cuda.current_stream()
+    cyc = Cycle(dataclasses.replace(prob, n_slices=1), rho.device)
+    cyc.run(rho)
+    torch.cuda.synchronize()
+    # with a guess no cold coarse lane runs beside the single fine lane; with
+    # one slice the guess does not enter the result
+    g = (cyc.uT.clone(), cyc.utheta.clone(), cyc.lam.clone())
+    ts = []
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        cyc.run(rho, *g)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[len(ts) // 2]
+    return {"ms_per_cycle": ms, "Theta": float(cyc.Theta), "status": cyc.status()["status"]}
+
+
+def paper_sweep(slices=(5, 10, 20, 30), max_iters=8, repeats=1) -> dict:
+    """The paper's preliminary experiment (Sec. 5.2-5.3) on its test case: for
+    N_tau in {5, 10, 20, 30} and 1..8 Parareal iterations, cold guesses from the
+    coarse propagators, the objective error |Theta_par - Theta_seq| / Theta_seq
+    and the sensitivity error ||grad_par - grad_seq||_2 / ||grad_seq||_2 against
+    the sequential method (one slice), and the speedup of the cycle over it.
+    The same rows with zero coarse propagators (Sec. 7, guesses u^0 = 0) follow.
+    All solves to relative residual 1e-12 in FP64."""
+    import dataclasses
+
+    import torch
+
+    from paper_2411_19030_amd import Problem
+    from paper_2411_19030_amd.cycle import Cycle
+    from workloads import workload, workload_density
+    w = workload("paper_100")
+    base = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=1, pnorm=w["p"],
+                   k0=w["k0"], kmin=w["kmin"], pk=w["pk"], c0=w["c0"], cmin=w["cmin"],
+                   pc=w["pc"], q=w["q"], t_final=w["t_final"], bc=w["bc"], iterations=1,
+                   cg_rtol=w["rtol"], max_iter=50000)
+    dev = torch.device("cuda:0")
+    rho = torch.tensor(workload_density("paper_100"), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(cyc, guess=()):
+        cyc.run(rho, *guess)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(repeats):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            cyc.run(rho, *guess)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+
+    seq = Cycle(base, dev)
+    seq.run(rho)
+    torch.cuda.synchronize()
+    g = (seq.uT.clone(), seq.utheta.clone(), seq.lam.clone())
+    t_seq = timed(seq, g)
+    th_seq = float(seq.Theta)
+    gr_seq = seq.grad.clone()
+    out = {"workload": "paper_100", "design": "seeded branched conductor (density_branches)",
+           "cg_rtol": base.cg_rtol, "sequential": {"ms_per_cycle": t_seq, "Theta": th_seq},
+           "columns": ["propagator", "n_slices", "iterations", "objective_error",
+                       "sensitivity_error", "ms_per_cycle", "speedup", "status"],
+           "rows": []}
+    del seq
+    for prop in (0, 1):
+        for Ntau in slices:
+            for it in range(1, max_iters + 1):
+                if prop == 1 and it > Ntau:
+                    break   # exact from N_tau iterations on
+                cyc = Cycle(dataclasses.replace(base, n_slices=Ntau, iterations=it,
+                                                propagator=prop), dev)
+                ms = timed(cyc)
+                e_obj = abs(float(cyc.Theta) - th_seq) / th_seq
+                e_sen = float(torch.linalg.norm(cyc.grad - gr_seq) / torch.linalg.norm(gr_seq))
+                out["rows"].append(["parareal" if prop == 0 else "plt", Ntau, it, e_obj, e_sen,
+                                    ms, t_seq / ms, cyc.status()["status"]])
+                print("paper_100", out["rows"][-1], file=sys.stderr, flush=True)
+                del cyc
     return out
 
 
@@ -331,6 +497,9 @@ def main():
     if args.workload == "batch_fp32_64":
         print(json.dumps(batch_compare()))
         return
+    if args.workload == "paper_100":
+        print(json.dumps(paper_sweep()))
+        return
     w = workload(WORKLOAD)
     prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
                    pnorm=w["p"], k0=w["k0"], kmin=w["kmin"], pk=w["pk"], c0=w["c0"],
@@ -418,6 +587,12 @@ def main():
     }
     if not args.no_precision_compare:
         out["vs_fp64"] = precision_compare(prob, rho, gT, gth, gl)
+    if not args.no_plt:
+        out["plt"] = plt_compare(prob, rho, ms, float(cyc.Theta))
+        seq = sequential_reference(prob, rho)
+        seq["speedup_parareal_fp64"] = seq["ms_per_cycle"] / ms
+        seq["speedup_plt_fp64"] = seq["ms_per_cycle"] / out["plt"]["fp64"]["ms_per_cycle"]
+        out["sequential_reference"] = seq
     if not args.no_batch:
         del cyc
         torch.cuda.empty_cache()

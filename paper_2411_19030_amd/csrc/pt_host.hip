@@ -687,6 +687,12 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
         }
         const int avail = (grid - lat_wgs) / g_min;  // groups left for batched lanes
         if (avail < nq) resident = false;
+        // without a sequential sweep (G = 0) the lanes are the whole pass:
+        // resident groups that cannot hold every lane at once leave the
+        // streaming form (all lanes at once, HBM-bound) ahead
+        int lanes = 0;
+        for (const auto &p : plans) lanes += p.latency ? 0 : p.count;
+        if (lat_wgs == 0 && avail < lanes && env_int("PT_RESIDENT", -1) != 1) resident = false;
     }
     if (resident) {
         int nq = 0;

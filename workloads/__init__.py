@@ -16,6 +16,11 @@ optimised design field is not given, so seeded densities stand in for it):
 * ``large_2048``        2048x2048, N_t=2048 in 128 slices, smooth field
 * ``large_law_512``     the large design's density law and solver at 512x512,
                         N_t=512 in 32 slices (small enough for the oracle)
+* ``paper_100``         the paper's own test case (Sec. 5.1): 100x100 elements,
+                        N_t=480, Table 1 materials (c-SIMP), q(t) of Eq. 5.1,
+                        the Dirichlet patch at the centre tenth of the bottom
+                        edge, p = 20; a seeded branched design stands in for
+                        the paper's optimised design
 """
 from __future__ import annotations
 
@@ -39,7 +44,40 @@ WORKLOADS = {
                        rtol=1e-10, precision="fp32_refine"),
     "large_law_512": dict(nx=512, ny=512, n_steps=512, n_slices=32, seed=4,
                           rtol=1e-10, precision="fp32_refine"),
+    # Table 1: k0 = 3, kmin = 0.03, c0 = 1, cmin = 0.5, pk = 3, pc = 2; p = 20
+    "paper_100": dict(nx=100, ny=100, n_steps=480, n_slices=10, seed=5, rtol=1e-12,
+                      precision="fp64", k0=3.0, kmin=0.03, pk=3.0, c0=1.0, cmin=0.5,
+                      pc=2.0, p=20, bc="bottom_centre", q="paper"),
 }
+
+
+def heat_load_paper(n_steps: int, t_final: float = 1.0) -> np.ndarray:
+    """q(t_n) = (1 - t)(1 + cos 50 t)/2 at t_n = n t_T / N_t, n = 0..N_t (Eq. 5.1)."""
+    t = np.arange(n_steps + 1) * (t_final / n_steps)
+    return 0.5 * (1.0 - t) * (1.0 + np.cos(50.0 * t))
+
+
+def density_branches(nx: int, ny: int, seed: int, n_arms: int = 7) -> np.ndarray:
+    """A branched conductor grown from the centre of the bottom edge, standing in
+    for an optimised heat-conduction design: seeded straight arms from (0.5, 0)
+    at angles spread over (10, 170) degrees, lengths U[0.45, 0.9], half-widths
+    U[0.015, 0.04]; rho = 0.1 + 0.9 max_arms exp(-d^2 / (2 w^2)) at element
+    centroids, d the distance to the arm."""
+    rng = np.random.default_rng(seed)
+    base = np.linspace(10.0, 170.0, n_arms)
+    ang = np.deg2rad(base + rng.uniform(-8.0, 8.0, n_arms))
+    length = rng.uniform(0.45, 0.9, n_arms)
+    width = rng.uniform(0.015, 0.04, n_arms)
+    xc = (np.arange(nx) + 0.5) / nx
+    yc = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(xc, yc)
+    field = np.zeros((ny, nx))
+    for k in range(n_arms):
+        ux, uy = np.cos(ang[k]), np.sin(ang[k])
+        s = np.clip((X - 0.5) * ux + Y * uy, 0.0, length[k])
+        d2 = (X - 0.5 - s * ux) ** 2 + (Y - s * uy) ** 2
+        field = np.maximum(field, np.exp(-d2 / (2 * width[k] ** 2)))
+    return np.clip(0.1 + 0.9 * field, 0.0, 1.0).reshape(-1).astype(np.float64)
 
 
 def density_uniform_noise(nx: int, ny: int, seed: int, base: float = 0.3,
@@ -96,6 +134,8 @@ def workload(name: str) -> dict:
     """Full parameter dict of a named workload, physics included."""
     w = dict(PHYSICS)
     w.update(WORKLOADS[name])
+    if isinstance(w["q"], str):
+        w["q"] = heat_load_paper(w["n_steps"], w["t_final"])
     w["name"] = name
     return w
 
@@ -104,4 +144,6 @@ def workload_density(name: str) -> np.ndarray:
     w = WORKLOADS[name]
     if name in ("large_2048", "large_law_512"):
         return density_gaussians(w["nx"], w["ny"], w["seed"])
+    if name == "paper_100":
+        return density_branches(w["nx"], w["ny"], w["seed"])
     return density_uniform_noise(w["nx"], w["ny"], w["seed"])
