@@ -8,13 +8,16 @@ common are the seeded arrays from ``workloads``.
 It is a plain, slow implementation written from the paper: assembled sparse
 Q1 matrices, a sparse direct solve per backward-Euler step, the sequential
 reference method, the modified / time-reversed Parareal passes step by step
-in the paper's order, and the zero-coarse-propagator (PLT) form of Sec. 7.
+in the paper's order, the zero-coarse-propagator (PLT) form of Sec. 7, and
+the design filter and projection of Sec. 2.1.
 Pins against closed forms, invariants and finite differences live in
 ``tests/test_oracle_*.py``.
 
 Every function is pinned; see the tests' docstrings for which property pins
 which part.
 """
+from .design import (filter_matrix, filter_projection, filter_projection_backward,
+                     projection, projection_deriv)
 from .fem import (Discretisation, Problem, dirichlet_mask, element_matrices,
                   element_nodes, simp, simp_deriv)
 from .parareal import (F_adj, F_pri, G_adj, G_pri, one_cycle, parareal_adjoint,
@@ -29,4 +32,6 @@ __all__ = [
     "one_cycle", "parareal_adjoint", "parareal_forward", "adjoint_sequential",
     "adjoint_source", "forward_sequential", "h_adj", "h_pri", "pnorm_p",
     "F_adj_tilde", "h_adj_tilde", "plt_adjoint", "plt_forward", "plt_objective",
+    "filter_matrix", "filter_projection", "filter_projection_backward", "projection",
+    "projection_deriv",
 ]
