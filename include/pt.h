@@ -196,6 +196,40 @@ int pt_query_status(const void *ws, hipStream_t stream, pt_stats *out);
 const char *pt_strerror(int code);
 
 /* ------------------------------------------------------------------------
+ * Design-field front end (Sec. 2.1): chi -> chi_fil = H chi -> chi_phys = P(chi_fil),
+ * the input rho of the calls above, and the adjoint of that map.
+ *   H: chi_fil_e = sum_i w_ei chi_i / W_e, w_ei = max(0, r_fil - |x_e - x_i|),
+ *      W_e = sum_i w_ei, over element centroids x_e = ((i+1/2)/nx, (j+1/2)/ny)
+ *      (elements off the grid are left out of both sums);
+ *   P: (tanh(beta (x - eta)) + tanh(beta eta)) / (tanh(beta (1 - eta)) + tanh(beta eta))
+ *      (the identity when beta <= 0).
+ * Element arrays are [N_e] FP64 device arrays, element (i, j) at j nx + i.
+ * ------------------------------------------------------------------------ */
+typedef struct pt_filter {
+    int32_t nx, ny;            /* elements along x and y, 1..16384                               */
+    double r_fil;              /* filter radius > 0 in unit-square coordinates; a radius of      */
+                               /* more than 255 elements (either direction) is rejected          */
+    double beta;               /* projection sharpness; <= 0: no projection                      */
+    double eta;                /* projection threshold in [0, 1]                                  */
+} pt_filter;
+
+/* Host-side check of a filter description: PT_OK or PT_EINVAL. */
+int pt_filter_validate(const pt_filter *f);
+
+/* chi_fil (may be NULL) and chi_phys from chi. No array may overlap another.
+ * Returns PT_OK once enqueued. */
+int pt_filter_projection(const pt_filter *f, const double *chi, double *chi_fil, double *chi_phys,
+                         hipStream_t stream);
+
+/* grad_chi = H^T (P'(chi_fil) o grad_phys): the gradient with respect to chi of a
+ * function whose gradient with respect to chi_phys is grad_phys. chi_fil is the
+ * forward's output; work is caller-owned [N_e] scratch, overwritten. No array
+ * may overlap another. Returns PT_OK once enqueued. */
+int pt_filter_projection_backward(const pt_filter *f, const double *chi_fil,
+                                  const double *grad_phys, double *work, double *grad_chi,
+                                  hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Many designs in one cycle (one persistent launch per pass for all designs).
  *
  * Each design is an independent problem of its own grid and slice count; all

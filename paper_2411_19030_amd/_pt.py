@@ -26,7 +26,8 @@ PT_PARAREAL, PT_PLT = 0, 1
 EXPORTS = ["pt_workspace_bytes", "pt_state_bytes", "pt_validate", "pt_parareal_forward", "pt_parareal_adjoint",
            "pt_sensitivities", "pt_query_status", "pt_query_trace", "pt_strerror",
            "pt_batched_workspace_bytes", "pt_batch_default_tuning", "pt_parareal_batched",
-           "pt_batched_status", "pt_autotune_batched"]
+           "pt_batched_status", "pt_autotune_batched", "pt_filter_validate",
+           "pt_filter_projection", "pt_filter_projection_backward"]
 
 
 class PtProblem(ctypes.Structure):
@@ -72,6 +73,11 @@ class PtBatchTuning(ctypes.Structure):
         for k in ("fine_wgs", "sweep_wgs", "sweep_groups", "resident", "grid"):
             setattr(t, k, int(d.get(k, 0)))
         return t
+
+
+class PtFilter(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("r_fil", ctypes.c_double),
+                ("beta", ctypes.c_double), ("eta", ctypes.c_double)]
 
 
 _lib = None
@@ -121,6 +127,13 @@ def load_library(path: str = LIB_PATH):
     lib.pt_autotune_batched.argtypes = [ctypes.c_int, P, pp, vp, pp, vp, ctypes.c_size_t, vp, TP,
                                         ctypes.POINTER(ctypes.c_double)]
     lib.pt_autotune_batched.restype = ctypes.c_int
+    FP = ctypes.POINTER(PtFilter)
+    lib.pt_filter_validate.argtypes = [FP]
+    lib.pt_filter_validate.restype = ctypes.c_int
+    lib.pt_filter_projection.argtypes = [FP, vp, vp, vp, vp]
+    lib.pt_filter_projection.restype = ctypes.c_int
+    lib.pt_filter_projection_backward.argtypes = [FP, vp, vp, vp, vp, vp]
+    lib.pt_filter_projection_backward.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -355,3 +368,30 @@ def pt_autotune_batched(probs, rhos, Theta_out, grads, ws, stream=None) -> tuple
         ws.numel() * ws.element_size(), _stream(stream), ctypes.byref(t), ctypes.byref(ms)),
         "pt_autotune_batched")
     return t.as_dict(), ms.value
+
+
+# ---------------------------------------------------------------------------
+# Design-field front end (filter and projection)
+# ---------------------------------------------------------------------------
+
+def make_filter(nx: int, ny: int, r_fil: float, beta: float, eta: float) -> PtFilter:
+    f = PtFilter()
+    f.nx, f.ny = int(nx), int(ny)
+    f.r_fil, f.beta, f.eta = float(r_fil), float(beta), float(eta)
+    return f
+
+
+def pt_filter_validate(f: PtFilter) -> int:
+    return load_library().pt_filter_validate(ctypes.byref(f))
+
+
+def pt_filter_projection(f: PtFilter, chi, chi_fil, chi_phys, stream=None):
+    _check(load_library().pt_filter_projection(ctypes.byref(f), _ptr(chi), _ptr(chi_fil),
+                                               _ptr(chi_phys), _stream(stream)),
+           "pt_filter_projection")
+
+
+def pt_filter_projection_backward(f: PtFilter, chi_fil, grad_phys, work, grad_chi, stream=None):
+    _check(load_library().pt_filter_projection_backward(
+        ctypes.byref(f), _ptr(chi_fil), _ptr(grad_phys), _ptr(work), _ptr(grad_chi),
+        _stream(stream)), "pt_filter_projection_backward")

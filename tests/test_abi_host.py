@@ -190,3 +190,29 @@ def test_state_bytes_store_all_and_checkpoint(lib):
     # a batch accepts only store-all designs
     arr = (PtProblem * 2)(base().to_c(), base(storage=1).to_c())
     assert lib.pt_batched_workspace_bytes(2, arr) == 0
+
+
+@pytest.mark.parametrize("kw", [dict(nx=0), dict(ny=-3), dict(r_fil=0.0), dict(r_fil=float("nan")),
+                                dict(eta=1.5), dict(eta=-0.1), dict(beta=float("inf")),
+                                dict(nx=4096, ny=4096, r_fil=0.1)])
+def test_filter_validate_rejects(lib, kw):
+    a = dict(nx=16, ny=16, r_fil=0.1, beta=8.0, eta=0.5)
+    a.update(kw)
+    f = _pt.make_filter(**a)
+    assert _pt.pt_filter_validate(f) == _pt.PT_EINVAL
+    assert lib.pt_filter_projection(ctypes.byref(f), 0x1000, None, 0x2000000, None) == _pt.PT_EINVAL
+
+
+def test_filter_argument_errors_before_any_device_work(lib):
+    f = _pt.make_filter(16, 16, 0.1, 8.0, 0.5)
+    assert _pt.pt_filter_validate(f) == _pt.PT_OK
+    n = 16 * 16 * 8
+    # missing arrays, overlapping arrays
+    assert lib.pt_filter_projection(ctypes.byref(f), None, None, 0x100000, None) == _pt.PT_EINVAL
+    assert lib.pt_filter_projection(ctypes.byref(f), 0x100000, None, 0x100000 + n // 2,
+                                    None) == _pt.PT_EINVAL
+    assert lib.pt_filter_projection_backward(ctypes.byref(f), 0x100000, 0x200000, None, 0x300000,
+                                             None) == _pt.PT_EINVAL
+    assert lib.pt_filter_projection_backward(ctypes.byref(f), 0x100000, 0x200000, 0x300000,
+                                             0x300000 + 8, None) == _pt.PT_EINVAL
+
