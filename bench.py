@@ -62,7 +62,7 @@ def parse():
                     help="skip the 64-design batch (batched FP32+refine vs plain FP64)")
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=[WORKLOAD, "batch_fp32_64", "large_2048", "large_law_512",
-                             "paper_100"],
+                             "paper_100", "one_shot_chain"],
                     help="the headline workload (default), or one of the other workloads "
                          "measured on its own")
     ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
@@ -336,6 +336,89 @@ def paper_sweep(slices=(5, 10, 20, 30), max_iters=8, repeats=1) -> dict:
     return out
 
 
+def one_shot_chain(n_cycles=30, Ntau=30) -> dict:
+    """Alg. 3 over a seeded design schedule on the paper's test case.
+
+    The designs chi_i come from `design_schedule`. It starts from the branched
+    design and takes smooth seeded steps that shrink by 0.9 per cycle; this
+    stands in for the optimiser's iterates, so all methods see the same designs.
+    Each passes the filter and projection of Sec. 6.1 (r = 0.03, beta = 32,
+    eta = 0.5). Per cycle the sequential method (one slice) gives Theta and
+    dTheta/dchi. One-shot Parareal and one-shot PLT (N_tau slices, one
+    iteration) restart from their own previous cycle; their first cycle is
+    exact (N_tau iterations), as Alg. 3 starts with a sequential cycle.
+    Reported per cycle: the objective and sensitivity errors of both one-shot
+    estimates and the cycle times (forward, backward and the filter)."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2411_19030_amd import Problem
+    from paper_2411_19030_amd.autograd import OneShotParareal
+    from paper_2411_19030_amd.cycle import Cycle
+    from paper_2411_19030_amd.design import DesignFilter
+    from workloads import density_branches, design_schedule, workload
+    w = workload("paper_100")
+    nx, ny = w["nx"], w["ny"]
+    base = Problem(nx=nx, ny=ny, n_steps=w["n_steps"], n_slices=Ntau, pnorm=w["p"], k0=w["k0"],
+                   kmin=w["kmin"], pk=w["pk"], c0=w["c0"], cmin=w["cmin"], pc=w["pc"], q=w["q"],
+                   t_final=w["t_final"], bc=w["bc"], iterations=1, cg_rtol=w["rtol"],
+                   max_iter=50000)
+    dev = torch.device("cuda:0")
+    flt = DesignFilter(nx, ny, 0.03, 32.0, 0.5)
+    designs = design_schedule(nx, ny, 6, n_cycles, start=density_branches(nx, ny, w["seed"]))
+    seq = OneShotParareal(dataclasses.replace(base, n_slices=1), dev, warm=False)
+    methods = {"parareal": OneShotParareal(base, dev, warm=True),
+               "plt": OneShotParareal(dataclasses.replace(base, propagator=1), dev, warm=True)}
+    stream = torch.cuda.current_stream()
+
+    def run(obj, chi):
+        x = torch.tensor(chi, device=dev, requires_grad=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        th = obj(flt(x))
+        th.backward()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return float(th), x.grad.clone(), e0.elapsed_time(e1)
+
+    rows = []
+    for i, chi in enumerate(designs):
+        th_s, g_s, t_s = run(seq, chi)
+        row = {"cycle": i, "Theta_seq": th_s, "ms_seq": t_s}
+        for name, obj in methods.items():
+            if i == 0:
+                # the exact first cycle: N_tau iterations, its outputs are the guesses
+                ex = Cycle(dataclasses.replace(obj.prob, iterations=Ntau), dev)
+                rho = flt(torch.tensor(chi, device=dev))
+                ex.run(rho)
+                obj.guess_T, obj.guess_theta = ex.uT.clone(), ex.utheta.clone()
+                obj.guess_lambda = ex.lam.clone()
+                torch.cuda.synchronize()
+                del ex
+                continue
+            th, g, t = run(obj, chi)
+            row[name] = {"objective_error": abs(th - th_s) / th_s,
+                         "sensitivity_error": float(torch.linalg.norm(g - g_s) /
+                                                    torch.linalg.norm(g_s)),
+                         "ms": t, "speedup": t_s / t}
+        rows.append(row)
+        print("one_shot_chain", json.dumps(row), file=sys.stderr, flush=True)
+    summary = {}
+    for name in methods:
+        r = [x[name] for x in rows[1:]]
+        summary[name] = {
+            "max_objective_error": max(x["objective_error"] for x in r),
+            "max_sensitivity_error": max(x["sensitivity_error"] for x in r),
+            "median_sensitivity_error": float(np.median([x["sensitivity_error"] for x in r])),
+            "mean_speedup": float(np.mean([x["speedup"] for x in r]))}
+    return {"workload": "paper_100", "n_slices": Ntau, "cycles": n_cycles,
+            "filter": {"r_fil": 0.03, "beta": 32.0, "eta": 0.5},
+            "schedule": "design_schedule(seed 6) from density_branches, step 0.08, decay 0.9",
+            "summary": summary, "rows": rows}
+
+
 # Worker shapes of the 64-design batch chosen by pt_autotune_batched on the
 # MI355X (coordinate descent over fine/sweep workgroups and sweep workers).
 BATCH_TUNING = {"fine_wgs": 4, "sweep_wgs": 8, "sweep_groups": 8, "resident": 0, "grid": 0}
@@ -499,6 +582,9 @@ def main():
         return
     if args.workload == "paper_100":
         print(json.dumps(paper_sweep()))
+        return
+    if args.workload == "one_shot_chain":
+        print(json.dumps(one_shot_chain()))
         return
     w = workload(WORKLOAD)
     prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],

@@ -108,6 +108,31 @@ def density_gaussians(nx: int, ny: int, seed: int, n_blobs: int = 32) -> np.ndar
     return np.clip(field, 0.0, 1.0).reshape(-1).astype(np.float64)
 
 
+def design_schedule(nx: int, ny: int, seed: int, n_cycles: int, start=0.3,
+                    step: float = 0.08, decay: float = 0.9, n_blobs: int = 12):
+    """A seeded sequence of design fields chi_0 .. chi_{n-1} standing in for the
+    iterates of an optimiser: chi_0 = start (a value everywhere, or an [N_e]
+    field), chi_{i+1} = clip(chi_i + step decay^i b_i, 0, 1) with b_i a sum of
+    seeded signed Gaussian bumps scaled to max |b_i| = 1."""
+    rng = np.random.default_rng(seed)
+    xc = (np.arange(nx) + 0.5) / nx
+    yc = (np.arange(ny) + 0.5) / ny
+    chi = np.broadcast_to(np.asarray(start, dtype=np.float64), (nx * ny,)).copy()
+    out = [chi.copy()]
+    for i in range(n_cycles - 1):
+        b = np.zeros((ny, nx))
+        for _ in range(n_blobs):
+            cx, cy = rng.uniform(0, 1, 2)
+            sig = rng.uniform(0.05, 0.2)
+            sgn = rng.choice([-1.0, 1.0])
+            b += sgn * np.outer(np.exp(-(yc - cy) ** 2 / (2 * sig ** 2)),
+                                np.exp(-(xc - cx) ** 2 / (2 * sig ** 2)))
+        b /= np.abs(b).max()
+        chi = np.clip(chi + step * decay ** i * b.reshape(-1), 0.0, 1.0)
+        out.append(chi.copy())
+    return out
+
+
 def batch_designs(seed: int = 3, n_designs: int = 64):
     """The multi-design batch: per design a side, a slice count and a density."""
     ss = np.random.SeedSequence(seed)
