@@ -595,6 +595,7 @@ int reset_launch_state(void *ws, const SharedLayout &S, int n_designs, hipStream
 // buffer must outlive the call.
 struct Run {
     int kind, ngroups, nwg, tile, s0, gstride, lstride, nlanes, smin, smax;
+    int lead_kind, lead_slice;  // a lane run first by every group of the run (kind < 0: none)
 };
 
 struct PlanArgs {
@@ -616,6 +617,13 @@ __global__ void k_build_plan(PlanArgs P, Group *groups, Lane *lanes, int *wg_gro
             G.queue = -1;
             G.lane0 = lidx;
             int n = 0;
+            if (R.lead_kind >= 0) {
+                lanes[lidx].kind = R.lead_kind;
+                lanes[lidx].slice = R.lead_slice;
+                lanes[lidx].design = 0;
+                lanes[lidx].tile = R.tile;
+                ++n;
+            }
             for (int k = 0; k < R.nlanes; ++k) {
                 const int sl = R.s0 + q * R.gstride + k * R.lstride;
                 if (sl < R.smin || sl > R.smax) continue;
@@ -645,6 +653,7 @@ struct LanePlan {
     bool latency;     // sweep-like: fixed group size
     int queues = 0;   // groups (0: one lane per group)
     int fixed_nwg = 0;  // workgroups per group if > 0 (same fine shape in both passes)
+    int lead_kind = -1, lead_slice = 0;  // a lane the group runs first (one group only)
 };
 
 // Runs one single-design engine launch with descriptor D (already uploaded).
@@ -810,6 +819,8 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
         R.nlanes = per_group[k];
         R.smin = std::min(p.slice0, p.slice0 + p.dir * (p.count - 1));
         R.smax = std::max(p.slice0, p.slice0 + p.dir * (p.count - 1));
+        R.lead_kind = p.lead_kind;
+        R.lead_slice = p.lead_slice;
     }
     hipLaunchKernelGGL(k_build_plan, dim3(1), dim3(64), 0, stream, P, at<Group>(ws, Lay.s.groups),
                        at<Lane>(ws, Lay.s.lanes), at<int>(ws, Lay.s.wg_group));
@@ -833,6 +844,16 @@ LanePlan fine_plan(int kind, int count, int slice0, int dir, const Consts &C,
         lp.fixed_nwg = fixed > 0 ? fixed : 8;
     }
     return lp;
+}
+
+// The correction sweep's first step needs the first fine slice of its pass
+// (F_0, or the last slice in the adjoint); its group runs that slice itself
+// rather than waiting for a fine group. Not with a fixed fine-lane shape
+// (checkpoints), where both passes must run every fine slice alike.
+bool lead_fine(const Consts &C, const pt_problem *p, int Ntau, bool plt) {
+    (void)p;
+    if (plt || Ntau < 2 || C.ckpt || env_int("PT_FINE_WGS", 0) > 0) return false;
+    return env_int("PT_LEAD_FINE", 1) != 0;
 }
 
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
@@ -1127,12 +1148,21 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
         B.Theta_out = Theta_out;
         PT_TRY(upload_descs(hd, D, stream));
         std::vector<LanePlan> plans;
-        plans.push_back(fine_plan(F_PRI, Ntau, 0, +1, C, prob));
+        // the sweep cannot start before F_0: its group runs F_0 itself
+        const bool lead = lead_fine(C, prob, Ntau, plt);
+        plans.push_back(lead ? fine_plan(F_PRI, Ntau - 1, 1, +1, C, prob)
+                             : fine_plan(F_PRI, Ntau, 0, +1, C, prob));
         if (I.gk_lanes)
             plans.push_back({GK_PRI, Ntau - 1, 1, +1, env_double("PT_GK_WEIGHT", 4.0), false,
                              env_int("PT_GQUEUES", 0)});
         if (I.cold) plans.push_back({COLD_PRI, 1, 0, +1, 0.0, true, 0});
-        if (Ntau > 1 && !plt) plans.push_back({SWEEP_PRI, 1, 0, +1, 0.0, true, 0});
+        if (Ntau > 1 && !plt) {
+            plans.push_back({SWEEP_PRI, 1, 0, +1, 0.0, true, 0});
+            if (lead) {
+                plans.back().lead_kind = F_PRI;
+                plans.back().lead_slice = 0;
+            }
+        }
         PT_TRY(run_engine(E, D, plans, ws, Lay, stream));
         if (it + 1 < prob->iterations) {
             hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Uprev, outT, Nt1 * Nn);
@@ -1196,12 +1226,20 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
         PT_TRY(upload_descs(hd, D, stream));
         std::vector<LanePlan> plans;
         // the reversed sweep consumes slices from N_tau downwards
-        plans.push_back(fine_plan(F_ADJ, Ntau, Ntau, -1, C, prob));
+        const bool lead = lead_fine(C, prob, Ntau, plt);
+        plans.push_back(lead ? fine_plan(F_ADJ, Ntau - 1, Ntau - 1, -1, C, prob)
+                             : fine_plan(F_ADJ, Ntau, Ntau, -1, C, prob));
         if (I.gk_lanes)
             plans.push_back({GK_ADJ, Ntau - 1, Ntau - 1, -1, env_double("PT_GK_WEIGHT", 4.0),
                              false, env_int("PT_GQUEUES", 0)});
         if (I.cold) plans.push_back({COLD_ADJ, 1, 0, +1, 0.0, true, 0});
-        if (Ntau > 1 && !plt) plans.push_back({SWEEP_ADJ, 1, 0, +1, 0.0, true, 0});
+        if (Ntau > 1 && !plt) {
+            plans.push_back({SWEEP_ADJ, 1, 0, +1, 0.0, true, 0});
+            if (lead) {
+                plans.back().lead_kind = F_ADJ;
+                plans.back().lead_slice = Ntau;
+            }
+        }
         PT_TRY(run_engine(E, D, plans, ws, Lay, stream));
         if (it + 1 < prob->iterations) {
             hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Lprev, outL, Nt1 * Nn);
