@@ -598,10 +598,20 @@ struct Run {
     int lead_kind, lead_slice;  // a lane run first by every group of the run (kind < 0: none)
 };
 
+// Groups of one shape taking two kinds of lanes from shared queue 0, in the
+// order the correction sweep consumes them: slice by slice along dirA, lane
+// kind A before kind B of the same slice.
+struct QueueArgs {
+    int ngroups, nwg, tile;
+    int kindA, nA, sA0, dirA;
+    int kindB, nB, sB0, dirB;
+};
+
 struct PlanArgs {
     int grid;
     int nruns;
     Run run[6];
+    QueueArgs Q;
 };
 
 __global__ void k_build_plan(PlanArgs P, Group *groups, Lane *lanes, int *wg_group) {
@@ -637,6 +647,35 @@ __global__ void k_build_plan(PlanArgs P, Group *groups, Lane *lanes, int *wg_gro
             lidx += n;
             groups[gidx] = G;
             for (int k = 0; k < R.nwg; ++k) wg_group[w++] = gidx;
+            ++gidx;
+        }
+    }
+    const QueueArgs &Q = P.Q;
+    if (Q.ngroups > 0) {
+        const int lane0 = lidx;
+        // merge the two slice sequences by position along the sweep
+        int ia = 0, ib = 0;
+        while (ia < Q.nA || ib < Q.nB) {
+            const int sa = Q.sA0 + Q.dirA * ia, sb = Q.sB0 + Q.dirB * ib;
+            const bool takeA = ib >= Q.nB || (ia < Q.nA && Q.dirA * sa <= Q.dirA * sb);
+            lanes[lidx].kind = takeA ? Q.kindA : Q.kindB;
+            lanes[lidx].slice = takeA ? sa : sb;
+            lanes[lidx].design = 0;
+            lanes[lidx].tile = Q.tile;
+            ++lidx;
+            if (takeA) ++ia;
+            else ++ib;
+        }
+        for (int q = 0; q < Q.ngroups; ++q) {
+            Group G;
+            G.wg0 = w;
+            G.nwg = Q.nwg;
+            G.vec = gidx;
+            G.queue = 0;
+            G.lane0 = lane0;
+            G.nlanes = lidx - lane0;
+            groups[gidx] = G;
+            for (int k = 0; k < Q.nwg; ++k) wg_group[w++] = gidx;
             ++gidx;
         }
     }
@@ -804,9 +843,38 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
     PlanArgs P{};
     P.grid = grid;
     P.nruns = 0;
+    // resident fine and batched coarse lanes of one shape: one shared queue in
+    // sweep order instead of private lists (balances lanes of unequal length)
+    int qa = -1, qb = -1;
+    if (resident && env_int("PT_SHARED_QUEUE", 1) != 0) {
+        for (size_t k = 0; k < plans.size(); ++k) {
+            if (plans[k].latency || plans[k].count == 0) continue;
+            if (qa < 0) qa = (int)k;
+            else if (qb < 0) qb = (int)k;
+            else qa = qb = -2;
+        }
+        if (qa >= 0 && qb >= 0 &&
+            (nwg[qa] != nwg[qb] || tile[qa] != tile[qb] || plans[qa].dir != plans[qb].dir))
+            qa = qb = -1;
+        if (qb < 0) qa = qb = -1;
+    }
+    if (qa >= 0) {
+        QueueArgs &Q = P.Q;
+        Q.ngroups = ngroups[qa] + ngroups[qb];
+        Q.nwg = nwg[qa];
+        Q.tile = tile[qa];
+        Q.kindA = plans[qa].kind;
+        Q.nA = plans[qa].count;
+        Q.sA0 = plans[qa].slice0;
+        Q.dirA = plans[qa].dir;
+        Q.kindB = plans[qb].kind;
+        Q.nB = plans[qb].count;
+        Q.sB0 = plans[qb].slice0;
+        Q.dirB = plans[qb].dir;
+    }
     for (size_t k = 0; k < plans.size(); ++k) {
         const auto &p = plans[k];
-        if (p.count == 0) continue;
+        if (p.count == 0 || (int)k == qa || (int)k == qb) continue;
         if (P.nruns >= 6) return PT_EINVAL;
         Run &R = P.run[P.nruns++];
         R.kind = p.kind;
