@@ -1545,11 +1545,14 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                     const int ppar = (nbar - 1) & 1;  // parity of the previous round
                     int tid = threadIdx.x;
                     asm volatile("" : "+v"(tid));  // per-round index math (not hoisted)
+                    // x of the tile is read and written only by its owning thread
+                    // during the rounds: plain (cached) accesses; leaving the
+                    // rounds releases them before any other workgroup reads x
                     double xo[NR];
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
                         const int id = a + tid + k * kThreads;
-                        xo[k] = id < b ? ldc(X + id) : 0.0;
+                        xo[k] = id < b ? X[id] : 0.0;
                     }
                     lds_sync();
                     if (hp_ok) {
@@ -1588,7 +1591,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                             const Real zi = dk * rr[k];
                             const Real pn = first ? zi : zi + (Real)be * rp[k];
                             const Real sn = first ? rw[k] : rw[k] + (Real)be * rs[k];
-                            stc(X + id, xo[k] + al * (double)pn);
+                            X[id] = xo[k] + al * (double)pn;
                             rr[k] -= (Real)al * sn;
                             rp[k] = pn;
                             rs[k] = sn;
@@ -1720,10 +1723,20 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                         c.verifying = true;
                         c.restarts += 1;
                         c.phase = PH_INIT;
+                        if constexpr (NPT > 0) {
+                            // the residual reads the neighbours' x: release the rounds' stores
+                            ok = barrier(true);
+                            if (!ok) break;
+                        }
                     } else {
                         c.phase = PH_POST;
                         if (rn > C.rtol * c.bnorm && rank == 0 && threadIdx.x == 0)
                             set_status(ctl, -4);
+                        if constexpr (NPT > 0) {
+                            // adjoint POST reads the neighbours' x
+                            ok = barrier(true);
+                            if (!ok) break;
+                        }
                     }
                 } else {
                     const double gnew = tot[0];
@@ -1745,7 +1758,8 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                     const int a = t * TS;
                     const int b = min(a + TS, C.Nn);
                     for (int id = a + threadIdx.x; id < b; id += kThreads) {
-                        const double x = zx ? 0.0 : ldc(X + id);
+                        // resident: the owning thread of the rounds reads its own x
+                        const double x = zx ? 0.0 : (NPT > 0 ? X[id] : ldc(X + id));
                         switch (L.kind) {
                             case F_PRI: {
                                 if (double *Sj = srow(C, B, st.j, nullptr)) Sj[id] = x;
