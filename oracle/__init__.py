@@ -8,14 +8,16 @@ common are the seeded arrays from ``workloads``.
 It is a plain, slow implementation written from the paper: assembled sparse
 Q1 matrices, a sparse direct solve per backward-Euler step, the sequential
 reference method, the modified / time-reversed Parareal passes step by step
-in the paper's order, the zero-coarse-propagator (PLT) form of Sec. 7, and
-the design filter and projection of Sec. 2.1.
+in the paper's order, the zero-coarse-propagator (PLT) form of Sec. 7, a
+cheaper (truncated-solve) coarse propagator, and the design filter and
+projection of Sec. 2.1.
 Pins against closed forms, invariants and finite differences live in
 ``tests/test_oracle_*.py``.
 
 Every function is pinned; see the tests' docstrings for which property pins
 which part.
 """
+from .coarse import make_G_adj, make_G_pri, pcg_fixed
 from .design import (filter_matrix, filter_projection, filter_projection_backward,
                      projection, projection_deriv)
 from .fem import (Discretisation, Problem, dirichlet_mask, element_matrices,
@@ -33,5 +35,5 @@ __all__ = [
     "adjoint_source", "forward_sequential", "h_adj", "h_pri", "pnorm_p",
     "F_adj_tilde", "h_adj_tilde", "plt_adjoint", "plt_forward", "plt_objective",
     "filter_matrix", "filter_projection", "filter_projection_backward", "projection",
-    "projection_deriv",
+    "projection_deriv", "make_G_adj", "make_G_pri", "pcg_fixed",
 ]

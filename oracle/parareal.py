@@ -54,12 +54,14 @@ def F_pri(d: Discretisation, T: np.ndarray, theta: float, n: int):
 
 
 def parareal_forward(d: Discretisation, iterations: int = 1, guess_T=None,
-                     guess_theta=None):
+                     guess_theta=None, G=None):
     """Modified Parareal for (T, theta).
 
+    G: the coarse propagator (default G_pri; any function of (d, T, theta, n)).
     Returns dict with S (N_t, N_n), uT (N_tau+1, N_n), utheta (N_tau+1,),
     Theta, and the initial guess that was used.
     """
+    G_pri_ = G_pri if G is None else G
     P = d.prob
     Nt, M = P.n_slices, P.M
     zero = np.zeros(P.n_nodes)
@@ -68,7 +70,7 @@ def parareal_forward(d: Discretisation, iterations: int = 1, guess_T=None,
         uT = [zero]
         uth = [0.0]
         for n in range(Nt):
-            T, th = G_pri(d, uT[n], uth[n], n)
+            T, th = G_pri_(d, uT[n], uth[n], n)
             uT.append(T)
             uth.append(th)
         GkT = [uT[n + 1] for n in range(Nt)]
@@ -92,13 +94,13 @@ def parareal_forward(d: Discretisation, iterations: int = 1, guess_T=None,
         if GkT is None:
             GkT, Gkth = [], []
             for n in range(Nt):
-                T, th = G_pri(d, uT[n], uth[n], n)
+                T, th = G_pri_(d, uT[n], uth[n], n)
                 GkT.append(T)
                 Gkth.append(th)
         newT, newth = [zero], [0.0]
         GnT, Gnth = [], []
         for n in range(Nt):
-            gT, gth = G_pri(d, newT[n], newth[n], n)
+            gT, gth = G_pri_(d, newT[n], newth[n], n)
             GnT.append(gT)
             Gnth.append(gth)
             newT.append(gT + FT[n] - GkT[n])
@@ -139,12 +141,15 @@ def F_adj(d: Discretisation, S: np.ndarray, Theta: float, lam: np.ndarray,
 
 
 def parareal_adjoint(d: Discretisation, S: np.ndarray, Theta: float,
-                     iterations: int = 1, guess_lambda=None):
+                     iterations: int = 1, guess_lambda=None, G=None):
     """Time-reversed vanilla Parareal for (lambda, g).
 
+    G: the coarse propagator (default G_adj; any function of
+    (d, S, Theta, lam, g, n)).
     Returns dict with lam (N_tau+1, N_n) where lam[n] estimates lambda_{Mn+1}
     (lam[N_tau] = 0), grad = g-part of v_0, and the guess that was used.
     """
+    G_adj_ = G_adj if G is None else G
     P = d.prob
     Nt = P.n_slices
     zl = np.zeros(P.n_nodes)
@@ -154,7 +159,7 @@ def parareal_adjoint(d: Discretisation, S: np.ndarray, Theta: float,
         vg = [None] * (Nt + 1)
         vl[Nt], vg[Nt] = zl, zg
         for n in range(Nt, 0, -1):
-            vl[n - 1], vg[n - 1] = G_adj(d, S, Theta, vl[n], vg[n], n)
+            vl[n - 1], vg[n - 1] = G_adj_(d, S, Theta, vl[n], vg[n], n)
         Gkl = {n: vl[n - 1] for n in range(1, Nt + 1)}
         Gkg = {n: vg[n - 1] for n in range(1, Nt + 1)}
     else:
@@ -170,13 +175,13 @@ def parareal_adjoint(d: Discretisation, S: np.ndarray, Theta: float,
         if Gkl is None:
             Gkl, Gkg = {}, {}
             for n in range(1, Nt + 1):
-                Gkl[n], Gkg[n] = G_adj(d, S, Theta, vl[n], vg[n], n)
+                Gkl[n], Gkg[n] = G_adj_(d, S, Theta, vl[n], vg[n], n)
         nl = [None] * (Nt + 1)
         ng = [None] * (Nt + 1)
         nl[Nt], ng[Nt] = zl, zg
         Gnl, Gng = {}, {}
         for n in range(Nt, 0, -1):
-            gl, gg = G_adj(d, S, Theta, nl[n], ng[n], n)
+            gl, gg = G_adj_(d, S, Theta, nl[n], ng[n], n)
             Gnl[n], Gng[n] = gl, gg
             nl[n - 1] = gl + Fl[n] - Gkl[n]
             ng[n - 1] = gg + Fg[n] - Gkg[n]
