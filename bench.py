@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--no-precision-compare", action="store_true",
                     help="skip the FP32+refine vs FP64 comparison at equal objective accuracy")
     ap.add_argument("--no-plt", action="store_true",
-                    help="skip the zero-coarse-propagator (PLT, Sec. 7) cycle on the workload")
+                    help="skip the PLT (Sec. 7), cheaper-coarse-propagator and sequential-method "
+                         "cycles on the workload")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-design batch (batched FP32+refine vs plain FP64)")
     ap.add_argument("--workload", default=WORKLOAD,
@@ -240,6 +241,44 @@ def plt_compare(prob, rho, parareal_ms, parareal_theta, repeats=5) -> dict:
     return out
 
 
+def coarse_compare(prob, rho, ref_ms, ref_theta, ref_grad, nus=(10, 20), repeats=3) -> dict:
+    """A cheaper coarse propagator on the same workload and protocol: every
+    coarse step is exactly nu Jacobi-PCG iterations from its input state
+    (coarse_iters = nu) instead of a solve to cg_rtol. The cold cycle gives the
+    guesses, then warm cycles are timed (median of `repeats`). Theta and the
+    gradient are compared with the exact-G one-shot cycle of the headline."""
+    import dataclasses
+
+    import torch
+
+    from paper_2411_19030_amd.cycle import Cycle
+    stream = torch.cuda.current_stream()
+    out = {}
+    for nu in nus:
+        cyc = Cycle(dataclasses.replace(prob, coarse_iters=nu), rho.device)
+        cyc.run(rho)
+        torch.cuda.synchronize()
+        g = (cyc.uT.clone(), cyc.utheta.clone(), cyc.lam.clone())
+        ts = []
+        for _ in range(repeats):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            cyc.run(rho, *g)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[len(ts) // 2]
+        th = float(cyc.Theta)
+        out[f"nu_{nu}"] = {
+            "ms_per_cycle": ms, "speedup_over_exact_G": ref_ms / ms,
+            "Theta_rel_diff_vs_exact_G": abs(th - ref_theta) / ref_theta,
+            "grad_rel_diff_vs_exact_G": float(torch.linalg.norm(cyc.grad - ref_grad) /
+                                              torch.linalg.norm(ref_grad)),
+            "status": cyc.status()["status"]}
+        del cyc
+    return out
+
+
 def sequential_reference(prob, rho, repeats=3) -> dict:
     """The reference method of Sec. 5.2 on the GPU: one slice (N_tau = 1), where
     one iteration is the sequential time stepping exactly (every step is a
@@ -346,7 +385,9 @@ def one_shot_chain(n_cycles=30, Ntau=30) -> dict:
     eta = 0.5). Per cycle the sequential method (one slice) gives Theta and
     dTheta/dchi. One-shot Parareal and one-shot PLT (N_tau slices, one
     iteration) restart from their own previous cycle; their first cycle is
-    exact (N_tau iterations), as Alg. 3 starts with a sequential cycle.
+    exact (N_tau iterations), as Alg. 3 starts with a sequential cycle. One-shot
+    Parareal with the cheaper coarse propagator (coarse steps of 60 CG
+    iterations) runs beside them.
     Reported per cycle: the objective and sensitivity errors of both one-shot
     estimates and the cycle times (forward, backward and the filter)."""
     import dataclasses
@@ -370,6 +411,8 @@ def one_shot_chain(n_cycles=30, Ntau=30) -> dict:
     designs = design_schedule(nx, ny, 6, n_cycles, start=density_branches(nx, ny, w["seed"]))
     seq = OneShotParareal(dataclasses.replace(base, n_slices=1), dev, warm=False)
     methods = {"parareal": OneShotParareal(base, dev, warm=True),
+               "parareal_coarse60": OneShotParareal(dataclasses.replace(base, coarse_iters=60),
+                                                    dev, warm=True),
                "plt": OneShotParareal(dataclasses.replace(base, propagator=1), dev, warm=True)}
     stream = torch.cuda.current_stream()
 
@@ -674,6 +717,7 @@ def main():
     if not args.no_precision_compare:
         out["vs_fp64"] = precision_compare(prob, rho, gT, gth, gl)
     if not args.no_plt:
+        out["coarse_truncated"] = coarse_compare(prob, rho, ms, float(cyc.Theta), cyc.grad.clone())
         out["plt"] = plt_compare(prob, rho, ms, float(cyc.Theta))
         seq = sequential_reference(prob, rho)
         seq["speedup_parareal_fp64"] = seq["ms_per_cycle"] / ms

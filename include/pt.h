@@ -91,6 +91,9 @@ typedef struct pt_problem {
     int32_t bc;                /* PT_BC_*                                                         */
     const uint8_t *dirichlet_mask; /* HOST, (nx+1)(ny+1) bytes, read when bc == PT_BC_MASK        */
     int32_t propagator;        /* PT_PARAREAL (0), or PT_PLT: zero coarse propagators (Sec. 7)    */
+    int32_t coarse_iters;      /* 0: coarse steps solved to cg_rtol; k > 0: a cheaper coarse     */
+                               /* propagator, exactly k Jacobi-PCG iterations from the step's    */
+                               /* input state (PT_FP64, PT_JACOBI and PT_PARAREAL only)         */
 } pt_problem;
 
 typedef struct pt_stats {
@@ -261,8 +264,8 @@ typedef struct pt_batch_tuning {
 } pt_batch_tuning;
 
 /* Workspace bytes of a batch of n designs; 0 if any problem is invalid, the
- * precisions differ, or a design has iterations != 1, storage != PT_STORE_ALL or
- * propagator != PT_PARAREAL. */
+ * precisions differ, or a design has iterations != 1, storage != PT_STORE_ALL,
+ * propagator != PT_PARAREAL or coarse_iters != 0. */
 size_t pt_batched_workspace_bytes(int n, const pt_problem *probs);
 
 /* The built-in worker shapes for n designs (environment overrides included). */

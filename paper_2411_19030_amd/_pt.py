@@ -43,7 +43,7 @@ class PtProblem(ctypes.Structure):
         ("precision", ctypes.c_int32), ("precond", ctypes.c_int32),
         ("storage", ctypes.c_int32), ("bc", ctypes.c_int32),
         ("dirichlet_mask", ctypes.POINTER(ctypes.c_uint8)),
-        ("propagator", ctypes.c_int32),
+        ("propagator", ctypes.c_int32), ("coarse_iters", ctypes.c_int32),
     ]
 
 
@@ -169,6 +169,7 @@ class Problem:
     storage: int = PT_STORE_ALL
     bc: object = "left_centre"  # name or boolean/uint8 node mask
     propagator: int = PT_PARAREAL
+    coarse_iters: int = 0       # > 0: coarse steps are this many CG iterations
     _keep: list = field(default_factory=list, repr=False, compare=False)
 
     @property
@@ -207,6 +208,7 @@ class Problem:
             c.bc = PT_BC["mask"]
             c.dirichlet_mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         c.propagator = int(self.propagator)
+        c.coarse_iters = int(self.coarse_iters)
         return c
 
 

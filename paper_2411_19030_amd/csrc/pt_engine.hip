@@ -546,6 +546,12 @@ __device__ StepInfo step_info(const Consts &C, const Bufs &B, const LaunchInfo &
             break;
         }
     }
+    // truncated coarse solves: the coarse propagator is a fixed number of CG
+    // iterations from its input state, so its start may depend on nothing else
+    if (C.coarse_iters > 0 && !st.fine) {
+        st.x0_src = st.tp_src;
+        st.d1 = st.d0 = nullptr;
+    }
     return st;
 }
 
@@ -1384,7 +1390,17 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                 }
                 c.it_local = 0;
                 const int restart_cap = C.fp32 ? C.max_restarts : 3;
-                if (c.bnorm == 0.0) {
+                if (C.coarse_iters > 0 && !st.fine) {
+                    // truncated coarse solve: exactly coarse_iters CG iterations
+                    // (fewer only if the residual vanishes)
+                    c.relres = c.bnorm > 0.0 ? rn / c.bnorm : 0.0;
+                    if (rn == 0.0) {
+                        c.phase = PH_POST;
+                    } else {
+                        c.r0n = rn;
+                        c.phase = PH_FIRST;
+                    }
+                } else if (c.bnorm == 0.0) {
                     c.zero_x = true;
                     c.relres = 0.0;
                     c.phase = PH_POST;
@@ -1714,10 +1730,13 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                 // step (INIT) decides convergence
                 const double target =
                     C.fp32 ? fmax(C.rtol * c.bnorm, C.inner_rtol * c.r0n) : C.rtol * c.bnorm;
-                if (rn <= target || c.iter >= C.max_iter) {
-                    c.relres = rn / c.bnorm;
-                    const bool check = C.fp32 ? (c.iter < C.max_iter)
-                                              : (C.verify && rn <= C.rtol * c.bnorm && c.restarts < 3);
+                const bool trunc = C.coarse_iters > 0 && !st.fine;
+                if (trunc ? (c.iter >= C.coarse_iters || rn == 0.0)
+                          : (rn <= target || c.iter >= C.max_iter)) {
+                    c.relres = c.bnorm > 0.0 ? rn / c.bnorm : 0.0;
+                    const bool check =
+                        !trunc && (C.fp32 ? (c.iter < C.max_iter)
+                                          : (C.verify && rn <= C.rtol * c.bnorm && c.restarts < 3));
                     if (check) {
                         // recompute r = b - A x in FP64, restart CG if needed
                         c.verifying = true;
@@ -1730,7 +1749,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                         }
                     } else {
                         c.phase = PH_POST;
-                        if (rn > C.rtol * c.bnorm && rank == 0 && threadIdx.x == 0)
+                        if (!trunc && rn > C.rtol * c.bnorm && rank == 0 && threadIdx.x == 0)
                             set_status(ctl, -4);
                         if constexpr (NPT > 0) {
                             // adjoint POST reads the neighbours' x

@@ -66,6 +66,10 @@ bool valid_problem(const pt_problem *p) {
     if (p->bc < 0 || p->bc > 3) return false;
     if (p->bc == PT_BC_MASK && !p->dirichlet_mask) return false;
     if (p->propagator != PT_PARAREAL && p->propagator != PT_PLT) return false;
+    if (p->coarse_iters < 0 || p->coarse_iters > 100000) return false;
+    if (p->coarse_iters > 0 &&
+        (p->precision != PT_FP64 || p->propagator != PT_PARAREAL || p->precond != PT_JACOBI))
+        return false;
     if (p->q_t)
         for (int n = 0; n <= p->n_steps; ++n)
             if (!isfinite(p->q_t[n])) return false;
@@ -326,6 +330,7 @@ Consts make_consts(const pt_problem *p) {
     C.ckpt = p->storage == PT_CHECKPOINT ? 1 : 0;
     C.sweep_x0 = env_int("PT_SWEEP_X0", 1);
     C.plt = p->propagator == PT_PLT ? 1 : 0;
+    C.coarse_iters = p->coarse_iters;
     if (C.gmg || C.ckpt) C.extrap = 0;
     // LDS-staged chunks of the multigrid rounds (one operand window in the CG
     // precision) and of the FP64 set-up of a solve (two windows), within the
@@ -1119,7 +1124,7 @@ bool valid_batch(int n, const pt_problem *probs) {
         if (!valid_problem(&probs[k])) return false;
         if (probs[k].storage != PT_STORE_ALL) return false;
         if (probs[k].iterations != 1) return false;
-        if (probs[k].propagator != PT_PARAREAL) return false;
+        if (probs[k].propagator != PT_PARAREAL || probs[k].coarse_iters != 0) return false;
         if (probs[k].precision != probs[0].precision) return false;
     }
     return true;

@@ -96,6 +96,7 @@ struct Consts {
     int ckpt;
     int sweep_x0;  // correction sweeps start from G(u^k_n) + (u^{k+1}_n - u^k_n)
     int plt;       // zero coarse propagators (Sec. 7): fine lanes only, objective Theta^p
+    int coarse_iters;  // > 0: coarse propagators are this many CG iterations from their input
     double gmg_omega;                 // smoother damping times the Gershgorin bound
     long long gmg_off[kMaxLevels];    // node offset of level l >= 1 in the level arrays
     long long gmg_nodes;              // sum of the nodes of levels 1..L-1

@@ -21,7 +21,8 @@ def gpu_problem(cfg: dict):
     from paper_2411_19030_amd import Problem
     kw = {k: cfg[k] for k in ("nx", "ny", "n_steps", "n_slices")}
     for k in ("k0", "kmin", "pk", "c0", "cmin", "pc", "q", "t_final", "pnorm", "iterations",
-              "cg_rtol", "max_iter", "bc", "precision", "precond", "storage", "propagator"):
+              "cg_rtol", "max_iter", "bc", "precision", "precond", "storage", "propagator",
+              "coarse_iters"):
         if k in cfg:
             kw[k] = cfg[k]
     return Problem(**kw)
@@ -36,12 +37,15 @@ def run_oracle(cfg: dict, rho: np.ndarray, guess=None):
         ad = O.plt_adjoint(d, fw["S"], fw["Theta"], it, None if guess is None else guess[2])
         return dict(S=fw["S"], uT=fw["uT"], utheta=fw["utheta"], Theta=fw["Theta"],
                     lam=ad["lam"], grad=ad["grad"])
+    nu = cfg.get("coarse_iters", 0)
+    Gp = O.make_G_pri(nu) if nu > 0 else None
+    Ga = O.make_G_adj(nu) if nu > 0 else None
     if guess is None:
-        fw = O.parareal_forward(d, it)
-        ad = O.parareal_adjoint(d, fw["S"], fw["Theta"], it)
+        fw = O.parareal_forward(d, it, G=Gp)
+        ad = O.parareal_adjoint(d, fw["S"], fw["Theta"], it, G=Ga)
     else:
-        fw = O.parareal_forward(d, it, guess[0], guess[1])
-        ad = O.parareal_adjoint(d, fw["S"], fw["Theta"], it, guess[2])
+        fw = O.parareal_forward(d, it, guess[0], guess[1], G=Gp)
+        ad = O.parareal_adjoint(d, fw["S"], fw["Theta"], it, guess[2], G=Ga)
     return dict(S=fw["S"], uT=fw["uT"], utheta=fw["utheta"], Theta=fw["Theta"],
                 lam=ad["lam"], grad=ad["grad"])
 

@@ -45,7 +45,8 @@ def base(**kw):
     dict(cg_rtol=0.0), dict(cg_rtol=float("nan")), dict(max_iter=0), dict(iterations=0),
     dict(t_final=0.0), dict(kmin=0.0), dict(pk=0.5), dict(precision=7), dict(precond=9),
     dict(storage=4), dict(n_steps=0), dict(q=float("inf")), dict(propagator=2),
-    dict(propagator=-1),
+    dict(propagator=-1), dict(coarse_iters=-1), dict(coarse_iters=5, precision=1),
+    dict(coarse_iters=5, propagator=1), dict(coarse_iters=5, precond=1),
 ])
 def test_validate_rejects(lib, kw):
     p = base(**kw)
@@ -118,6 +119,7 @@ def test_struct_layout_matches_header():
     assert offs["q_t"] == 64 and offs["t_final"] == 72 and offs["n_steps"] == 80
     assert offs["cg_rtol"] == 96 and offs["max_iter"] == 104
     assert offs["dirichlet_mask"] == 128 and offs["propagator"] == 136
+    assert offs["coarse_iters"] == 140
     assert ctypes.sizeof(PtProblem) == 144
 
 
@@ -144,7 +146,8 @@ def test_batched_workspace_and_validation(lib):
     assert nb2 > nb1 > 0
     # mixed precision, several Parareal iterations, zero coarse propagators,
     # invalid members: no workspace
-    for bad in (base(precision=1), base(iterations=2), base(pnorm=3), base(propagator=1)):
+    for bad in (base(precision=1), base(iterations=2), base(pnorm=3), base(propagator=1),
+                base(coarse_iters=4)):
         arr_bad = (PtProblem * 2)(a.to_c(), bad.to_c())
         assert lib.pt_batched_workspace_bytes(2, arr_bad) == 0
     assert lib.pt_batched_workspace_bytes(0, arr) == 0
