@@ -63,7 +63,7 @@ def parse():
                     help="skip the 64-design batch (batched FP32+refine vs plain FP64)")
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=[WORKLOAD, "batch_fp32_64", "large_2048", "large_law_512",
-                             "paper_100", "one_shot_chain"],
+                             "paper_100", "one_shot_chain", "plt_fp64_256"],
                     help="the headline workload (default), or one of the other workloads "
                          "measured on its own")
     ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
@@ -174,7 +174,8 @@ def precision_compare(prob, rho, gT, gth, gl, accuracy=1e-6, repeats=3) -> dict:
     return out
 
 
-def plt_compare(prob, rho, parareal_ms, parareal_theta, repeats=5) -> dict:
+def plt_compare(prob, rho, parareal_ms, parareal_theta, repeats=5,
+                precisions=(("fp64", 0, None), ("fp32_refine", 1, 1e-7))) -> dict:
     """Zero coarse propagators (the PLT form of Sec. 7) on the same workload.
 
     Each PLT cycle carries information one slice further, so the PLT cycles
@@ -194,7 +195,8 @@ def plt_compare(prob, rho, parareal_ms, parareal_theta, repeats=5) -> dict:
     Nn, Nt = prob.n_nodes, prob.n_steps
     out = {"guess": f"converged ({prob.n_slices} PLT cycles on the design)"}
     th_ref = None
-    for name, prec, rtol in (("fp64", 0, prob.cg_rtol), ("fp32_refine", 1, 1e-7)):
+    for name, prec, rtol in precisions:
+        rtol = prob.cg_rtol if rtol is None else rtol
         cyc = Cycle(dataclasses.replace(prob, propagator=1, precision=prec, cg_rtol=rtol),
                     rho.device)
         cyc.run(rho)
@@ -628,6 +630,20 @@ def main():
         return
     if args.workload == "one_shot_chain":
         print(json.dumps(one_shot_chain()))
+        return
+    if args.workload == "plt_fp64_256":
+        # the PLT cycle of the headline workload on its own (FP64, converged
+        # guesses), e.g. for profiling the streaming engine
+        w = workload(WORKLOAD)
+        prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
+                       pnorm=w["p"], k0=w["k0"], kmin=w["kmin"], pk=w["pk"], c0=w["c0"],
+                       cmin=w["cmin"], pc=w["pc"], q=w["q"], t_final=w["t_final"], bc=w["bc"],
+                       iterations=1, cg_rtol=w["rtol"], max_iter=20000)
+        rho = torch.tensor(workload_density(WORKLOAD), dtype=torch.float64,
+                           device=torch.device("cuda:0"))
+        print(json.dumps(plt_compare(prob, rho, float("nan"), float("nan"),
+                                     precisions=(("fp64", 0, prob.cg_rtol),),
+                                     repeats=max(1, args.steps))))
         return
     w = workload(WORKLOAD)
     prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
