@@ -923,8 +923,7 @@ LanePlan fine_plan(int kind, int count, int slice0, int dir, const Consts &C,
 // (F_0, or the last slice in the adjoint); its group runs that slice itself
 // rather than waiting for a fine group. Not with a fixed fine-lane shape
 // (checkpoints), where both passes must run every fine slice alike.
-bool lead_fine(const Consts &C, const pt_problem *p, int Ntau, bool plt) {
-    (void)p;
+bool lead_fine(const Consts &C, int Ntau, bool plt) {
     if (plt || Ntau < 2 || C.ckpt || env_int("PT_FINE_WGS", 0) > 0) return false;
     return env_int("PT_LEAD_FINE", 1) != 0;
 }
@@ -1222,7 +1221,7 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
         PT_TRY(upload_descs(hd, D, stream));
         std::vector<LanePlan> plans;
         // the sweep cannot start before F_0: its group runs F_0 itself
-        const bool lead = lead_fine(C, prob, Ntau, plt);
+        const bool lead = lead_fine(C, Ntau, plt);
         plans.push_back(lead ? fine_plan(F_PRI, Ntau - 1, 1, +1, C, prob)
                              : fine_plan(F_PRI, Ntau, 0, +1, C, prob));
         if (I.gk_lanes)
@@ -1299,7 +1298,7 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
         PT_TRY(upload_descs(hd, D, stream));
         std::vector<LanePlan> plans;
         // the reversed sweep consumes slices from N_tau downwards
-        const bool lead = lead_fine(C, prob, Ntau, plt);
+        const bool lead = lead_fine(C, Ntau, plt);
         plans.push_back(lead ? fine_plan(F_ADJ, Ntau - 1, Ntau - 1, -1, C, prob)
                              : fine_plan(F_ADJ, Ntau, Ntau, -1, C, prob));
         if (I.gk_lanes)
