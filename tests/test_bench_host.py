@@ -1,0 +1,35 @@
+"""Host-side checks of bench.py (no GPU): the multi-GPU refusal, the argument
+surface, and that the stored HBM traffic figure belongs to the kernel sources
+it was measured on (otherwise the bench reports traffic as null)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def _run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args],
+                          capture_output=True, text=True, timeout=120)
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = _run("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_help_lists_the_workloads():
+    r = _run("--help")
+    assert r.returncode == 0
+    for w in ("plain_fp64_256", "batch_fp32_64", "large_2048", "paper_100", "one_shot_chain",
+              "plt_fp64_256"):
+        assert w in r.stdout
+
+
+def test_traffic_figure_matches_the_sources():
+    import bench
+    assert bench.TRAFFIC["bytes_per_launch"] > 0
+    assert bench.sources_sha1() == bench.TRAFFIC["sources_sha1"], \
+        "kernel sources changed since the rocprofv3 counters were taken"
