@@ -34,8 +34,8 @@ WORKLOAD = "plain_fp64_256"
 # WRITE_SIZE runs (each scaled by what the counter reads for a 1 GiB device
 # copy: x2.0 and x1.0), averaged over the forward and adjoint launches of a warm
 # cycle; valid only for the kernel sources with this hash (see profiles/).
-TRAFFIC = {"sources_sha1": "8413d6b97a7929ce472882a746a1ce754ecaeae5",
-           "bytes_per_launch": 0.5 * (29.57e9 + 29.36e9)}
+TRAFFIC = {"sources_sha1": "90df25c9bc3a3f51cf63ed573219310c0fbb2d9e",
+           "bytes_per_launch": 0.5 * (29.37e9 + 29.19e9)}
 
 
 def sources_sha1() -> str:

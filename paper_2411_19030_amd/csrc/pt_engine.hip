@@ -793,6 +793,10 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
         Real *LR = reinterpret_cast<Real *>(LB);  // own residuals of the CG rounds
         Real *LD = LR;  // resident: D^{-1} of the tile (the INIT window is free after FIRST)
         int ea_res = 0;
+        // resident: bit k set if this thread's k-th tile node is a Dirichlet node
+        // (read once per lane; a per-round byte load per node would serialise a
+        // cache round trip per node behind the unrolled stencil)
+        unsigned dmask = 0;
         if constexpr (NPT > 0) {
             const int a = min(rank * TS, C.Nn);
             const int b = min(a + TS, C.Nn);
@@ -801,6 +805,11 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
             if (a < b) {
                 elem_window(C, a, b, ea_res, elen);
                 stage_elems(B, ea_res, elen, LK, LC);
+            }
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int id = a + (int)threadIdx.x + k * kThreads;
+                if (id < b && B.mask[id]) dmask |= 1u << k;
             }
             lds_sync();
         }
@@ -1461,7 +1470,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                         if (id < b) {
                             const int li2 = id - lo;
                             Real w = 0;
-                            if (!B.mask[id]) {
+                            if (!((dmask >> k) & 1u)) {
                                 const int j = id / C.W, i = id - j * C.W;
                                 const CoefT<Real> aa = node_coef_t<Real>(C, LK, LC, ea_res, i, j, ms, 1.0);
                                 w = apply_t<Real>(aa, LZ, li2, C.W);
@@ -1622,7 +1631,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                         if (id < b) {
                             const int li2 = id - lo;
                             Real w = 0;
-                            if (!B.mask[id]) {
+                            if (!((dmask >> k) & 1u)) {
                                 const int j = id / C.W, i = id - j * C.W;
                                 const CoefT<Real> aa = node_coef_t<Real>(C, LK, LC, ea_res, i, j, ms, 1.0);
                                 w = apply_t<Real>(aa, LZ, li2, C.W);
