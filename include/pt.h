@@ -63,9 +63,11 @@ enum {
 enum { PT_FP64 = 0, PT_FP32_REFINE = 1 };
 enum { PT_JACOBI = 0, PT_GMG = 1 };
 enum { PT_STORE_ALL = 0, PT_CHECKPOINT = 1 };
-/* Coarse propagators: the method's G (Alg. 1-2 with dtau), or G = 0, the
- * Parallel Local-in-Time form of Sec. 7 (see pt_parareal_forward). */
-enum { PT_PARAREAL = 0, PT_PLT = 1 };
+/* Coarse propagators: the method's G (Alg. 1-2 with dtau); G = 0, the
+ * Parallel Local-in-Time form of Sec. 7; or G on a coarser spatial mesh, the
+ * cheaper coarse propagator that Sec. 7.3 and Sec. 8 propose (see
+ * pt_parareal_forward). */
+enum { PT_PARAREAL = 0, PT_PLT = 1, PT_COARSE_MESH = 2 };
 
 typedef struct pt_problem {
     int32_t nx, ny;            /* elements along x and y, >= 1                                   */
@@ -90,7 +92,9 @@ typedef struct pt_problem {
                                /* pass recomputes the other fine states of each slice             */
     int32_t bc;                /* PT_BC_*                                                         */
     const uint8_t *dirichlet_mask; /* HOST, (nx+1)(ny+1) bytes, read when bc == PT_BC_MASK        */
-    int32_t propagator;        /* PT_PARAREAL (0), or PT_PLT: zero coarse propagators (Sec. 7)    */
+    int32_t propagator;        /* PT_PARAREAL (0); PT_PLT: zero coarse propagators (Sec. 7);      */
+                               /* PT_COARSE_MESH: coarse propagators on an nx/2 x ny/2 mesh      */
+                               /* (nx, ny even; PT_FP64, PT_JACOBI, PT_STORE_ALL only)          */
     int32_t coarse_iters;      /* 0: coarse steps solved to cg_rtol; k > 0: a cheaper coarse     */
                                /* propagator, exactly k Jacobi-PCG iterations from the step's    */
                                /* input state (PT_FP64, PT_JACOBI and PT_PARAREAL only)         */
@@ -141,6 +145,16 @@ size_t pt_state_bytes(const pt_problem *prob);
  * summed over those trajectories, and Theta_out = Theta~^{1/p} (Eq. 7.6);
  * utheta_out[n] = (the part of Theta~ before tau_n)^{1/p}. guess_theta is
  * ignored and may be NULL.
+ *
+ * With propagator == PT_COARSE_MESH the coarse propagators act on a mesh of
+ * nx/2 x ny/2 elements whose node (I, J) is fine node (2I, 2J): k and c of a
+ * coarse element are the means of its four fine elements' SIMP values, a
+ * coarse node is fixed where its fine node is, R is injection and P bilinear
+ * interpolation set to 0 at fine Dirichlet nodes. G_pri(T, theta, n) =
+ * (P x, theta'), x the coarse backward-Euler step of size dtau from R T with
+ * the load at tau_{n+1}, theta' = (theta^p + ||P x||_p^p/(N_tau N_e))^{1/p}.
+ * Everything else is as with PT_PARAREAL; the coarse steps are solved to
+ * cg_rtol by Jacobi PCG on one workgroup each.
  */
 int pt_parareal_forward(const pt_problem *prob, const double *rho, const double *guess_T,
                         const double *guess_theta, double *S, double *uT_out,
@@ -164,6 +178,11 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
  * so lambda_out holds lambda~ = p Theta^{p-1} lambda. The first fine step of
  * slice n takes T_{M(n-1)} from S (the end of slice n-1's trajectory). Theta
  * (the forward's Theta_out) is kept for the back-transform of pt_sensitivities.
+ *
+ * With propagator == PT_COARSE_MESH: G_adj(lambda, n) = P x, x the coarse
+ * adjoint step from R lambda whose source is P^T of the fine source of Eq. 4.6
+ * at T_m (m = M(n-1)+1); the sensitivity increment of Eq. 4.10 uses P x on
+ * the fine elements.
  */
 int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double *S,
                         const double *Theta, const double *guess_lambda, double *lambda_out,
@@ -265,7 +284,7 @@ typedef struct pt_batch_tuning {
 
 /* Workspace bytes of a batch of n designs; 0 if any problem is invalid, the
  * precisions differ, or a design has iterations != 1, storage != PT_STORE_ALL,
- * propagator != PT_PARAREAL or coarse_iters != 0. */
+ * propagator != PT_PARAREAL (PT_PLT, PT_COARSE_MESH) or coarse_iters != 0. */
 size_t pt_batched_workspace_bytes(int n, const pt_problem *probs);
 
 /* The built-in worker shapes for n designs (environment overrides included). */

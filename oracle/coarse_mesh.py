@@ -49,21 +49,22 @@ def restrict(T: np.ndarray, nx: int, ny: int, f: int) -> np.ndarray:
     return np.asarray(T).reshape(ny + 1, nx + 1)[::f, ::f].reshape(-1).copy()
 
 
+def _weights(n: int, f: int):
+    """For fine index k = 0..n: the coarse indices K, K1 of its coarse interval
+    and the bilinear weight w of K1 (1 - w of K)."""
+    k = np.arange(n + 1)
+    K, a = np.divmod(k, f)
+    return K, np.minimum(K + 1, n // f), a / f
+
+
 def prolong_unmasked(Tc: np.ndarray, nx: int, ny: int, f: int) -> np.ndarray:
     """Bilinear interpolant of the coarse nodal field at every fine node."""
-    nxc, nyc = nx // f, ny // f
-    G = np.asarray(Tc).reshape(nyc + 1, nxc + 1)
-    out = np.zeros((ny + 1, nx + 1))
-    for j in range(ny + 1):
-        J, b = divmod(j, f)
-        J1 = min(J + 1, nyc)
-        wy = b / f
-        for i in range(nx + 1):
-            I, a = divmod(i, f)
-            I1 = min(I + 1, nxc)
-            wx = a / f
-            out[j, i] = ((1 - wx) * (1 - wy) * G[J, I] + wx * (1 - wy) * G[J, I1]
-                         + (1 - wx) * wy * G[J1, I] + wx * wy * G[J1, I1])
+    G = np.asarray(Tc).reshape(ny // f + 1, nx // f + 1)
+    I, I1, wx = _weights(nx, f)
+    J, J1, wy = _weights(ny, f)
+    wx, wy = wx[None, :], wy[:, None]
+    out = ((1 - wx) * (1 - wy) * G[np.ix_(J, I)] + wx * (1 - wy) * G[np.ix_(J, I1)]
+           + (1 - wx) * wy * G[np.ix_(J1, I)] + wx * wy * G[np.ix_(J1, I1)])
     return out.reshape(-1)
 
 
@@ -115,22 +116,15 @@ class CoarseMesh:
         """The transpose of P: each fine value goes to the coarse nodes of its
         element with the bilinear weights (fine Dirichlet nodes contribute 0)."""
         Pd = self.d.prob
-        nxc, f = self.nx, self.f
         w = np.where(self.d.dmask, 0.0, np.asarray(v, dtype=np.float64)).reshape(Pd.ny + 1,
                                                                               Pd.nx + 1)
-        out = np.zeros((self.ny + 1, nxc + 1))
-        for j in range(Pd.ny + 1):
-            J, b = divmod(j, f)
-            J1 = min(J + 1, self.ny)
-            wy = b / f
-            for i in range(Pd.nx + 1):
-                I, a = divmod(i, f)
-                I1 = min(I + 1, nxc)
-                wx = a / f
-                out[J, I] += (1 - wx) * (1 - wy) * w[j, i]
-                out[J, I1] += wx * (1 - wy) * w[j, i]
-                out[J1, I] += (1 - wx) * wy * w[j, i]
-                out[J1, I1] += wx * wy * w[j, i]
+        I, I1, wx = _weights(Pd.nx, self.f)
+        J, J1, wy = _weights(Pd.ny, self.f)
+        wx, wy = wx[None, :], wy[:, None]
+        out = np.zeros((self.ny + 1, self.nx + 1))
+        for rows, cols, wgt in ((J, I, (1 - wx) * (1 - wy)), (J, I1, wx * (1 - wy)),
+                                (J1, I, (1 - wx) * wy), (J1, I1, wx * wy)):
+            np.add.at(out, (rows[:, None], cols[None, :]), wgt * w)
         return out.reshape(-1)
 
     def solve(self, rhs: np.ndarray) -> np.ndarray:

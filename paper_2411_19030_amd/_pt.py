@@ -21,7 +21,7 @@ PT_BC = {"left_centre": 0, "bottom_centre": 1, "none": 2, "mask": 3}
 PT_FP64, PT_FP32_REFINE = 0, 1
 PT_JACOBI, PT_GMG = 0, 1
 PT_STORE_ALL, PT_CHECKPOINT = 0, 1
-PT_PARAREAL, PT_PLT = 0, 1
+PT_PARAREAL, PT_PLT, PT_COARSE_MESH = 0, 1, 2
 
 EXPORTS = ["pt_workspace_bytes", "pt_state_bytes", "pt_validate", "pt_parareal_forward", "pt_parareal_adjoint",
            "pt_sensitivities", "pt_query_status", "pt_query_trace", "pt_strerror",
@@ -168,7 +168,7 @@ class Problem:
     precond: int = PT_JACOBI
     storage: int = PT_STORE_ALL
     bc: object = "left_centre"  # name or boolean/uint8 node mask
-    propagator: int = PT_PARAREAL
+    propagator: int = PT_PARAREAL  # PT_PARAREAL, PT_PLT or PT_COARSE_MESH
     coarse_iters: int = 0       # > 0: coarse steps are this many CG iterations
     _keep: list = field(default_factory=list, repr=False, compare=False)
 

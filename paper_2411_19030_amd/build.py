@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpt.so")
 ARCH = os.environ.get("PT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = [os.path.join(CSRC, "pt_host.hip"), os.path.join(CSRC, "pt_filter.hip")]
+SOURCES = [os.path.join(CSRC, "pt_host.hip"), os.path.join(CSRC, "pt_filter.hip"),
+           os.path.join(CSRC, "pt_cmesh.hip")]
 DEPS = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + [os.path.join(ROOT, "include", "pt.h")]
 
 

@@ -1,0 +1,581 @@
+// Coarse propagators on a coarser spatial mesh (Sec. 7.3 and Sec. 8 name this
+// as the way to cheapen the sequential coarse propagators; the construction
+// below is this library's reading of it).
+//
+// The coarse mesh halves the element grid: coarse node (I, J) is fine node
+// (2I, 2J). A coarse element's k and c are the means of the SIMP values of its
+// four fine elements; a coarse node is fixed (T = 0) iff its fine node is.
+// R is injection, P the bilinear interpolant set to 0 at fine Dirichlet nodes.
+//   G_pri^c(T, theta, n): (C_c/dtau + K_c) x = C_c/dtau R T + q(tau_{n+1}) f_c,
+//     output P x, theta' = (theta^p + ||P x||_p^p / (N_tau N_e))^{1/p} (Alg. 1);
+//   G_adj^c(lambda, n): (C_c/dtau + K_c) x = C_c/dtau R lambda + P^T s(T_m),
+//     s the fine source of Eq. 4.6 at m = M(n-1)+1, output P x (Alg. 2).
+// A Parareal pass with these propagators runs the fine propagators of every
+// slice in one engine launch, then on the coarse mesh: the batched steps
+// G(R u^k_n) (one workgroup each), the sequential correction sweep (one
+// workgroup), and the corrected fine states F_n + P(G(u^{k+1}_n) - G(u^k_n))
+// (Eq. 4.2 / Eq. 4.9 with both coarse outputs prolonged by the same linear P).
+// The sensitivity part of the reversed correction is linear in the coarse
+// output difference; it is summed per fine element after the sweep (Eq. 4.10).
+//
+// Each coarse solve is Jacobi-preconditioned CG (Hestenes-Stiefel form) run by
+// one workgroup of 1024 threads over vectors in global memory, with the true
+// residual checked at the end; reductions are in a fixed order, so results are
+// bitwise reproducible. One workgroup suits the coarse meshes of moderate
+// grids (the 257^2-node mesh of a 512^2 design is about 1 MB per vector); the
+// sweep is latency-bound and a workgroup barrier costs far less than a
+// cross-workgroup one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "pt.h"
+#include "pt_internal.h"
+
+namespace pt {
+
+namespace {
+
+constexpr int kCT = kCoarseMeshThreads;
+constexpr int kCW = kCT / 64;
+
+__device__ __forceinline__ double cm_ipow(double x, int n) {
+    double r = 1.0, b = x;
+    while (n) {
+        if (n & 1) r *= b;
+        b *= b;
+        n >>= 1;
+    }
+    return r;
+}
+
+// Q1 rectangle element matrices, local nodes (0,0), (1,0), (1,1), (0,1):
+// K = (1/6)(hy/hx Kx + hx/hy Ky), C = hx hy/36 Cm with the integer patterns
+// below (derived from the tensor-product shape functions).
+__device__ __forceinline__ int ox(int a) { return (a == 1 || a == 2) ? 1 : 0; }
+__device__ __forceinline__ int oy(int a) { return a >= 2 ? 1 : 0; }
+__device__ __forceinline__ double kx_pat(int a, int b) {
+    return (ox(a) == ox(b) ? 1.0 : -1.0) * (oy(a) == oy(b) ? 2.0 : 1.0);
+}
+__device__ __forceinline__ double ky_pat(int a, int b) {
+    return (oy(a) == oy(b) ? 1.0 : -1.0) * (ox(a) == ox(b) ? 2.0 : 1.0);
+}
+__device__ __forceinline__ double cm_pat(int a, int b) {
+    return (ox(a) == ox(b) ? 2.0 : 1.0) * (oy(a) == oy(b) ? 2.0 : 1.0);
+}
+
+__device__ __forceinline__ int fine_of(const Consts &C, const CoarseMesh &M, int I) {
+    const int J = I / M.Wc, i = I - J * M.Wc;
+    return 2 * J * C.W + 2 * i;
+}
+
+// Coarse element coefficients: means of the fine SIMP values (Eq. 2.5-2.6).
+__global__ void k_cm_coef(const EngineDesc *__restrict__ D, CoarseMesh M) {
+    const Consts &C = D->C;
+    const Bufs &B = D->B;
+    for (int E = blockIdx.x * blockDim.x + threadIdx.x; E < M.Nec; E += gridDim.x * blockDim.x) {
+        const int EJ = E / M.nxc, EI = E - EJ * M.nxc;
+        double ks = 0.0, cs = 0.0;
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+                const double r = B.rho[(2 * EJ + b) * C.nx + 2 * EI + a];
+                const double rr = r > 0.0 ? r : 0.0;
+                ks += C.kmin + (C.k0 - C.kmin) * pow(rr, C.pk);
+                cs += C.cmin + (C.c0 - C.cmin) * pow(rr, C.pc);
+            }
+        M.kE[E] = 0.25 * ks;
+        M.cE[E] = 0.25 * cs;
+    }
+}
+
+// 9-point rows of A = C_c/dtau + K_c (Dirichlet rows and columns removed),
+// of C_c/dtau (Dirichlet rows removed), 1/diag(A), and the unit load
+// f_c = int N_I (0 on Dirichlet nodes). Entry k = (dj+1)*3 + (di+1).
+__global__ void k_cm_stencil(const EngineDesc *__restrict__ D, CoarseMesh M) {
+    const Consts &C = D->C;
+    const Bufs &B = D->B;
+    const double Hx = 2.0 * C.hx, Hy = 2.0 * C.hy;
+    for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < M.Nc; I += gridDim.x * blockDim.x) {
+        const int J = I / M.Wc, i = I - J * M.Wc;
+        const bool dir = B.mask[fine_of(C, M, I)] != 0;
+        double a9[9], c9[9];
+        for (int k = 0; k < 9; ++k) a9[k] = c9[k] = 0.0;
+        double f = 0.0;
+        // the (up to) four coarse elements around the node, and the node's
+        // local index a in each
+        for (int e = 0; e < 4; ++e) {
+            const int EI = i - ox(e), EJ = J - oy(e);
+            if (EI < 0 || EJ < 0 || EI >= M.nxc || EJ >= M.nyc) continue;
+            const int a = e;
+            const double kv = M.kE[EJ * M.nxc + EI], cv = M.cE[EJ * M.nxc + EI];
+            f += 0.25 * Hx * Hy;
+            for (int b = 0; b < 4; ++b) {
+                const int di = ox(b) - ox(a), dj = oy(b) - oy(a);
+                const int k = (dj + 1) * 3 + (di + 1);
+                const double kab = kv * (Hy / Hx * kx_pat(a, b) + Hx / Hy * ky_pat(a, b)) / 6.0;
+                const double cab = cv * Hx * Hy / 36.0 * cm_pat(a, b) * C.inv_dtau;
+                c9[k] += cab;
+                const int nb = (J + dj) * M.Wc + (i + di);
+                const bool nb_dir = B.mask[fine_of(C, M, nb)] != 0;
+                if (!nb_dir) a9[k] += kab + cab;
+            }
+        }
+        for (int k = 0; k < 9; ++k) {
+            M.A9[(size_t)k * M.Nc + I] = dir ? 0.0 : a9[k];
+            M.C9[(size_t)k * M.Nc + I] = dir ? 0.0 : c9[k];
+        }
+        M.dinv[I] = dir ? 0.0 : 1.0 / a9[4];
+        M.fc[I] = dir ? 0.0 : f;
+    }
+}
+
+// 9-point row I of a stencil array applied to a coarse vector.
+__device__ __forceinline__ double cm_row(const CoarseMesh &M, const double *S9, const double *x,
+                                         int I) {
+    const int J = I / M.Wc, i = I - J * M.Wc;
+    double s = 0.0;
+    for (int dj = -1; dj <= 1; ++dj) {
+        const int jj = J + dj;
+        if (jj < 0 || jj > M.nyc) continue;
+        for (int di = -1; di <= 1; ++di) {
+            const int ii = i + di;
+            if (ii < 0 || ii > M.nxc) continue;
+            s += S9[(size_t)((dj + 1) * 3 + di + 1) * M.Nc + I] * x[jj * M.Wc + ii];
+        }
+    }
+    return s;
+}
+
+// P x at fine node id (0 on fine Dirichlet nodes).
+__device__ __forceinline__ double cm_prolong(const Consts &C, const CoarseMesh &M,
+                                             const unsigned char *mask, const double *x, int id) {
+    if (mask[id]) return 0.0;
+    const int j = id / C.W, i = id - j * C.W;
+    const int I = i >> 1, J = j >> 1;
+    const double *r0 = x + (size_t)J * M.Wc + I;
+    if (!(i & 1) && !(j & 1)) return r0[0];
+    if (!(j & 1)) return 0.5 * r0[0] + 0.5 * r0[1];
+    if (!(i & 1)) return 0.5 * r0[0] + 0.5 * r0[M.Wc];
+    return 0.25 * r0[0] + 0.25 * r0[1] + 0.25 * r0[M.Wc] + 0.25 * r0[M.Wc + 1];
+}
+
+// P x - P y at fine node id.
+__device__ __forceinline__ double cm_prolong_diff(const Consts &C, const CoarseMesh &M,
+                                                  const unsigned char *mask, const double *x,
+                                                  const double *y, int id) {
+    return cm_prolong(C, M, mask, x, id) - cm_prolong(C, M, mask, y, id);
+}
+
+// (P^T s)_I for the fine adjoint source s_j = scale T_j^{p-1} (Eq. 4.6), with
+// the bilinear weights 1, 1/2, 1/4 of the fine nodes around coarse node I.
+__device__ __forceinline__ double cm_source(const Consts &C, const CoarseMesh &M,
+                                            const unsigned char *mask, const double *Tm,
+                                            double scale, int I) {
+    const int J = I / M.Wc, i = I - J * M.Wc;
+    double s = 0.0;
+    for (int dj = -1; dj <= 1; ++dj) {
+        const int fj = 2 * J + dj;
+        if (fj < 0 || fj > C.ny) continue;
+        for (int di = -1; di <= 1; ++di) {
+            const int fi = 2 * i + di;
+            if (fi < 0 || fi > C.nx) continue;
+            const int id = fj * C.W + fi;
+            if (mask[id]) continue;
+            const double w = (di == 0 ? 1.0 : 0.5) * (dj == 0 ? 1.0 : 0.5);
+            s += w * (scale * cm_ipow(Tm[id], C.p - 1));
+        }
+    }
+    return s;
+}
+
+// Sum of Q values over the workgroup in a fixed order (wave butterflies, then
+// the wave totals in wave order); every thread returns the same totals.
+// `red` holds 2 * Q * kCW doubles used alternately.
+template <int Q>
+__device__ void cm_reduce(double (&v)[Q], double *red, int &par) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    double *buf = red + par * Q * kCW;
+    if (l == 0)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) buf[q * kCW + w] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        double s = 0.0;
+        for (int k = 0; k < kCW; ++k) s += buf[q * kCW + k];
+        v[q] = s;
+    }
+    par ^= 1;
+}
+
+struct CmVecs {
+    double *r, *z, *p, *q, *b, *u;
+};
+
+__device__ __forceinline__ CmVecs cm_vecs(const CoarseMesh &M, int slot) {
+    double *base = M.vec + (size_t)slot * kCoarseMeshVecs * M.Nc;
+    CmVecs V;
+    V.r = base;
+    V.z = base + M.Nc;
+    V.p = base + 2 * (size_t)M.Nc;
+    V.q = base + 3 * (size_t)M.Nc;
+    V.b = base + 4 * (size_t)M.Nc;
+    V.u = base + 5 * (size_t)M.Nc;
+    return V;
+}
+
+// Solves (C_c/dtau + K_c) x = b on the coarse free nodes by Jacobi PCG from
+// x0, to ||b - A x|| <= rtol ||b|| checked on the true residual (at most three
+// restarts from it), x = 0 on Dirichlet nodes. rhs(I) and x0(I) are read once
+// per node before any write to x. Records the solve in the status block.
+template <typename Rhs, typename X0>
+__device__ void cm_pcg(const Consts &C, const CoarseMesh &M, Control *ctl, const CmVecs &V,
+                       double *x, Rhs rhs, X0 x0, double *red, int &par) {
+    const int Nc = M.Nc;
+    double bb[1] = {0.0};
+    for (int I = threadIdx.x; I < Nc; I += kCT) {
+        const bool d = M.dinv[I] == 0.0;
+        const double b = d ? 0.0 : rhs(I);
+        const double xv = d ? 0.0 : x0(I);
+        V.b[I] = b;
+        bb[0] += b * b;
+        V.q[I] = xv;  // staged: x may alias the inputs rhs/x0 read
+    }
+    __syncthreads();
+    for (int I = threadIdx.x; I < Nc; I += kCT) x[I] = V.q[I];
+    cm_reduce<1>(bb, red, par);  // its barrier also completes x
+    const double bnorm = sqrt(bb[0]);
+    int it = 0;
+    double rn = 0.0;
+    if (bnorm == 0.0) {
+        for (int I = threadIdx.x; I < Nc; I += kCT) x[I] = 0.0;
+        __syncthreads();
+    } else {
+        const double tol = C.rtol * bnorm;
+        for (int pass = 0;; ++pass) {
+            // true residual r = b - A x, z = D^{-1} r, p = z
+            double v[2] = {0.0, 0.0};
+            for (int I = threadIdx.x; I < Nc; I += kCT) {
+                const double r = V.b[I] - cm_row(M, M.A9, x, I);
+                const double z = M.dinv[I] * r;
+                V.r[I] = r;
+                V.p[I] = z;
+                v[0] += r * z;
+                v[1] += r * r;
+            }
+            cm_reduce<2>(v, red, par);
+            double rz = v[0];
+            rn = sqrt(v[1]);
+            if (rn <= tol || it >= C.max_iter || pass == 3) break;
+            for (;;) {
+                double w[1] = {0.0};
+                for (int I = threadIdx.x; I < Nc; I += kCT) {
+                    const double q = cm_row(M, M.A9, V.p, I);
+                    V.q[I] = q;
+                    w[0] += V.p[I] * q;
+                }
+                cm_reduce<1>(w, red, par);
+                const double alpha = rz / w[0];
+                double v2[2] = {0.0, 0.0};
+                for (int I = threadIdx.x; I < Nc; I += kCT) {
+                    x[I] += alpha * V.p[I];
+                    const double r = V.r[I] - alpha * V.q[I];
+                    const double z = M.dinv[I] * r;
+                    V.r[I] = r;
+                    V.z[I] = z;
+                    v2[0] += r * z;
+                    v2[1] += r * r;
+                }
+                cm_reduce<2>(v2, red, par);
+                const double beta = v2[0] / rz;
+                rz = v2[0];
+                ++it;
+                if (sqrt(v2[1]) <= tol || it >= C.max_iter) break;
+                for (int I = threadIdx.x; I < Nc; I += kCT) V.p[I] = V.z[I] + beta * V.p[I];
+                __syncthreads();
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        const double relres = bnorm > 0.0 ? rn / bnorm : 0.0;
+        const bool conv = bnorm == 0.0 || rn <= C.rtol * bnorm;
+        atomicAdd(&ctl->iters_coarse, (unsigned long long)it);
+        atomicAdd(&ctl->solves_coarse, 1ull);
+        atomicMax(&ctl->max_iters, it);
+        atomicMax(&ctl->max_relres_bits, (unsigned long long)__double_as_longlong(relres));
+        if (!conv) atomicCAS(&ctl->status, 0, PT_ENOCONV);
+        if (!isfinite(relres)) atomicExch(&ctl->status, PT_EDOMAIN);
+    }
+    __syncthreads();
+}
+
+// theta' = (theta^p + ||P x||_p^p / (N_tau N_e))^{1/p} (Alg. 1 with dtau, N_tau)
+__device__ double cm_theta(const Consts &C, const CoarseMesh &M, const Bufs &B, const double *x,
+                           double theta, double *red, int &par) {
+    double s[1] = {0.0};
+    for (int id = threadIdx.x; id < C.Nn; id += kCT)
+        s[0] += cm_ipow(cm_prolong(C, M, B.mask, x, id), C.p);
+    cm_reduce<1>(s, red, par);
+    return pow(cm_ipow(theta, C.p) + s[0] * C.inv_NtauNe, C.inv_p);
+}
+
+__device__ __forceinline__ double *crow(double *base, const CoarseMesh &M, int n) {
+    return base + (size_t)n * M.Nc;
+}
+
+// Batched coarse steps G(R u^k_n), n = blockIdx.x + 1 (1 .. N_tau - 1):
+// primal from (in_T[n], in_th[n]) into Gk[n], Gk_th[n]; adjoint from in_L[n]
+// into Gk[n]. One workgroup per step, vector slot n.
+__global__ void __launch_bounds__(kCT) k_cm_batched(const EngineDesc *__restrict__ D,
+                                                    CoarseMesh M, int adjoint) {
+    __shared__ double red[2 * 2 * kCW];
+    int par = 0;
+    const Consts &C = D->C;
+    const Bufs &B = D->B;
+    const int n = blockIdx.x + 1;
+    const CmVecs V = cm_vecs(M, n);
+    double *x = crow(M.Gk, M, n);
+    if (!adjoint) {
+        const double *u = B.in_T + (size_t)n * C.Nn;
+        const double qn = B.qt[C.M * (n + 1)];
+        auto ru = [&](int I) { return u[fine_of(C, M, I)]; };
+        // R u in the slot's u vector, so the stencil can read it by coarse index
+        for (int I = threadIdx.x; I < M.Nc; I += kCT) V.u[I] = ru(I);
+        __syncthreads();
+        cm_pcg(
+            C, M, B.ctl, V, x, [&](int I) { return cm_row(M, M.C9, V.u, I) + qn * M.fc[I]; },
+            [&](int I) { return V.u[I]; }, red, par);
+        const double th = cm_theta(C, M, B, x, B.in_th[n], red, par);
+        if (threadIdx.x == 0) B.Gk_th[n] = th;
+    } else {
+        const double *l = B.in_L + (size_t)n * C.Nn;
+        const int m = C.M * (n - 1) + 1;
+        const double *Tm = B.S + (size_t)(m - 1) * C.Nn;
+        const double scale = pow(*B.Theta, 1.0 - C.p) / (double)C.Ne;
+        for (int I = threadIdx.x; I < M.Nc; I += kCT) V.u[I] = l[fine_of(C, M, I)];
+        __syncthreads();
+        cm_pcg(
+            C, M, B.ctl, V, x,
+            [&](int I) { return cm_row(M, M.C9, V.u, I) + cm_source(C, M, B.mask, Tm, scale, I); },
+            [&](int I) { return V.u[I]; }, red, par);
+    }
+}
+
+// The sequential coarse chain on one workgroup (vector slot 0).
+// cold = 1: the cold sweep u^0_{n+1} = G(u^0_n) from u_0 = 0 (primal) or
+// v^0_{n-1} = G(v^0_n) from v_{N_tau} = 0 (adjoint), written to Gk.
+// cold = 0: the correction sweep of Eq. 4.2 / Eq. 4.9 on the coarse mesh,
+//   hat u_{n+1} = G(hat u_n) + R F_n - G(R u^k_n), hat u_1 = R F_0,
+// with G(hat u_n) written to Gn (and the theta chain to Gn_th, out_th); the
+// primal reads F_n from S row M(n+1) and theta(F_n) from F_th, the adjoint
+// F_n from FL. Each solve starts from G(u^k_n) + (hat u_n - R u^k_n).
+__global__ void __launch_bounds__(kCT) k_cm_sweep(const EngineDesc *__restrict__ D,
+                                                  CoarseMesh M, int adjoint, int cold) {
+    __shared__ double red[2 * 2 * kCW];
+    int par = 0;
+    const Consts &C = D->C;
+    const Bufs &B = D->B;
+    const CmVecs V = cm_vecs(M, 0);
+    const int Nt = C.Ntau;
+    double *u = V.u;
+    if (!adjoint) {
+        double th;
+        int n0;
+        if (cold) {
+            for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = 0.0;
+            th = 0.0;
+            n0 = 0;
+        } else {
+            const double *F0 = B.S + (size_t)(C.M - 1) * C.Nn;
+            for (int I = threadIdx.x; I < M.Nc; I += kCT)
+                u[I] = M.dinv[I] == 0.0 ? 0.0 : F0[fine_of(C, M, I)];
+            th = B.F_th[0];
+            if (threadIdx.x == 0) B.out_th[1] = th;
+            n0 = 1;
+        }
+        __syncthreads();
+        for (int n = n0; n < Nt; ++n) {
+            const double qn = B.qt[C.M * (n + 1)];
+            double *x = crow(cold ? M.Gk : M.Gn, M, n);
+            const double *gk = crow(M.Gk, M, n);
+            const double *uk = B.in_T ? B.in_T + (size_t)n * C.Nn : nullptr;
+            cm_pcg(
+                C, M, B.ctl, V, x, [&](int I) { return cm_row(M, M.C9, u, I) + qn * M.fc[I]; },
+                [&](int I) {
+                    if (cold) return u[I];
+                    return gk[I] + (u[I] - (uk ? uk[fine_of(C, M, I)] : 0.0));
+                },
+                red, par);
+            const double thG = cm_theta(C, M, B, x, th, red, par);
+            if (cold) {
+                if (threadIdx.x == 0) B.Gk_th[n] = thG;
+                th = thG;
+                for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = x[I];
+            } else {
+                th = thG + B.F_th[n] - B.Gk_th[n];
+                if (threadIdx.x == 0) {
+                    B.Gn_th[n] = thG;
+                    B.out_th[n + 1] = th;
+                }
+                const double *Fn = B.S + (size_t)(C.M * (n + 1) - 1) * C.Nn;
+                for (int I = threadIdx.x; I < M.Nc; I += kCT)
+                    u[I] = M.dinv[I] == 0.0 ? 0.0 : x[I] + Fn[fine_of(C, M, I)] - gk[I];
+            }
+            __syncthreads();
+        }
+    } else {
+        const double scale = pow(*B.Theta, 1.0 - C.p) / (double)C.Ne;
+        int n0;
+        if (cold) {
+            for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = 0.0;
+            n0 = Nt;
+        } else {
+            const double *FN = B.FL + (size_t)Nt * C.Nn;
+            for (int I = threadIdx.x; I < M.Nc; I += kCT)
+                u[I] = M.dinv[I] == 0.0 ? 0.0 : FN[fine_of(C, M, I)];
+            n0 = Nt - 1;
+        }
+        __syncthreads();
+        for (int n = n0; n >= 1; --n) {
+            const int m = C.M * (n - 1) + 1;
+            const double *Tm = B.S + (size_t)(m - 1) * C.Nn;
+            double *x = crow(cold ? M.Gk : M.Gn, M, n);
+            const double *gk = crow(M.Gk, M, n);
+            const double *lk = B.in_L ? B.in_L + (size_t)n * C.Nn : nullptr;
+            cm_pcg(
+                C, M, B.ctl, V, x,
+                [&](int I) {
+                    return cm_row(M, M.C9, u, I) + cm_source(C, M, B.mask, Tm, scale, I);
+                },
+                [&](int I) {
+                    if (cold) return u[I];
+                    return gk[I] + (u[I] - (lk ? lk[fine_of(C, M, I)] : 0.0));
+                },
+                red, par);
+            if (cold) {
+                for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = x[I];
+            } else {
+                const double *Fn = B.FL + (size_t)n * C.Nn;
+                for (int I = threadIdx.x; I < M.Nc; I += kCT)
+                    u[I] = M.dinv[I] == 0.0 ? 0.0 : x[I] + Fn[fine_of(C, M, I)] - gk[I];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Fine guesses from the cold sweep: primal T[n] = P Gk[n-1], th[n] = Gk_th[n-1]
+// (T[0] = 0, th[0] = 0); adjoint L[n] = P Gk[n+1] (L[N_tau] = 0).
+// blockIdx.y = row.
+__global__ void k_cm_guess(const EngineDesc *__restrict__ D, CoarseMesh M, int adjoint,
+                           double *rows, double *th) {
+    const Consts &C = D->C;
+    const Bufs &B = D->B;
+    const int n = blockIdx.y;
+    double *out = rows + (size_t)n * C.Nn;
+    const int src = adjoint ? n + 1 : n - 1;
+    const bool zero = adjoint ? n == C.Ntau : n == 0;
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < C.Nn; id += gridDim.x * blockDim.x)
+        out[id] = zero ? 0.0 : cm_prolong(C, M, B.mask, crow(M.Gk, M, src), id);
+    if (!adjoint && blockIdx.x == 0 && threadIdx.x == 0) th[n] = zero ? 0.0 : B.Gk_th[n - 1];
+}
+
+// Corrected fine states (blockIdx.y = n):
+// primal u^{k+1}_{n+1} = F_n + P(Gn[n] - Gk[n]) into S row M(n+1) and out_T[n+1]
+// (n = 0: F_0); adjoint lambda^{k+1}_{n-1} = F_n + P(Gn[n] - Gk[n]) into
+// out_L[n-1] (n = N_tau: F_{N_tau}), and out_L[N_tau] = 0.
+__global__ void k_cm_correct(const EngineDesc *__restrict__ D, CoarseMesh M, int adjoint) {
+    const Consts &C = D->C;
+    const Bufs &B = D->B;
+    const int n = blockIdx.y + (adjoint ? 1 : 0);
+    const bool corr = adjoint ? n < C.Ntau : n > 0;
+    const double *gn = crow(M.Gn, M, n), *gk = crow(M.Gk, M, n);
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < C.Nn;
+         id += gridDim.x * blockDim.x) {
+        const double d = corr ? cm_prolong_diff(C, M, B.mask, gn, gk, id) : 0.0;
+        if (!adjoint) {
+            double *row = B.S + (size_t)(C.M * (n + 1) - 1) * C.Nn;
+            const double v = row[id] + d;
+            row[id] = v;
+            B.out_T[(size_t)(n + 1) * C.Nn + id] = v;
+        } else {
+            B.out_L[(size_t)(n - 1) * C.Nn + id] = B.FL[(size_t)n * C.Nn + id] + d;
+            if (n == C.Ntau) B.out_L[(size_t)C.Ntau * C.Nn + id] = 0.0;
+        }
+    }
+}
+
+// accG_e = sum_{n=1}^{N_tau-1} lambda_n^T (dC (T_m - T_{m-M})/dtau + dK T_m) on
+// fine element e, lambda_n = P(Gn[n] - Gk[n]), m = M(n-1)+1 (T_{m-M} = 0 when
+// m - M < 1): the coarse-correction part of the summed Eq. 4.10.
+__global__ void k_cm_sens(const EngineDesc *__restrict__ D, CoarseMesh M) {
+    const Consts &C = D->C;
+    const Bufs &B = D->B;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < C.Ne; e += gridDim.x * blockDim.x) {
+        const int ey = e / C.nx, ex = e - ey * C.nx;
+        int id[4];
+        for (int a = 0; a < 4; ++a) id[a] = (ey + oy(a)) * C.W + ex + ox(a);
+        double sk = 0.0, sc = 0.0;
+        for (int n = 1; n < C.Ntau; ++n) {
+            const double *gn = crow(M.Gn, M, n), *gk = crow(M.Gk, M, n);
+            const int m = C.M * (n - 1) + 1;
+            const double *Tm = B.S + (size_t)(m - 1) * C.Nn;
+            const double *Tp = m - C.M >= 1 ? B.S + (size_t)(m - C.M - 1) * C.Nn : nullptr;
+            double l[4], t[4], dt[4];
+            for (int a = 0; a < 4; ++a) {
+                l[a] = cm_prolong_diff(C, M, B.mask, gn, gk, id[a]);
+                t[a] = Tm[id[a]];
+                dt[a] = t[a] - (Tp ? Tp[id[a]] : 0.0);
+            }
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) {
+                    sk += l[a] * (C.hy / C.hx * kx_pat(a, b) + C.hx / C.hy * ky_pat(a, b)) * t[b];
+                    sc += l[a] * cm_pat(a, b) * dt[b];
+                }
+        }
+        B.accG[e] = B.dk[e] * sk / 6.0 + B.dc[e] * C.inv_dtau * C.hx * C.hy / 36.0 * sc;
+    }
+}
+
+int cm_check() { return hipGetLastError() == hipSuccess ? PT_OK : PT_EHIP; }
+
+}  // namespace
+
+int cm_setup(const EngineDesc *D, const CoarseMesh &M, hipStream_t stream) {
+    hipLaunchKernelGGL(k_cm_coef, dim3((M.Nec + 255) / 256), dim3(256), 0, stream, D, M);
+    hipLaunchKernelGGL(k_cm_stencil, dim3((M.Nc + 255) / 256), dim3(256), 0, stream, D, M);
+    return cm_check();
+}
+
+int cm_cold(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
+            double *rows, double *th, hipStream_t stream) {
+    hipLaunchKernelGGL(k_cm_sweep, dim3(1), dim3(kCT), 0, stream, D, M, adjoint ? 1 : 0, 1);
+    hipLaunchKernelGGL(k_cm_guess, dim3(std::min((Nn + 255) / 256, 1024), Ntau + 1), dim3(256),
+                       0, stream, D, M, adjoint ? 1 : 0, rows, th);
+    return cm_check();
+}
+
+int cm_batched(const EngineDesc *D, const CoarseMesh &M, int Ntau, bool adjoint,
+               hipStream_t stream) {
+    if (Ntau < 2) return PT_OK;
+    hipLaunchKernelGGL(k_cm_batched, dim3(Ntau - 1), dim3(kCT), 0, stream, D, M,
+                       adjoint ? 1 : 0);
+    return cm_check();
+}
+
+int cm_sweep_correct(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
+                     int Ne, hipStream_t stream) {
+    hipLaunchKernelGGL(k_cm_sweep, dim3(1), dim3(kCT), 0, stream, D, M, adjoint ? 1 : 0, 0);
+    hipLaunchKernelGGL(k_cm_correct, dim3(std::min((Nn + 255) / 256, 1024), Ntau), dim3(256), 0,
+                       stream, D, M, adjoint ? 1 : 0);
+    if (adjoint)
+        hipLaunchKernelGGL(k_cm_sens, dim3(std::min((Ne + 255) / 256, 4096)), dim3(256), 0,
+                           stream, D, M);
+    return cm_check();
+}
+
+}  // namespace pt

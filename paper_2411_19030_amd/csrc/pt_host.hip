@@ -65,7 +65,13 @@ bool valid_problem(const pt_problem *p) {
         return false;
     if (p->bc < 0 || p->bc > 3) return false;
     if (p->bc == PT_BC_MASK && !p->dirichlet_mask) return false;
-    if (p->propagator != PT_PARAREAL && p->propagator != PT_PLT) return false;
+    if (p->propagator != PT_PARAREAL && p->propagator != PT_PLT &&
+        p->propagator != PT_COARSE_MESH)
+        return false;
+    if (p->propagator == PT_COARSE_MESH &&
+        ((p->nx % 2) || (p->ny % 2) || p->precision != PT_FP64 || p->precond != PT_JACOBI ||
+         p->storage != PT_STORE_ALL || p->coarse_iters != 0))
+        return false;
     if (p->coarse_iters < 0 || p->coarse_iters > 100000) return false;
     if (p->coarse_iters > 0 &&
         (p->precision != PT_FP64 || p->propagator != PT_PARAREAL || p->precond != PT_JACOBI))
@@ -122,6 +128,8 @@ struct DesignLayout {
     size_t gA64, gA, gA0, gmg_g, gmg_w, ck;
     size_t ck_stride;
     size_t Gk, Gn, Gk_th, Gn_th, F_th, Uprev, Uprev_th, Ubuf, Ubuf_th, acc, accG;
+    // coarse-mesh propagators (PT_COARSE_MESH)
+    size_t cm_kE, cm_cE, cm_A9, cm_C9, cm_dinv, cm_fc, cm_Gk, cm_Gn, cm_vec;
     // multi-design cycles keep the cycle's state here
     size_t S, uT, uth, lam, gT, gth, gL;
 };
@@ -159,6 +167,19 @@ void carve_design(Carver &c, const pt_problem *p, DesignLayout &L, bool batched)
     const int M = p->n_steps / p->n_slices;
     L.ck_stride = p->storage == PT_CHECKPOINT ? (size_t)std::max(M - 2, 0) * Nn : 0;
     L.ck = c.take(d * (size_t)ck_slots(p) * L.ck_stride + d);
+    if (p->propagator == PT_COARSE_MESH) {
+        const size_t Nc = (size_t)(p->nx / 2 + 1) * (p->ny / 2 + 1);
+        const size_t Nec = (size_t)(p->nx / 2) * (p->ny / 2);
+        L.cm_kE = c.take(d * Nec);
+        L.cm_cE = c.take(d * Nec);
+        L.cm_A9 = c.take(d * 9 * Nc);
+        L.cm_C9 = c.take(d * 9 * Nc);
+        L.cm_dinv = c.take(d * Nc);
+        L.cm_fc = c.take(d * Nc);
+        L.cm_Gk = c.take(d * Nt1 * Nc);
+        L.cm_Gn = c.take(d * Nt1 * Nc);
+        L.cm_vec = c.take(d * (size_t)p->n_slices * kCoarseMeshVecs * Nc);
+    }
     if (!batched) {
         L.Uprev = c.take(d * Nt1 * Nn);
         L.Uprev_th = c.take(d * Nt1);
@@ -385,6 +406,25 @@ Bufs make_bufs(void *ws, const DesignLayout &L, const SharedLayout &S, int desig
     B.ck = at<double>(ws, L.ck);
     B.ck_stride = L.ck_stride;
     return B;
+}
+
+CoarseMesh make_coarse_mesh(void *ws, const DesignLayout &L, const pt_problem *p) {
+    CoarseMesh M{};
+    M.nxc = p->nx / 2;
+    M.nyc = p->ny / 2;
+    M.Wc = M.nxc + 1;
+    M.Nc = M.Wc * (M.nyc + 1);
+    M.Nec = M.nxc * M.nyc;
+    M.kE = at<double>(ws, L.cm_kE);
+    M.cE = at<double>(ws, L.cm_cE);
+    M.A9 = at<double>(ws, L.cm_A9);
+    M.C9 = at<double>(ws, L.cm_C9);
+    M.dinv = at<double>(ws, L.cm_dinv);
+    M.fc = at<double>(ws, L.cm_fc);
+    M.Gk = at<double>(ws, L.cm_Gk);
+    M.Gn = at<double>(ws, L.cm_Gn);
+    M.vec = at<double>(ws, L.cm_vec);
+    return M;
 }
 
 Launch make_launch(void *ws, const SharedLayout &S, Control *ctl0, long long timeout_ticks) {
@@ -1129,6 +1169,110 @@ bool valid_batch(int n, const pt_problem *probs) {
     return true;
 }
 
+// Passes with coarse propagators on the coarse spatial mesh (PT_COARSE_MESH).
+// Per iteration: one engine launch of every slice's fine propagator from the
+// guesses u^k_n, then on the coarse mesh the batched steps G(R u^k_n) (first
+// warm iteration; later ones reuse the previous sweep's outputs, and a cold
+// start takes them from the cold sweep), the sequential correction sweep, and
+// the corrected fine states. A cold start first runs the coarse cold sweep and
+// prolongs it into the fine guesses.
+int coarse_mesh_forward(const pt_problem *prob, std::vector<EngineDesc> &hd, EngineDesc *D,
+                        const Layout &Lay, void *ws, const double *guess_T,
+                        const double *guess_theta, hipStream_t stream) {
+    EngineDesc &E = hd[0];
+    const Consts &C = E.C;
+    Bufs &B = E.B;
+    const int Ntau = C.Ntau;
+    const size_t Nt1 = (size_t)Ntau + 1, Nn = C.Nn;
+    CoarseMesh M = make_coarse_mesh(ws, Lay.d, prob);
+    double *Uprev = at<double>(ws, Lay.d.Uprev), *Uprev_th = at<double>(ws, Lay.d.Uprev_th);
+    double *Ga_th = at<double>(ws, Lay.d.Gk_th), *Gb_th = at<double>(ws, Lay.d.Gn_th);
+    if (Ntau > 1) PT_TRY(cm_setup(D, M, stream));
+    for (int it = 0; it < prob->iterations; ++it) {
+        LaunchInfo &I = E.I;
+        I = LaunchInfo{};
+        I.has_dc = (prob->c0 != prob->cmin) ? 1 : 0;
+        I.epoch = 1;
+        B.Gk_th = Ga_th;
+        B.Gn_th = Gb_th;
+        const bool cold0 = guess_T == nullptr && it == 0 && Ntau > 1;
+        const double *inT = it == 0 ? guess_T : Uprev;
+        const double *inth = it == 0 ? guess_theta : Uprev_th;
+        if (cold0) {
+            B.in_T = nullptr;
+            B.in_th = nullptr;
+            PT_TRY(upload_descs(hd, D, stream));
+            PT_TRY(cm_cold(D, M, C.Nn, Ntau, false, Uprev, Uprev_th, stream));
+            inT = Uprev;
+            inth = Uprev_th;
+        }
+        B.in_T = inT;
+        B.in_th = inth;
+        PT_TRY(upload_descs(hd, D, stream));
+        std::vector<LanePlan> plans;
+        plans.push_back(fine_plan(F_PRI, Ntau, 0, +1, C, prob));
+        PT_TRY(run_engine(E, D, plans, ws, Lay, stream));
+        if (Ntau > 1) {
+            if (it == 0 && !cold0) PT_TRY(cm_batched(D, M, Ntau, false, stream));
+            PT_TRY(cm_sweep_correct(D, M, C.Nn, Ntau, false, C.Ne, stream));
+        }
+        if (it + 1 < prob->iterations) {
+            hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Uprev, B.out_T,
+                               Nt1 * Nn);
+            hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(256), 0, stream, Uprev_th, B.out_th, Nt1);
+            PT_TRY(launch_check());
+            std::swap(M.Gk, M.Gn);
+            std::swap(Ga_th, Gb_th);
+        }
+    }
+    hipLaunchKernelGGL(k_finalize_fwd, dim3(256, 1), dim3(256), 0, stream, D);
+    return launch_check();
+}
+
+int coarse_mesh_adjoint(const pt_problem *prob, std::vector<EngineDesc> &hd, EngineDesc *D,
+                        const Layout &Lay, void *ws, const double *guess_lambda,
+                        hipStream_t stream) {
+    EngineDesc &E = hd[0];
+    const Consts &C = E.C;
+    Bufs &B = E.B;
+    const int Ntau = C.Ntau;
+    const size_t Nt1 = (size_t)Ntau + 1, Nn = C.Nn;
+    CoarseMesh M = make_coarse_mesh(ws, Lay.d, prob);
+    double *Lprev = at<double>(ws, Lay.d.Uprev);
+    if (Ntau > 1) PT_TRY(cm_setup(D, M, stream));
+    for (int it = 0; it < prob->iterations; ++it) {
+        LaunchInfo &I = E.I;
+        I = LaunchInfo{};
+        I.has_dc = (prob->c0 != prob->cmin) ? 1 : 0;
+        I.epoch = 1;
+        const bool cold0 = guess_lambda == nullptr && it == 0 && Ntau > 1;
+        const double *inL = it == 0 ? guess_lambda : Lprev;
+        if (cold0) {
+            B.in_L = nullptr;
+            PT_TRY(upload_descs(hd, D, stream));
+            PT_TRY(cm_cold(D, M, C.Nn, Ntau, true, Lprev, nullptr, stream));
+            inL = Lprev;
+        }
+        B.in_L = inL;
+        PT_TRY(upload_descs(hd, D, stream));
+        std::vector<LanePlan> plans;
+        plans.push_back(fine_plan(F_ADJ, Ntau, Ntau, -1, C, prob));
+        PT_TRY(run_engine(E, D, plans, ws, Lay, stream));
+        if (Ntau > 1) {
+            if (it == 0 && !cold0) PT_TRY(cm_batched(D, M, Ntau, true, stream));
+            PT_TRY(cm_sweep_correct(D, M, C.Nn, Ntau, true, C.Ne, stream));
+        }
+        if (it + 1 < prob->iterations) {
+            hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Lprev, B.out_L,
+                               Nt1 * Nn);
+            PT_TRY(launch_check());
+            std::swap(M.Gk, M.Gn);
+        }
+    }
+    hipLaunchKernelGGL(k_finalize_adj, dim3(256, 1), dim3(256), 0, stream, D);
+    return launch_check();
+}
+
 }  // namespace
 
 extern "C" {
@@ -1200,6 +1344,13 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
     const bool cold = guess_T == nullptr;
     const int Ntau = C.Ntau;
     Bufs &B = E.B;
+    if (prob->propagator == PT_COARSE_MESH) {
+        B.S = S;
+        B.out_T = outT;
+        B.out_th = outth;
+        B.Theta_out = Theta_out;
+        return coarse_mesh_forward(prob, hd, D, Lay, ws, guess_T, guess_theta, stream);
+    }
     for (int it = 0; it < prob->iterations; ++it) {
         LaunchInfo &I = E.I;
         I = LaunchInfo{};
@@ -1282,6 +1433,12 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
     const bool cold = guess_lambda == nullptr;
     const int Ntau = C.Ntau;
     Bufs &B = E.B;
+    if (prob->propagator == PT_COARSE_MESH) {
+        B.S = const_cast<double *>(S);
+        B.Theta = Theta;
+        B.out_L = outL;
+        return coarse_mesh_adjoint(prob, hd, D, Lay, ws, guess_lambda, stream);
+    }
     for (int it = 0; it < prob->iterations; ++it) {
         LaunchInfo &I = E.I;
         I = LaunchInfo{};

@@ -209,4 +209,30 @@ enum {
     TR_HDR = 12
 };
 
+// Coarse-spatial-mesh propagators (propagator PT_COARSE_MESH): the coarse
+// mesh has nx/2 x ny/2 elements; coarse node (I, J) is fine node (2I, 2J).
+constexpr int kCoarseMeshThreads = 1024;  // one workgroup per coarse solve
+constexpr int kCoarseMeshVecs = 6;        // r, z, p, q, b, u of one solve slot
+
+struct CoarseMesh {
+    int nxc, nyc, Wc, Nc, Nec;  // elements per side, nodes per row, nodes, elements
+    double *kE, *cE;            // coarse element k and c (means of the fine SIMP values)
+    double *A9;                 // [9][Nc] rows of C_c/dtau + K_c without Dirichlet rows/columns
+    double *C9;                 // [9][Nc] rows of C_c/dtau (Dirichlet rows zero)
+    double *dinv;               // [Nc] 1/diag of A (0 on Dirichlet nodes)
+    double *fc;                 // [Nc] int N_I (0 on Dirichlet nodes)
+    double *Gk, *Gn;            // [Ntau+1][Nc] coarse outputs G(R u^k_n), G(u^{k+1}_n)
+    double *vec;                // [Ntau][kCoarseMeshVecs][Nc] solve slots
+};
+
+// Host entry points of the coarse-mesh kernels (pt_cmesh.hip); D is the
+// uploaded single-design descriptor. Each returns PT_OK or PT_EHIP.
+int cm_setup(const EngineDesc *D, const CoarseMesh &M, hipStream_t stream);
+int cm_cold(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
+            double *rows, double *th, hipStream_t stream);
+int cm_batched(const EngineDesc *D, const CoarseMesh &M, int Ntau, bool adjoint,
+               hipStream_t stream);
+int cm_sweep_correct(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
+                     int Ne, hipStream_t stream);
+
 }  // namespace pt

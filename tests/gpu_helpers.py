@@ -40,6 +40,8 @@ def run_oracle(cfg: dict, rho: np.ndarray, guess=None):
     nu = cfg.get("coarse_iters", 0)
     Gp = O.make_G_pri(nu) if nu > 0 else None
     Ga = O.make_G_adj(nu) if nu > 0 else None
+    if cfg.get("propagator", 0) == 2:   # coarse propagators on the coarse spatial mesh
+        Gp, Ga = O.make_G_pri_mesh(d), O.make_G_adj_mesh(d)
     if guess is None:
         fw = O.parareal_forward(d, it, G=Gp)
         ad = O.parareal_adjoint(d, fw["S"], fw["Theta"], it, G=Ga)

@@ -44,9 +44,13 @@ def base(**kw):
     dict(pnorm=7), dict(pnorm=0), dict(n_slices=5), dict(nx=0), dict(ny=-1),
     dict(cg_rtol=0.0), dict(cg_rtol=float("nan")), dict(max_iter=0), dict(iterations=0),
     dict(t_final=0.0), dict(kmin=0.0), dict(pk=0.5), dict(precision=7), dict(precond=9),
-    dict(storage=4), dict(n_steps=0), dict(q=float("inf")), dict(propagator=2),
+    dict(storage=4), dict(n_steps=0), dict(q=float("inf")), dict(propagator=3),
     dict(propagator=-1), dict(coarse_iters=-1), dict(coarse_iters=5, precision=1),
     dict(coarse_iters=5, propagator=1), dict(coarse_iters=5, precond=1),
+    # the coarse spatial mesh halves even grids, with FP64 Jacobi store-all passes
+    dict(propagator=2, nx=9), dict(propagator=2, ny=7), dict(propagator=2, precision=1),
+    dict(propagator=2, precond=1), dict(propagator=2, storage=1),
+    dict(propagator=2, coarse_iters=5),
 ])
 def test_validate_rejects(lib, kw):
     p = base(**kw)
@@ -58,6 +62,10 @@ def test_validate_accepts_and_sizes(lib):
     p = base()
     assert _pt.pt_validate(p) == _pt.PT_OK
     assert _pt.pt_validate(base(propagator=_pt.PT_PLT)) == _pt.PT_OK
+    assert _pt.pt_validate(base(propagator=_pt.PT_COARSE_MESH)) == _pt.PT_OK
+    # the coarse mesh's arrays are part of the workspace
+    assert (_pt.pt_workspace_bytes(base(propagator=_pt.PT_COARSE_MESH))
+            > _pt.pt_workspace_bytes(base()))
     small = _pt.pt_workspace_bytes(p)
     big = _pt.pt_workspace_bytes(base(nx=64, ny=64))
     assert 0 < small < big
@@ -144,10 +152,10 @@ def test_batched_workspace_and_validation(lib):
     nb2 = lib.pt_batched_workspace_bytes(2, arr)
     nb1 = lib.pt_batched_workspace_bytes(1, one)
     assert nb2 > nb1 > 0
-    # mixed precision, several Parareal iterations, zero coarse propagators,
-    # invalid members: no workspace
+    # mixed precision, several Parareal iterations, zero or coarse-mesh coarse
+    # propagators, invalid members: no workspace
     for bad in (base(precision=1), base(iterations=2), base(pnorm=3), base(propagator=1),
-                base(coarse_iters=4)):
+                base(propagator=2), base(coarse_iters=4)):
         arr_bad = (PtProblem * 2)(a.to_c(), bad.to_c())
         assert lib.pt_batched_workspace_bytes(2, arr_bad) == 0
     assert lib.pt_batched_workspace_bytes(0, arr) == 0
