@@ -34,8 +34,8 @@ WORKLOAD = "plain_fp64_256"
 # WRITE_SIZE runs (each scaled by what the counter reads for a 1 GiB device
 # copy: x2.0 and x1.0), averaged over the forward and adjoint launches of a warm
 # cycle; valid only for the kernel sources with this hash (see profiles/).
-TRAFFIC = {"sources_sha1": "90df25c9bc3a3f51cf63ed573219310c0fbb2d9e",
-           "bytes_per_launch": 0.5 * (29.37e9 + 29.19e9)}
+TRAFFIC = {"sources_sha1": "cedb8cdf580963775e216f31f2ef2244ded2c64b",
+           "bytes_per_launch": 0.5 * (29.41e9 + 29.24e9)}
 
 
 def sources_sha1() -> str:
@@ -63,7 +63,7 @@ def parse():
                     help="skip the 64-design batch (batched FP32+refine vs plain FP64)")
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=[WORKLOAD, "batch_fp32_64", "large_2048", "large_law_512",
-                             "paper_100", "one_shot_chain", "plt_fp64_256"],
+                             "paper_100", "one_shot_chain", "plt_fp64_256", "cmesh_fp64_256"],
                     help="the headline workload (default), or one of the other workloads "
                          "measured on its own")
     ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
@@ -282,13 +282,13 @@ def coarse_compare(prob, rho, ref_ms, ref_theta, ref_grad, nus=(10, 20), repeats
     return out
 
 
-def coarse_mesh_compare(prob, rho, ref_ms, ref_theta, ref_grad, repeats=3) -> dict:
+def coarse_mesh_compare(prob, rho, ref_ms=None, ref_theta=None, ref_grad=None,
+                        repeats=3) -> dict:
     """The coarse propagators on the nx/2 x ny/2 mesh (propagator
     PT_COARSE_MESH, Sec. 7.3) on the same workload and protocol as the
     headline: the cold cycle gives the guesses, warm cycles are timed (median
     of `repeats`), and Theta and the gradient are compared with the exact-G
-    one-shot cycle. The per-pass split into the fine-propagator launch and the
-    coarse-mesh work comes from the status counters of each pass."""
+    one-shot cycle when it is given."""
     import dataclasses
 
     import torch
@@ -311,13 +311,14 @@ def coarse_mesh_compare(prob, rho, ref_ms, ref_theta, ref_grad, repeats=3) -> di
     ms = sorted(ts)[len(ts) // 2]
     th = float(cyc.Theta)
     st = cyc.status()
-    out = {"ms_per_cycle": ms, "speedup_over_exact_G": ref_ms / ms,
-           "Theta_rel_diff_vs_exact_G": abs(th - ref_theta) / ref_theta,
-           "grad_rel_diff_vs_exact_G": float(torch.linalg.norm(cyc.grad - ref_grad) /
-                                             torch.linalg.norm(ref_grad)),
+    out = {"ms_per_cycle": ms, "Theta": th,
            "adjoint_coarse_cg_iterations": st["cg_iters_coarse"],
-           "adjoint_coarse_solves": st["solves_coarse"],
-           "status": st["status"]}
+           "adjoint_coarse_solves": st["solves_coarse"], "status": st["status"]}
+    if ref_ms is not None:
+        out.update({"speedup_over_exact_G": ref_ms / ms,
+                    "Theta_rel_diff_vs_exact_G": abs(th - ref_theta) / ref_theta,
+                    "grad_rel_diff_vs_exact_G": float(torch.linalg.norm(cyc.grad - ref_grad) /
+                                                      torch.linalg.norm(ref_grad))})
     del cyc
     return out
 
@@ -687,6 +688,19 @@ def main():
         print(json.dumps(plt_compare(prob, rho, None, None,
                                      precisions=(("fp64", 0, prob.cg_rtol),),
                                      repeats=max(1, args.steps))))
+        return
+    if args.workload == "cmesh_fp64_256":
+        # the coarse-spatial-mesh cycle of the headline workload on its own
+        # (FP64, guesses from its cold cycle), e.g. for profiling its kernels
+        w = workload(WORKLOAD)
+        prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
+                       pnorm=w["p"], k0=w["k0"], kmin=w["kmin"], pk=w["pk"], c0=w["c0"],
+                       cmin=w["cmin"], pc=w["pc"], q=w["q"], t_final=w["t_final"], bc=w["bc"],
+                       iterations=1, cg_rtol=w["rtol"], max_iter=20000)
+        rho = torch.tensor(workload_density(WORKLOAD), dtype=torch.float64,
+                           device=torch.device("cuda:0"))
+        print(json.dumps({"workload": "cmesh_fp64_256",
+                          **coarse_mesh_compare(prob, rho, repeats=max(1, args.steps))}))
         return
     w = workload(WORKLOAD)
     prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],

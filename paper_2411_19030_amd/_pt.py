@@ -91,6 +91,11 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"libpt.so not found at {path}: build it with "
                            "`python -m paper_2411_19030_amd.build`")
+    # torch first: libpt.so then binds to the HIP runtime torch has loaded, the
+    # one that owns the tensors and streams passed in. Opened before torch, it
+    # would pull in the system runtime beside torch's bundled one, and its
+    # launches would fail on torch's pointers and streams.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER(PtProblem)
     vp = ctypes.c_void_p
