@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "pt.h"
 #include "pt_internal.h"
@@ -313,6 +314,22 @@ __device__ void cm_pcg(const Consts &C, const CoarseMesh &M, Control *ctl, const
     __syncthreads();
 }
 
+extern __shared__ double cm_lds[];
+
+// The solve slot's vectors in LDS (6 Nc doubles of dynamic LDS) instead of
+// global memory, for coarse meshes that fit: the same arithmetic, with the
+// per-iteration vector traffic off the CU's cache path.
+__device__ __forceinline__ CmVecs cm_vecs_lds(const CoarseMesh &M) {
+    CmVecs V;
+    V.r = cm_lds;
+    V.z = cm_lds + M.Nc;
+    V.p = cm_lds + 2 * (size_t)M.Nc;
+    V.q = cm_lds + 3 * (size_t)M.Nc;
+    V.b = cm_lds + 4 * (size_t)M.Nc;
+    V.u = cm_lds + 5 * (size_t)M.Nc;
+    return V;
+}
+
 // theta' = (theta^p + ||P x||_p^p / (N_tau N_e))^{1/p} (Alg. 1 with dtau, N_tau)
 __device__ double cm_theta(const Consts &C, const CoarseMesh &M, const Bufs &B, const double *x,
                            double theta, double *red, int &par) {
@@ -330,6 +347,7 @@ __device__ __forceinline__ double *crow(double *base, const CoarseMesh &M, int n
 // Batched coarse steps G(R u^k_n), n = blockIdx.x + 1 (1 .. N_tau - 1):
 // primal from (in_T[n], in_th[n]) into Gk[n], Gk_th[n]; adjoint from in_L[n]
 // into Gk[n]. One workgroup per step, vector slot n.
+template <bool LDS>
 __global__ void __launch_bounds__(kCT) k_cm_batched(const EngineDesc *__restrict__ D,
                                                     CoarseMesh M, int adjoint) {
     __shared__ double red[2 * 2 * kCW];
@@ -337,7 +355,7 @@ __global__ void __launch_bounds__(kCT) k_cm_batched(const EngineDesc *__restrict
     const Consts &C = D->C;
     const Bufs &B = D->B;
     const int n = blockIdx.x + 1;
-    const CmVecs V = cm_vecs(M, n);
+    const CmVecs V = LDS ? cm_vecs_lds(M) : cm_vecs(M, n);
     double *x = crow(M.Gk, M, n);
     if (!adjoint) {
         const double *u = B.in_T + (size_t)n * C.Nn;
@@ -373,13 +391,14 @@ __global__ void __launch_bounds__(kCT) k_cm_batched(const EngineDesc *__restrict
 // with G(hat u_n) written to Gn (and the theta chain to Gn_th, out_th); the
 // primal reads F_n from S row M(n+1) and theta(F_n) from F_th, the adjoint
 // F_n from FL. Each solve starts from G(u^k_n) + (hat u_n - R u^k_n).
+template <bool LDS>
 __global__ void __launch_bounds__(kCT) k_cm_sweep(const EngineDesc *__restrict__ D,
                                                   CoarseMesh M, int adjoint, int cold) {
     __shared__ double red[2 * 2 * kCW];
     int par = 0;
     const Consts &C = D->C;
     const Bufs &B = D->B;
-    const CmVecs V = cm_vecs(M, 0);
+    const CmVecs V = LDS ? cm_vecs_lds(M) : cm_vecs(M, 0);
     const int Nt = C.Ntau;
     double *u = V.u;
     if (!adjoint) {
@@ -543,6 +562,46 @@ __global__ void k_cm_sens(const EngineDesc *__restrict__ D, CoarseMesh M) {
 
 int cm_check() { return hipGetLastError() == hipSuccess ? PT_OK : PT_EHIP; }
 
+// LDS-resident solve vectors when they fit the workgroup's LDS;
+// PT_CM_LDS=0 keeps them in global memory at every size.
+size_t cm_lds_bytes(const CoarseMesh &M) {
+    const char *e = getenv("PT_CM_LDS");
+    if (e && atoi(e) == 0) return 0;
+    int dev = 0, cap = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    const size_t need = sizeof(double) * kCoarseMeshVecs * (size_t)M.Nc;
+    const size_t fixed = sizeof(double) * 2 * 2 * kCW;  // the reduction buffer
+    return need + fixed <= (size_t)cap ? need : 0;
+}
+
+// Launches kernel K<true> with the vectors in LDS when they fit, else K<false>.
+template <template <bool> class K, typename... Args>
+int cm_launch(const CoarseMesh &M, dim3 grid, hipStream_t stream, Args... args) {
+    const size_t lds = cm_lds_bytes(M);
+    if (lds > 0) {
+        auto kern = K<true>::kernel();
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds) != hipSuccess)
+            return PT_EHIP;
+        hipLaunchKernelGGL(kern, grid, dim3(kCT), (unsigned)lds, stream, args...);
+    } else {
+        hipLaunchKernelGGL(K<false>::kernel(), grid, dim3(kCT), 0, stream, args...);
+    }
+    return cm_check();
+}
+
+template <bool LDS>
+struct SweepK {
+    static auto kernel() { return &k_cm_sweep<LDS>; }
+};
+template <bool LDS>
+struct BatchedK {
+    static auto kernel() { return &k_cm_batched<LDS>; }
+};
+
 }  // namespace
 
 int cm_setup(const EngineDesc *D, const CoarseMesh &M, hipStream_t stream) {
@@ -553,7 +612,8 @@ int cm_setup(const EngineDesc *D, const CoarseMesh &M, hipStream_t stream) {
 
 int cm_cold(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
             double *rows, double *th, hipStream_t stream) {
-    hipLaunchKernelGGL(k_cm_sweep, dim3(1), dim3(kCT), 0, stream, D, M, adjoint ? 1 : 0, 1);
+    const int rc = cm_launch<SweepK>(M, dim3(1), stream, D, M, adjoint ? 1 : 0, 1);
+    if (rc != PT_OK) return rc;
     hipLaunchKernelGGL(k_cm_guess, dim3(std::min((Nn + 255) / 256, 1024), Ntau + 1), dim3(256),
                        0, stream, D, M, adjoint ? 1 : 0, rows, th);
     return cm_check();
@@ -562,14 +622,13 @@ int cm_cold(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adj
 int cm_batched(const EngineDesc *D, const CoarseMesh &M, int Ntau, bool adjoint,
                hipStream_t stream) {
     if (Ntau < 2) return PT_OK;
-    hipLaunchKernelGGL(k_cm_batched, dim3(Ntau - 1), dim3(kCT), 0, stream, D, M,
-                       adjoint ? 1 : 0);
-    return cm_check();
+    return cm_launch<BatchedK>(M, dim3(Ntau - 1), stream, D, M, adjoint ? 1 : 0);
 }
 
 int cm_sweep_correct(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
                      int Ne, hipStream_t stream) {
-    hipLaunchKernelGGL(k_cm_sweep, dim3(1), dim3(kCT), 0, stream, D, M, adjoint ? 1 : 0, 0);
+    const int rc = cm_launch<SweepK>(M, dim3(1), stream, D, M, adjoint ? 1 : 0, 0);
+    if (rc != PT_OK) return rc;
     hipLaunchKernelGGL(k_cm_correct, dim3(std::min((Nn + 255) / 256, 1024), Ntau), dim3(256), 0,
                        stream, D, M, adjoint ? 1 : 0);
     if (adjoint)

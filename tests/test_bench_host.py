@@ -32,4 +32,20 @@ def test_traffic_figure_matches_the_sources():
     import bench
     assert bench.TRAFFIC["bytes_per_launch"] > 0
     assert bench.sources_sha1() == bench.TRAFFIC["sources_sha1"], \
-        "kernel sources changed since the rocprofv3 counters were taken"
+        "engine sources changed since the rocprofv3 counters were taken"
+
+
+def test_traffic_hash_covers_the_engine_sources():
+    # every file the engine kernel is compiled from (its includes) is hashed
+    import re
+
+    import bench
+    csrc = os.path.join(ROOT, "paper_2411_19030_amd", "csrc")
+    seen, todo = set(), ["pt_host.hip"]
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(os.path.join(csrc, f)):
+            continue
+        seen.add(f)
+        todo += re.findall(r'#include "([^"/]+)"', open(os.path.join(csrc, f)).read())
+    assert seen == set(bench.ENGINE_SOURCES)

@@ -7,7 +7,9 @@ each output must agree to 1e-10 (relative to the field's maximum), the bar of
 the other parity tests. Cases: cold starts on several grids (ragged tiles,
 N_tau = 1, an odd-index Dirichlet mask), warm starts and two iterations (the
 sweep's outputs then serve as G(u^k_n)), c-SIMP with the paper's time-varying
-load and p = 20, bitwise reproducibility, the status counters, N_tau
+load and p = 20, the solve vectors in LDS (small coarse meshes) and in global
+memory (forced here, the form of large ones), bitwise reproducibility, the
+status counters, N_tau
 iterations giving the sequential method, and the full 256 x 256 workload in
 the launch configuration the benchmark times (cold and warm cycles at its own
 cg_rtol 1e-10, bar 1e-8 as in the other full-size tests).
@@ -110,3 +112,13 @@ def test_coarse_mesh_full_size_256(gpu):
     cold, _ = _check(cfg, rho, bar=1e-8)
     rho2 = np.clip(rho + 0.005 * np.cos(np.arange(rho.size) * 0.37), 0, 1)
     _check(cfg, rho2, (cold["uT"], cold["utheta"], cold["lam"]), bar=1e-8)
+
+
+def test_coarse_mesh_global_memory_solver(gpu, monkeypatch):
+    # the coarse solves' vectors in global memory (the form of coarse meshes
+    # too large for LDS) on a small case
+    monkeypatch.setenv("PT_CM_LDS", "0")
+    cfg = _cfg(nx=24, ny=20, n_steps=30, n_slices=10)
+    rho = density_uniform_noise(24, 20, 44)
+    _check(cfg, rho)
+    _check(dict(cfg, iterations=2), rho)
