@@ -1,0 +1,67 @@
+"""Device-side non-convergence reporting, forced from the host with an
+iteration cap (every kernel still ends normally).
+
+The cap is the largest CG count of the fine solves, taken from an uncapped
+run of the PLT form (fine solves only) in both passes; under it that run is
+unchanged and reports no problem. The coarse solves (dtau = M dt, a stiffer
+system) need more iterations, so a pass with coarse solves under the same cap
+must report PT_ENOCONV from its status block, with every output still written
+and finite: the engine's coarse lanes (exact G) and the one-workgroup
+coarse-mesh solver.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import gpu_problem
+from workloads import density_uniform_noise
+
+pytestmark = pytest.mark.gpu
+
+PT_ENOCONV = -4
+
+
+def _cfg(**kw):
+    c = dict(nx=32, ny=32, n_steps=64, n_slices=8, pnorm=8, cg_rtol=1e-10, max_iter=20000)
+    c.update(kw)
+    return c
+
+
+def _passes(cfg, rho):
+    """One cold cycle; the status block read after each pass."""
+    import torch
+
+    from paper_2411_19030_amd.cycle import Cycle
+    cyc = Cycle(gpu_problem(cfg), "cuda")
+    r = torch.tensor(rho, dtype=torch.float64, device="cuda")
+    cyc.forward(r)
+    st_f = cyc.status()
+    cyc.adjoint(r)
+    st_a = cyc.status()
+    cyc.sensitivities(r)
+    torch.cuda.synchronize()
+    out = dict(S=cyc.S.cpu().numpy(), uT=cyc.uT.cpu().numpy(), lam=cyc.lam.cpu().numpy(),
+               grad=cyc.grad.cpu().numpy(), Theta=float(cyc.Theta))
+    return out, st_f, st_a
+
+
+@pytest.mark.parametrize("prop", [0, 2])
+def test_capped_coarse_solves_report_enoconv(gpu, prop):
+    rho = density_uniform_noise(32, 32, 21)
+    _, pf, pa = _passes(_cfg(propagator=1), rho)
+    _, ff, fa = _passes(_cfg(propagator=prop), rho)
+    print(prop, pf, pa, ff, fa, flush=True)
+    assert pf["status"] == pa["status"] == ff["status"] == fa["status"] == 0
+    cap = max(pf["max_cg_iters"], pa["max_cg_iters"])
+    assert ff["max_cg_iters"] > cap and fa["max_cg_iters"] > cap
+    # the fine-only run is unchanged under the cap
+    _, qf, qa = _passes(_cfg(propagator=1, max_iter=cap), rho)
+    assert qf["status"] == qa["status"] == 0
+    g, sf, sa = _passes(_cfg(propagator=prop, max_iter=cap), rho)
+    print(sf, sa, flush=True)
+    for st in (sf, sa):
+        assert st["status"] == PT_ENOCONV
+        assert st["max_cg_iters"] == cap
+        assert st["max_rel_residual"] > 1e-10
+    for k in ("S", "uT", "lam", "grad"):
+        assert np.all(np.isfinite(g[k])), k
+    assert np.isfinite(g["Theta"]) and g["Theta"] > 0
