@@ -34,8 +34,8 @@ WORKLOAD = "plain_fp64_256"
 # WRITE_SIZE runs (each scaled by what the counter reads for a 1 GiB device
 # copy: x2.0 and x1.0), averaged over the forward and adjoint launches of a warm
 # cycle; valid only for the engine sources with this hash (see profiles/).
-TRAFFIC = {"sources_sha1": "cbbadeed47a1882631febb3813dc77addb2d87ba",
-           "bytes_per_launch": 0.5 * (29.41e9 + 29.24e9)}
+TRAFFIC = {"sources_sha1": "34ec1bfa2b2f319daad3b69cd92b3daa3375d842",
+           "bytes_per_launch": 0.5 * (29.52e9 + 29.30e9)}
 
 
 # The sources k_engine is built from: its kernel, its layouts and the host

@@ -104,7 +104,9 @@ __device__ __forceinline__ void lds_sync() {
 // the group counter and spins until all g workgroups have arrived. With
 // `release`, thread 0 also issues an agent-scope release fence first, which
 // publishes this workgroup's plain stores to other XCDs. Returns false on
-// timeout or when another workgroup aborted.
+// timeout or when another workgroup aborted. Each group's counter has a cache
+// line of its own, and the spin reads the shared abort flag only every 64th
+// turn: the groups' polls then do not contend for one line.
 __device__ bool group_barrier(unsigned *cnt, unsigned target, Control *ctl, long long timeout,
                               bool release) {
     __shared__ int s_ok;
@@ -116,9 +118,10 @@ __device__ bool group_barrier(unsigned *cnt, unsigned target, Control *ctl, long
         __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
         long long t0 = now_ticks();
+        unsigned spins = 0;
         while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
-            if (aborted(ctl) || now_ticks() - t0 > timeout) {
+            if ((++spins & 63u) == 0 && (aborted(ctl) || now_ticks() - t0 > timeout)) {
                 ok = 0;
                 break;
             }
@@ -716,7 +719,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
     const Group G = S.groups[gid];
     const int rank = blockIdx.x - G.wg0;
     const int g = G.nwg;
-    unsigned *bar = S.bar + gid;
+    unsigned *bar = S.bar + (size_t)gid * kBarStride;
     double *part = S.partials + (size_t)gid * 2 * kMaxGroup * 4;
     unsigned nbar = 0;
     const int XS = S.xch_stride;  // launch-wide halo slot length (>= H of every design)

@@ -212,7 +212,7 @@ void carve_shared(Carver &c, SharedLayout &S, int n_designs, int max_lanes, int 
     S.xch_stride = xch_stride;
     S.pool_stride = pool_stride;
     S.desc = c.take(sizeof(EngineDesc) * n_designs);
-    S.bar = c.take(sizeof(unsigned) * kMaxGroups);
+    S.bar = c.take(sizeof(unsigned) * kMaxGroups * kBarStride);
     S.flags = c.take(sizeof(unsigned) * kMaxFlags * (size_t)n_designs);
     S.partials = c.take(sizeof(double) * (size_t)max_groups * 2 * kMaxGroup * 4);
     S.wg_group = c.take(sizeof(int) * kMaxGrid);
@@ -620,7 +620,7 @@ int launch_engine(bool fp32, int npt, const EngineDesc *D, const EngineDesc *sin
 
 int reset_launch_state(void *ws, const SharedLayout &S, int n_designs, hipStream_t stream) {
     hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream, at<unsigned>(ws, S.bar),
-                       (size_t)kMaxGroups, 0u);
+                       (size_t)kMaxGroups * kBarStride, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, stream, at<unsigned>(ws, S.flags),
                        (size_t)kMaxFlags * n_designs, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, at<unsigned>(ws, S.qhead),
