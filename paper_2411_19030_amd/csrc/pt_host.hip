@@ -750,7 +750,15 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
     const int H = C.W + 1;
     const int lds_cap_d = lds_cap_doubles(dev);
     int grid = dev.cus * std::max(1, env_int("PT_WG_PER_CU", 1));
+    // sweep group: 40 workgroups. A resident sweep of full solves to a tight
+    // tolerance is the longest lane of the pass: it gets about 1200 nodes per
+    // workgroup within 40..56 (measured best at 256^2 and 100^2 with rtol
+    // 1e-10); shorter sweeps (truncated or loose solves) leave the fine lanes
+    // critical, and there more sweep workgroups only slow the fine lanes
     const int sweep_wgs = env_int("PT_SWEEP_WGS", 40);
+    const bool long_sweep = C.coarse_iters == 0 && C.rtol < 1e-9;
+    const int sweep_wgs_res = env_int(
+        "PT_SWEEP_WGS", long_sweep ? std::min(56, std::max(40, C.Nn / 1200)) : 40);
 
     const int NT = kThreads;
     const int res_npt_max = std::max(1, std::min(8, env_int("PT_RES_NPT", 8)));
@@ -769,7 +777,7 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
         for (size_t k = 0; k < plans.size(); ++k) {
             auto &p = plans[k];
             if (p.latency) {
-                nwg[k] = std::max(g_min, std::min(sweep_wgs, grid / 4));
+                nwg[k] = std::max(g_min, std::min(sweep_wgs_res, grid / 4));
                 nwg[k] = std::max(1, std::min(nwg[k], max_wg_per_lane));
                 ngroups[k] = p.count;
                 lat_wgs += nwg[k] * p.count;
