@@ -19,12 +19,13 @@
 // output difference; it is summed per fine element after the sweep (Eq. 4.10).
 //
 // Each coarse solve is Jacobi-preconditioned CG (Hestenes-Stiefel form) run by
-// one workgroup of 1024 threads over vectors in global memory, with the true
-// residual checked at the end; reductions are in a fixed order, so results are
-// bitwise reproducible. One workgroup suits the coarse meshes of moderate
-// grids (the 257^2-node mesh of a 512^2 design is about 1 MB per vector); the
-// sweep is latency-bound and a workgroup barrier costs far less than a
-// cross-workgroup one.
+// one workgroup of 1024 threads, with the true residual checked at the end;
+// reductions are in a fixed order, so results are bitwise reproducible. The
+// solve's vectors sit in LDS when they fit (about 3400 coarse nodes, e.g. the
+// 51^2 mesh of a 100^2 design), else in global memory, with the same
+// arithmetic. A workgroup barrier costs far less than a cross-workgroup one,
+// but one CU's memory path bounds the solve on large coarse meshes (about
+// 58 us per iteration at 129^2 with global vectors).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -346,7 +347,7 @@ __device__ __forceinline__ double *crow(double *base, const CoarseMesh &M, int n
 
 // Batched coarse steps G(R u^k_n), n = blockIdx.x + 1 (1 .. N_tau - 1):
 // primal from (in_T[n], in_th[n]) into Gk[n], Gk_th[n]; adjoint from in_L[n]
-// into Gk[n]. One workgroup per step, vector slot n.
+// into Gk[n]. One workgroup per step; its vectors in LDS, else in slot n.
 template <bool LDS>
 __global__ void __launch_bounds__(kCT) k_cm_batched(const EngineDesc *__restrict__ D,
                                                     CoarseMesh M, int adjoint) {
@@ -383,7 +384,7 @@ __global__ void __launch_bounds__(kCT) k_cm_batched(const EngineDesc *__restrict
     }
 }
 
-// The sequential coarse chain on one workgroup (vector slot 0).
+// The sequential coarse chain on one workgroup (vectors in LDS, else slot 0).
 // cold = 1: the cold sweep u^0_{n+1} = G(u^0_n) from u_0 = 0 (primal) or
 // v^0_{n-1} = G(v^0_n) from v_{N_tau} = 0 (adjoint), written to Gk.
 // cold = 0: the correction sweep of Eq. 4.2 / Eq. 4.9 on the coarse mesh,
