@@ -122,3 +122,13 @@ def test_coarse_mesh_global_memory_solver(gpu, monkeypatch):
     rho = density_uniform_noise(24, 20, 44)
     _check(cfg, rho)
     _check(dict(cfg, iterations=2), rho)
+
+
+@pytest.mark.parametrize("precision,precond,rtol,bar", [(1, 0, 1e-12, 1e-9), (0, 1, 1e-13, 1e-10),
+                                                        (1, 1, 1e-12, 1e-9)])
+def test_coarse_mesh_with_fp32_refine_and_multigrid_fine_lanes(gpu, precision, precond, rtol,
+                                                               bar):
+    # the fine lanes in FP32 with FP64 refinement and/or multigrid-preconditioned;
+    # the coarse-mesh solves stay FP64 Jacobi PCG
+    _check(_cfg(nx=48, ny=40, n_steps=60, n_slices=6, precision=precision, precond=precond,
+                cg_rtol=rtol), density_uniform_noise(48, 40, 52), bar=bar)
