@@ -94,7 +94,7 @@ typedef struct pt_problem {
     const uint8_t *dirichlet_mask; /* HOST, (nx+1)(ny+1) bytes, read when bc == PT_BC_MASK        */
     int32_t propagator;        /* PT_PARAREAL (0); PT_PLT: zero coarse propagators (Sec. 7);      */
                                /* PT_COARSE_MESH: coarse propagators on an nx/2 x ny/2 mesh      */
-                               /* (nx, ny even; PT_STORE_ALL; coarse solves FP64 Jacobi PCG)    */
+                               /* (nx, ny even; its coarse solves are FP64 Jacobi PCG)         */
     int32_t coarse_iters;      /* 0: coarse steps solved to cg_rtol; k > 0: a cheaper coarse     */
                                /* propagator, exactly k Jacobi-PCG iterations from the step's    */
                                /* input state (PT_FP64, PT_JACOBI and PT_PARAREAL only)         */

@@ -72,6 +72,17 @@ __device__ __forceinline__ int fine_of(const Consts &C, const CoarseMesh &M, int
     return 2 * J * C.W + 2 * i;
 }
 
+// Row of S holding the fine state T_j (j >= 1). Store-all keeps every state;
+// checkpoints keep the slice ends T_{Mn} (rows n - 1) and the slice starts
+// T_{Mn+1} (rows N_tau + n), which are the only states the coarse-mesh
+// kernels read (coarse points, and the adjoint's T_m and T_{m-M} with
+// m = M(n-1)+1).
+__device__ __forceinline__ double *cm_srow(const Consts &C, const Bufs &B, int j) {
+    if (!C.ckpt) return B.S + (size_t)(j - 1) * C.Nn;
+    if (j % C.M == 0) return B.S + (size_t)(j / C.M - 1) * C.Nn;
+    return B.S + (size_t)(C.Ntau + (j - 1) / C.M) * C.Nn;
+}
+
 // Coarse element coefficients: means of the fine SIMP values (Eq. 2.5-2.6).
 __global__ void k_cm_coef(const EngineDesc *__restrict__ D, CoarseMesh M) {
     const Consts &C = D->C;
@@ -373,7 +384,7 @@ __global__ void __launch_bounds__(kCT) k_cm_batched(const EngineDesc *__restrict
     } else {
         const double *l = B.in_L + (size_t)n * C.Nn;
         const int m = C.M * (n - 1) + 1;
-        const double *Tm = B.S + (size_t)(m - 1) * C.Nn;
+        const double *Tm = cm_srow(C, B, m);
         const double scale = pow(*B.Theta, 1.0 - C.p) / (double)C.Ne;
         for (int I = threadIdx.x; I < M.Nc; I += kCT) V.u[I] = l[fine_of(C, M, I)];
         __syncthreads();
@@ -410,7 +421,7 @@ __global__ void __launch_bounds__(kCT) k_cm_sweep(const EngineDesc *__restrict__
             th = 0.0;
             n0 = 0;
         } else {
-            const double *F0 = B.S + (size_t)(C.M - 1) * C.Nn;
+            const double *F0 = cm_srow(C, B, C.M);
             for (int I = threadIdx.x; I < M.Nc; I += kCT)
                 u[I] = M.dinv[I] == 0.0 ? 0.0 : F0[fine_of(C, M, I)];
             th = B.F_th[0];
@@ -441,7 +452,7 @@ __global__ void __launch_bounds__(kCT) k_cm_sweep(const EngineDesc *__restrict__
                     B.Gn_th[n] = thG;
                     B.out_th[n + 1] = th;
                 }
-                const double *Fn = B.S + (size_t)(C.M * (n + 1) - 1) * C.Nn;
+                const double *Fn = cm_srow(C, B, C.M * (n + 1));
                 for (int I = threadIdx.x; I < M.Nc; I += kCT)
                     u[I] = M.dinv[I] == 0.0 ? 0.0 : x[I] + Fn[fine_of(C, M, I)] - gk[I];
             }
@@ -462,7 +473,7 @@ __global__ void __launch_bounds__(kCT) k_cm_sweep(const EngineDesc *__restrict__
         __syncthreads();
         for (int n = n0; n >= 1; --n) {
             const int m = C.M * (n - 1) + 1;
-            const double *Tm = B.S + (size_t)(m - 1) * C.Nn;
+            const double *Tm = cm_srow(C, B, m);
             double *x = crow(cold ? M.Gk : M.Gn, M, n);
             const double *gk = crow(M.Gk, M, n);
             const double *lk = B.in_L ? B.in_L + (size_t)n * C.Nn : nullptr;
@@ -518,7 +529,7 @@ __global__ void k_cm_correct(const EngineDesc *__restrict__ D, CoarseMesh M, int
          id += gridDim.x * blockDim.x) {
         const double d = corr ? cm_prolong_diff(C, M, B.mask, gn, gk, id) : 0.0;
         if (!adjoint) {
-            double *row = B.S + (size_t)(C.M * (n + 1) - 1) * C.Nn;
+            double *row = cm_srow(C, B, C.M * (n + 1));
             const double v = row[id] + d;
             row[id] = v;
             B.out_T[(size_t)(n + 1) * C.Nn + id] = v;
@@ -543,8 +554,8 @@ __global__ void k_cm_sens(const EngineDesc *__restrict__ D, CoarseMesh M) {
         for (int n = 1; n < C.Ntau; ++n) {
             const double *gn = crow(M.Gn, M, n), *gk = crow(M.Gk, M, n);
             const int m = C.M * (n - 1) + 1;
-            const double *Tm = B.S + (size_t)(m - 1) * C.Nn;
-            const double *Tp = m - C.M >= 1 ? B.S + (size_t)(m - C.M - 1) * C.Nn : nullptr;
+            const double *Tm = cm_srow(C, B, m);
+            const double *Tp = m - C.M >= 1 ? cm_srow(C, B, m - C.M) : nullptr;
             double l[4], t[4], dt[4];
             for (int a = 0; a < 4; ++a) {
                 l[a] = cm_prolong_diff(C, M, B.mask, gn, gk, id[a]);

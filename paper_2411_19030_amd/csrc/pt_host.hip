@@ -68,10 +68,9 @@ bool valid_problem(const pt_problem *p) {
     if (p->propagator != PT_PARAREAL && p->propagator != PT_PLT &&
         p->propagator != PT_COARSE_MESH)
         return false;
-    // the coarse-mesh kernels address S as store-all; the fine lanes may use any
-    // precision and preconditioner (the coarse solves are FP64 Jacobi PCG)
-    if (p->propagator == PT_COARSE_MESH &&
-        ((p->nx % 2) || (p->ny % 2) || p->storage != PT_STORE_ALL || p->coarse_iters != 0))
+    // the fine lanes may use any precision, preconditioner and storage (the
+    // coarse solves are FP64 Jacobi PCG on the nx/2 x ny/2 mesh)
+    if (p->propagator == PT_COARSE_MESH && ((p->nx % 2) || (p->ny % 2) || p->coarse_iters != 0))
         return false;
     if (p->coarse_iters < 0 || p->coarse_iters > 100000) return false;
     if (p->coarse_iters > 0 &&

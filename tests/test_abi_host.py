@@ -47,9 +47,8 @@ def base(**kw):
     dict(storage=4), dict(n_steps=0), dict(q=float("inf")), dict(propagator=3),
     dict(propagator=-1), dict(coarse_iters=-1), dict(coarse_iters=5, precision=1),
     dict(coarse_iters=5, propagator=1), dict(coarse_iters=5, precond=1),
-    # the coarse spatial mesh halves even grids, with store-all passes
-    dict(propagator=2, nx=9), dict(propagator=2, ny=7), dict(propagator=2, storage=1),
-    dict(propagator=2, coarse_iters=5),
+    # the coarse spatial mesh halves even grids
+    dict(propagator=2, nx=9), dict(propagator=2, ny=7), dict(propagator=2, coarse_iters=5),
 ])
 def test_validate_rejects(lib, kw):
     p = base(**kw)
@@ -62,7 +61,7 @@ def test_validate_accepts_and_sizes(lib):
     assert _pt.pt_validate(p) == _pt.PT_OK
     assert _pt.pt_validate(base(propagator=_pt.PT_PLT)) == _pt.PT_OK
     assert _pt.pt_validate(base(propagator=_pt.PT_COARSE_MESH)) == _pt.PT_OK
-    for kw in (dict(precision=1), dict(precond=1), dict(precision=1, precond=1)):
+    for kw in (dict(precision=1), dict(precond=1), dict(precision=1, precond=1), dict(storage=1)):
         assert _pt.pt_validate(base(propagator=_pt.PT_COARSE_MESH, **kw)) == _pt.PT_OK
     # the coarse mesh's arrays are part of the workspace
     assert (_pt.pt_workspace_bytes(base(propagator=_pt.PT_COARSE_MESH))

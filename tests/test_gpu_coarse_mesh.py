@@ -132,3 +132,25 @@ def test_coarse_mesh_with_fp32_refine_and_multigrid_fine_lanes(gpu, precision, p
     # the coarse-mesh solves stay FP64 Jacobi PCG
     _check(_cfg(nx=48, ny=40, n_steps=60, n_slices=6, precision=precision, precond=precond,
                 cg_rtol=rtol), density_uniform_noise(48, 40, 52), bar=bar)
+
+
+def test_coarse_mesh_with_checkpoints(gpu):
+    # S holds T_{Mn} and T_{Mn+1} only; the fine adjoint lanes recompute the rest
+    cfg = _cfg(nx=48, ny=40, n_steps=60, n_slices=6)
+    rho = density_uniform_noise(48, 40, 61)
+    o = run_oracle(cfg, rho)
+    g = run_gpu(dict(cfg, storage=1), rho, with_status=True)
+    assert g["status"]["status"] == 0
+    M, Ntau = 10, 6
+    assert g["S"].shape[0] == 2 * Ntau
+    ref = dict(o, S=np.concatenate([o["S"][M - 1::M], o["S"][0::M]]))
+    e = compare(g, ref)
+    print("ckpt", e, g["status"], flush=True)
+    assert max(e.values()) <= 1e-10
+    # two iterations: the sweep's outputs serve as G(u^k_n) again
+    cfg2 = dict(cfg, iterations=2)
+    o2 = run_oracle(cfg2, rho)
+    g2 = run_gpu(dict(cfg2, storage=1), rho, with_status=True)
+    e2 = compare(g2, dict(o2, S=np.concatenate([o2["S"][M - 1::M], o2["S"][0::M]])))
+    print("ckpt 2 it", e2, flush=True)
+    assert g2["status"]["status"] == 0 and max(e2.values()) <= 1e-10
