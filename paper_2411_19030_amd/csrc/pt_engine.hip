@@ -185,12 +185,24 @@ __device__ void block_sum(double (&v)[Q], double *red) {
 }
 
 // Sum partials[0..g)[0..Q) in a fixed order (identical in every workgroup).
+// Each thread loads one value (entry e: workgroup e / Q, component e % Q), so
+// the loads of a round are all in flight at once; loading a workgroup's Q
+// values in one thread made the compiler reuse one register pair and wait
+// for each load in turn.
 template <int Q>
 __device__ void group_sum(const double *part, int g, double (&out)[Q], double *red) {
     double v[Q];
     for (int q = 0; q < Q; ++q) v[q] = 0.0;
-    for (int r = threadIdx.x; r < g; r += kThreads)
-        for (int q = 0; q < Q; ++q) v[q] += ldc(part + r * 4 + q);
+    // per-call index math (a hoisted, spilled address would be reloaded
+    // behind a wait for every load in flight)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    for (int e = tid; e < g * Q; e += kThreads) {
+        const int r = e / Q, q = e - r * Q;
+        const double x = ldc(part + r * 4 + q);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) v[k] += (k == q) ? x : 0.0;
+    }
     block_sum<Q>(v, red);
     for (int q = 0; q < Q; ++q) out[q] = v[q];
 }
@@ -1118,9 +1130,14 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                 const int ppar = (nbar - 1) & 1;  // parity of the round just published
                 const double *dinv = st.fine ? B.dinv_f : B.dinv_c;
                 hp_ok = 2 * H <= kThreads * kHP;
+                // per-call index math: hoisted out of the lane loop it would be
+                // held in spilled registers, and each reload would wait for the
+                // halo loads already in flight
+                int tid = threadIdx.x;
+                asm volatile("" : "+v"(tid));
 #pragma unroll
                 for (int u = 0; u < kHP; ++u) {
-                    const int q = threadIdx.x + u * kThreads;
+                    const int q = tid + u * kThreads;
                     hpr[u] = hpw[u] = hps[u] = hpd[u] = (Real)0;
                     if (hp_ok && q < 2 * H) {
                         const bool left = q < H;
@@ -1611,6 +1628,11 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                         }
                         LZ[left ? q : (b - lo) + (q - H)] = z;
                     }
+                    // all x loads done before the first x store: with stores in
+                    // flight the compiler can only wait for a load by draining
+                    // the stores too (loads and stores share one counter), i.e.
+                    // one store round trip per node
+                    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
                         const int id = a + tid + k * kThreads;
