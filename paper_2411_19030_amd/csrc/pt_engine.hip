@@ -1692,6 +1692,19 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                     for (int q0 = threadIdx.x; q0 < len; q0 += kThreads * kU) {
                         Real rv[kU], wv[kU], sv[kU], dv[kU], pv[kU];
                         double xv[kU];
+                        // D^{-1} is read unmasked at a clamped (always valid)
+                        // index and zeroed afterwards: a masked load needs a zero
+                        // default in its destination, so its address sits in
+                        // another register, and reusing that register for the
+                        // next node's address waited for every load in flight
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int q = q0 + u * kThreads;
+                            const int id = lo + q;
+                            const bool in = q < len && id >= 0 && id < C.Nn;
+                            const double d = dinv[min(max(id, 0), C.Nn - 1)];
+                            dv[u] = in ? (Real)d : (Real)0;
+                        }
 #pragma unroll
                         for (int u = 0; u < kU; ++u) {
                             const int q = q0 + u * kThreads;
@@ -1701,7 +1714,6 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                             rv[u] = in ? ldc(Rc + id) : 0.0;
                             wv[u] = in ? ldc(Wc + id) : 0.0;
                             sv[u] = (in && !first) ? ldc(Sc + id) : 0.0;
-                            dv[u] = in ? (Real)dinv[id] : (Real)0;
                             pv[u] = (own && !first) ? ldc(P + id) : 0.0;
                             xv[u] = own ? ldc(X + id) : 0.0;
                         }
@@ -1745,10 +1757,12 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                 }
                 block_sum<3>(loc, red);
                 const int par = nbar & 1;
-                if (threadIdx.x == 0) {
-                    stc(my_part(par) + 0, loc[0]);
-                    stc(my_part(par) + 1, loc[1]);
-                    stc(my_part(par) + 2, loc[2]);
+                // one partial per thread: one thread storing all three reused a
+                // register that an earlier store still read, and waited for it
+                if (threadIdx.x < 3) {
+                    const double v =
+                        threadIdx.x == 0 ? loc[0] : (threadIdx.x == 1 ? loc[1] : loc[2]);
+                    stc(my_part(par) + threadIdx.x, v);
                 }
                 ok = barrier(false);
                 if (!ok) break;
