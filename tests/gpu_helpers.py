@@ -52,7 +52,8 @@ def run_oracle(cfg: dict, rho: np.ndarray, guess=None):
                 lam=ad["lam"], grad=ad["grad"])
 
 
-def run_gpu(cfg: dict, rho: np.ndarray, guess=None, device="cuda", with_status=False):
+def run_gpu(cfg: dict, rho: np.ndarray, guess=None, device="cuda", with_status=False,
+            with_trace=False):
     import torch
 
     from paper_2411_19030_amd.cycle import Cycle
@@ -70,6 +71,9 @@ def run_gpu(cfg: dict, rho: np.ndarray, guess=None, device="cuda", with_status=F
                grad=res.grad.cpu().numpy())
     if with_status:
         out["status"] = cyc.status()
+    if with_trace:
+        from paper_2411_19030_amd._pt import pt_query_trace
+        out["trace"] = pt_query_trace(prob, cyc.ws)  # lanes of the last (adjoint) launch
     return out
 
 

@@ -45,6 +45,25 @@ def test_plt_cold_against_oracle(gpu, nx, ny, Nt, Ntau):
     _check(_cfg(nx=nx, ny=ny, n_steps=Nt, n_slices=Ntau), density_uniform_noise(nx, ny, nx * ny))
 
 
+def test_plt_single_lane_on_a_wide_group(gpu):
+    """One slice at 256 x 256: the planner spreads the single lane over more
+    than 170 workgroups, so a round's partial sums (three per workgroup)
+    outnumber the 512 threads that add them and some threads load two. At
+    k dt / h^2 of about 4e3, FP64 Jacobi-PCG cannot certify a true residual
+    of 1e-13 (one solve ended at 1.1e-13), so the solves run to 1e-12 and the
+    bar is 1e-9."""
+    cfg = _cfg(nx=256, ny=256, n_steps=16, n_slices=1, cg_rtol=1e-12)
+    rho = density_uniform_noise(256, 256, 31)
+    o = run_oracle(cfg, rho)
+    g = run_gpu(cfg, rho, with_status=True, with_trace=True)
+    nwg = max(r["nwg"] for r in g["trace"])
+    e = compare(g, o)
+    print(nwg, e, g["status"], flush=True)
+    assert nwg * 3 > 512
+    assert g["status"]["status"] == 0
+    assert max(e.values()) <= 1e-9
+
+
 def test_plt_warm_and_two_iterations(gpu):
     """Warm restart from the oracle's cold outputs on a perturbed design, with
     one and with two iterations per pass."""
