@@ -71,6 +71,17 @@ __device__ __forceinline__ float ldc(const float *p) {
 __device__ __forceinline__ void stc(float *p, float v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Marker of a Dirichlet node in an own-node residual slot of the streaming
+// rounds' LDS (D^{-1} is exactly 0 there, and the residual is 0): a NaN bit
+// pattern that is only ever stored and compared, never used in arithmetic.
+__device__ __forceinline__ double dir_tag(double) {
+    return __longlong_as_double(0x7FF8D1D1D1D1D1D1LL);
+}
+__device__ __forceinline__ float dir_tag(float) { return __int_as_float(0x7FC5D1D1); }
+__device__ __forceinline__ bool is_dir_tag(double v) {
+    return __double_as_longlong(v) == 0x7FF8D1D1D1D1D1D1LL;
+}
+__device__ __forceinline__ bool is_dir_tag(float v) { return __float_as_int(v) == 0x7FC5D1D1; }
 __device__ __forceinline__ int ldc(const int *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1732,7 +1743,10 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                                     stc(Sn + id, s_new);
                                     stc(X + id, xv[u] + al * (double)pn);
                                     stc(Rn + id, r_new);
-                                    LR[id - a] = r_new;
+                                    // Dirichlet nodes (D^{-1} = 0) carry the marker, so
+                                    // the stencil loop below needs no flag load: a load
+                                    // there would wait for the node stores in flight
+                                    LR[id - a] = dv[u] == (Real)0 ? dir_tag(r_new) : r_new;
                                 }
                             }
                         }
@@ -1741,14 +1755,16 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                     for (int id = a + threadIdx.x; id < b; id += kThreads) {
                         const int li2 = id - lo;
                         Real w = 0;
-                        if (!B.mask[id]) {
+                        const Real rraw = LR[id - a];
+                        const bool dir = is_dir_tag(rraw);
+                        if (!dir) {
                             const int j = id / C.W, i = id - j * C.W;
                             const CoefT<Real> aa = node_coef_t<Real>(C, LK, LC, ea, i, j, ms, 1.0);
                             w = apply_t<Real>(aa, LZ, li2, C.W);
                         }
                         stc(Wn + id, w);
                         const Real z = LZ[li2];
-                        const double rn = LR[id - a];
+                        const double rn = dir ? 0.0 : (double)rraw;
                         loc[0] += rn * z;
                         loc[1] += (double)z * (double)w;
                         loc[2] += rn * rn;
