@@ -177,7 +177,7 @@ __device__ __forceinline__ int flag_index(int kind, int n) { return kind * 4096 
 
 // Deterministic block sum of Q values; every thread receives the totals.
 template <int Q>
-__device__ void block_sum(double (&v)[Q], double *red) {
+__device__ __forceinline__ void block_sum(double (&v)[Q], double *red) {
     for (int q = 0; q < Q; ++q) {
         double x = v[q];
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -1685,8 +1685,14 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                     }
                 }
                 } else if (C.gmg) {
-                    ok = gmg_round(st, true, first, al, be, loc, 3);
+                    // its own array: passing loc's address keeps loc in scratch
+                    // memory in every round form, stored on every node
+                    double gl[3] = {0.0, 0.0, 0.0};
+                    ok = gmg_round(st, true, first, al, be, gl, 3);
                     if (!ok) break;
+                    loc[0] = gl[0];
+                    loc[1] = gl[1];
+                    loc[2] = gl[2];
                 } else {
                 const int cur = i0 & 1, nxt = cur ^ 1;
                 Real *Rc = Rb[cur], *Rn = Rb[nxt], *Wc = Wb[cur], *Wn = Wb[nxt];
