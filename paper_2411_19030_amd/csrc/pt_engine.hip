@@ -1706,16 +1706,17 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                     elem_window(C, a, b, ea, elen);
                     lds_sync();
                     stage_elems(B, ea, elen, LK, LC);
-                    for (int q0 = threadIdx.x; q0 < len; q0 += kThreads * kU) {
-                        Real rv[kU], wv[kU], sv[kU], dv[kU], pv[kU];
-                        double xv[kU];
+                    constexpr int kUW = 6;  // window nodes per thread and iteration
+                    for (int q0 = threadIdx.x; q0 < len; q0 += kThreads * kUW) {
+                        Real rv[kUW], wv[kUW], sv[kUW], dv[kUW], pv[kUW];
+                        double xv[kUW];
                         // D^{-1} is read unmasked at a clamped (always valid)
                         // index and zeroed afterwards: a masked load needs a zero
                         // default in its destination, so its address sits in
                         // another register, and reusing that register for the
                         // next node's address waited for every load in flight
 #pragma unroll
-                        for (int u = 0; u < kU; ++u) {
+                        for (int u = 0; u < kUW; ++u) {
                             const int q = q0 + u * kThreads;
                             const int id = lo + q;
                             const bool in = q < len && id >= 0 && id < C.Nn;
@@ -1723,7 +1724,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                             dv[u] = in ? (Real)d : (Real)0;
                         }
 #pragma unroll
-                        for (int u = 0; u < kU; ++u) {
+                        for (int u = 0; u < kUW; ++u) {
                             const int q = q0 + u * kThreads;
                             const int id = lo + q;
                             const bool in = q < len && id >= 0 && id < C.Nn;
@@ -1735,7 +1736,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                             xv[u] = own ? ldc(X + id) : 0.0;
                         }
 #pragma unroll
-                        for (int u = 0; u < kU; ++u) {
+                        for (int u = 0; u < kUW; ++u) {
                             const int q = q0 + u * kThreads;
                             const int id = lo + q;
                             if (q < len) {
