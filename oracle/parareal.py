@@ -83,14 +83,18 @@ def parareal_forward(d: Discretisation, iterations: int = 1, guess_T=None,
         GkT = None
         Gkth = None
     guess = (np.array(uT), np.array(uth))
-    trajs = None
+    # the intermediate slots of S take each F sweep's fine states as they are
+    # computed; only the last iteration's survive (Sec. 4.3)
+    S = np.zeros((P.n_steps, P.n_nodes))
     for _ in range(iterations):
-        FT, Fth, trajs = [], [], []
+        FT, Fth = [], []
         for n in range(Nt):
             T, th, tr = F_pri(d, uT[n], uth[n], n)
             FT.append(T)
             Fth.append(th)
-            trajs.append(tr)
+            for i in range(1, M):
+                S[M * n + i - 1] = tr[i - 1]
+            del tr
         if GkT is None:
             GkT, Gkth = [], []
             for n in range(Nt):
@@ -107,10 +111,7 @@ def parareal_forward(d: Discretisation, iterations: int = 1, guess_T=None,
             newth.append(gth + Fth[n] - Gkth[n])
         uT, uth = newT, newth
         GkT, Gkth = GnT, Gnth
-    S = np.zeros((P.n_steps, P.n_nodes))
     for n in range(Nt):
-        for i in range(1, M):
-            S[M * n + i - 1] = trajs[n][i - 1]
         S[M * (n + 1) - 1] = uT[n + 1]
     return dict(S=S, uT=np.array(uT), utheta=np.array(uth), Theta=uth[Nt],
                 guess=guess)

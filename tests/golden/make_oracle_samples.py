@@ -36,6 +36,26 @@ def sample_indices(seed: int, shape: tuple, count: int) -> np.ndarray:
     return idx
 
 
+def checkpoint_rows(n_steps: int, n_slices: int) -> np.ndarray:
+    """Rows of S[N_t][N_n] holding T_{Mn} (n = 1..N_tau) and T_{Mn+1} (n = 0..N_tau-1):
+    the states that checkpointed storage keeps."""
+    M = n_steps // n_slices
+    return np.concatenate([np.arange(M - 1, n_steps, M), np.arange(0, n_steps, M)])
+
+
+def sample_rows(seed: int, rows: np.ndarray, n_cols: int, count: int) -> np.ndarray:
+    """Seeded flat indices into S[N_t][n_cols] restricted to the given rows."""
+    rng = np.random.default_rng(seed)
+    r = rows[rng.integers(0, rows.size, count)]
+    c = rng.integers(0, n_cols, count)
+    return np.unique(r.astype(np.int64) * n_cols + c)
+
+
+# Workloads whose GPU runs keep only the checkpointed states: their S samples
+# are drawn from those rows.
+CHECKPOINTED = ("large_2048_512",)
+
+
 def main(name: str) -> str:
     w = workload(name)
     rho = workload_density(name)
@@ -62,7 +82,11 @@ def main(name: str) -> str:
     ]
     for key, arr, seed in (("S", S, 11), ("uT", uT, 12), ("lam", lam, 13), ("grad", grad, 14)):
         a = np.asarray(arr, dtype=np.float64)
-        idx = sample_indices(seed, a.shape, N_SAMPLES)
+        if key == "S" and name in CHECKPOINTED:
+            idx = sample_rows(seed, checkpoint_rows(w["n_steps"], w["n_slices"]), a.shape[1],
+                              N_SAMPLES)
+        else:
+            idx = sample_indices(seed, a.shape, N_SAMPLES)
         flat = a.reshape(-1)
         lines.append(f"{key}_idx " + " ".join(str(int(i)) for i in idx))
         lines.append(f"{key}_val " + " ".join(repr(float(flat[i])) for i in idx))

@@ -16,6 +16,9 @@ optimised design field is not given, so seeded densities stand in for it):
 * ``large_2048``        2048x2048, N_t=2048 in 128 slices, smooth field
 * ``large_law_512``     the large design's density law and solver at 512x512,
                         N_t=512 in 32 slices (small enough for the oracle)
+* ``large_2048_512``    the large design at 2048x2048 with N_t=512 in 32 slices
+                        (M=16 as in ``large_2048``; one oracle cycle fits the
+                        host's memory)
 * ``paper_100``         the paper's own test case (Sec. 5.1): 100x100 elements,
                         N_t=480, Table 1 materials (c-SIMP), q(t) of Eq. 5.1,
                         the Dirichlet patch at the centre tenth of the bottom
@@ -44,6 +47,10 @@ WORKLOADS = {
                        rtol=1e-10, precision="fp32_refine"),
     "large_law_512": dict(nx=512, ny=512, n_steps=512, n_slices=32, seed=4,
                           rtol=1e-10, precision="fp32_refine"),
+    # the large design at its full grid with a quarter of its steps (same
+    # M = 16): small enough for one oracle cycle in the test fixtures
+    "large_2048_512": dict(nx=2048, ny=2048, n_steps=512, n_slices=32, seed=4,
+                           rtol=1e-10, precision="fp32_refine"),
     # Table 1: k0 = 3, kmin = 0.03, c0 = 1, cmin = 0.5, pk = 3, pc = 2; p = 20
     "paper_100": dict(nx=100, ny=100, n_steps=480, n_slices=10, seed=5, rtol=1e-12,
                       precision="fp64", k0=3.0, kmin=0.03, pk=3.0, c0=1.0, cmin=0.5,
@@ -167,7 +174,7 @@ def workload(name: str) -> dict:
 
 def workload_density(name: str) -> np.ndarray:
     w = WORKLOADS[name]
-    if name in ("large_2048", "large_law_512"):
+    if name in ("large_2048", "large_law_512", "large_2048_512"):
         return density_gaussians(w["nx"], w["ny"], w["seed"])
     if name == "paper_100":
         return density_branches(w["nx"], w["ny"], w["seed"])
