@@ -20,8 +20,10 @@
  * Ownership: every array argument is a DEVICE pointer owned by the caller,
  * except the two fields of pt_problem marked HOST. The library allocates no
  * device memory: all scratch lives in the caller's workspace `ws`
- * (pt_workspace_bytes). It keeps no global state between calls; state that
- * flows from one call to the next of the same cycle lives in `ws`. Calls are
+ * (pt_workspace_bytes), or, for pt_cycle_noalloc only, in one static device
+ * array per GPU. Apart from that array it keeps no global state between
+ * calls; state that flows from one call to the next of the same cycle lives
+ * in `ws`. Calls are
  * stream-ordered and asynchronous, except where noted; calls that overlap on
  * the same `ws` race.
  *
@@ -46,10 +48,12 @@ enum {
     PT_OK = 0,
     PT_EINVAL = -1,   /* invalid argument (sizes, N_tau not dividing N_t, odd p, NULL, aliasing) */
     PT_ENOMEM = -2,   /* workspace smaller than pt_workspace_bytes()                              */
-    PT_EHIP = -3,     /* HIP runtime error (launch, copy, co-residency)                           */
+    PT_EHIP = -3,     /* HIP runtime error (launch, copy) or a device wait that timed out         */
     PT_ENOCONV = -4,  /* some CG solve stopped at max_iter; outputs were still written            */
     PT_EDOMAIN = -5,  /* non-finite input/result or Theta <= 0                                    */
-    PT_ESTATE = -6    /* call order violated (adjoint before forward, sensitivities before adjoint) */
+    PT_ESTATE = -6,   /* call order violated (adjoint before forward, sensitivities before adjoint) */
+    PT_ESIZE = -7     /* the problem does not fit: it needs more workspace than the static array   */
+                      /* of pt_cycle_noalloc, or a launch shape the device cannot hold co-resident */
 };
 
 /* Dirichlet node sets */
@@ -216,6 +220,33 @@ int pt_query_status(const void *ws, hipStream_t stream, pt_stats *out);
 
 /* Static string for a return code. */
 const char *pt_strerror(int code);
+
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one whole
+ * optimisation cycle -- pt_parareal_forward, pt_parareal_adjoint and
+ * pt_sensitivities with the arguments of those calls -- whose workspace is a
+ * static device array of PT_NOALLOC_WS_BYTES inside the library instead of a
+ * caller-owned one. The array exists once per GPU the library runs on and is
+ * held until the process ends; the call allocates and frees nothing.
+ *   guess_T, guess_theta, guess_lambda  as for the three calls (NULL = cold start)
+ *   S, uT_out, utheta_out, lambda_out,  outputs as for the three calls (uT_out,
+ *   Theta_out, dTheta_drho              utheta_out, lambda_out may be NULL)
+ *   stats_out   [1] DEVICE pt_stats, or NULL: the cycle's status and counters,
+ *               written stream-ordered at the end (what pt_query_status reports
+ *               after the adjoint and sensitivities of the three-call form)
+ * Returns PT_ESIZE when pt_workspace_bytes(prob) > PT_NOALLOC_WS_BYTES, other
+ * argument errors as the three calls do, all before anything is enqueued.
+ * Every call on one GPU shares that GPU's array and leaves its contents there;
+ * each call clears what must start at zero. Calls that overlap on one GPU
+ * (other streams, other host threads) race on the array.
+ * ------------------------------------------------------------------------ */
+#define PT_NOALLOC_WS_BYTES ((size_t)64 << 20)
+
+int pt_cycle_noalloc(const pt_problem *prob, const double *rho, const double *guess_T,
+                     const double *guess_theta, const double *guess_lambda, double *S,
+                     double *uT_out, double *utheta_out, double *lambda_out, double *Theta_out,
+                     double *dTheta_drho, pt_stats *stats_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Design-field front end (Sec. 2.1): chi -> chi_fil = H chi -> chi_phys = P(chi_fil),

@@ -16,7 +16,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpt.so")
 
-PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ENOCONV, PT_EDOMAIN, PT_ESTATE = 0, -1, -2, -3, -4, -5, -6
+PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ENOCONV, PT_EDOMAIN, PT_ESTATE, PT_ESIZE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+# bytes of the static per-GPU workspace of pt_cycle_noalloc (PT_NOALLOC_WS_BYTES)
+PT_NOALLOC_WS_BYTES = 64 << 20
 PT_BC = {"left_centre": 0, "bottom_centre": 1, "none": 2, "mask": 3}
 PT_FP64, PT_FP32_REFINE = 0, 1
 PT_JACOBI, PT_GMG = 0, 1
@@ -27,7 +30,7 @@ EXPORTS = ["pt_workspace_bytes", "pt_state_bytes", "pt_validate", "pt_parareal_f
            "pt_sensitivities", "pt_query_status", "pt_query_trace", "pt_strerror",
            "pt_batched_workspace_bytes", "pt_batch_default_tuning", "pt_parareal_batched",
            "pt_batched_status", "pt_autotune_batched", "pt_filter_validate",
-           "pt_filter_projection", "pt_filter_projection_backward"]
+           "pt_filter_projection", "pt_filter_projection_backward", "pt_cycle_noalloc"]
 
 
 class PtProblem(ctypes.Structure):
@@ -139,6 +142,8 @@ def load_library(path: str = LIB_PATH):
     lib.pt_filter_projection.restype = ctypes.c_int
     lib.pt_filter_projection_backward.argtypes = [FP, vp, vp, vp, vp, vp]
     lib.pt_filter_projection_backward.restype = ctypes.c_int
+    lib.pt_cycle_noalloc.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pt_cycle_noalloc.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -278,6 +283,27 @@ def pt_sensitivities(prob: Problem, rho, ws, dTheta_drho, stream=None, check: bo
     if check:
         _check(rc, "pt_sensitivities")
     return rc
+
+
+def pt_cycle_noalloc(prob: Problem, rho, guess_T, guess_theta, guess_lambda, S, uT_out,
+                     utheta_out, lambda_out, Theta_out, dTheta_drho, stats_out=None,
+                     stream=None, check: bool = True) -> int:
+    """One whole cycle on the library's static workspace (no allocation);
+    stats_out: optional device tensor of at least sizeof(pt_stats) bytes."""
+    c = prob.to_c()
+    rc = load_library().pt_cycle_noalloc(
+        ctypes.byref(c), _ptr(rho), _ptr(guess_T), _ptr(guess_theta), _ptr(guess_lambda),
+        _ptr(S), _ptr(uT_out), _ptr(utheta_out), _ptr(lambda_out), _ptr(Theta_out),
+        _ptr(dTheta_drho), _ptr(stats_out), _stream(stream))
+    if check:
+        _check(rc, "pt_cycle_noalloc")
+    return rc
+
+
+def stats_from_bytes(raw: bytes) -> dict:
+    """A pt_stats read back from device memory (e.g. stats_out of pt_cycle_noalloc)."""
+    st = PtStats.from_buffer_copy(raw[:ctypes.sizeof(PtStats)])
+    return {k: getattr(st, k) for k, _ in PtStats._fields_}
 
 
 LANE_KINDS = ["F_PRI", "GK_PRI", "SWEEP_PRI", "COLD_PRI", "F_ADJ", "GK_ADJ", "SWEEP_ADJ",

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -1281,6 +1282,43 @@ int coarse_mesh_adjoint(const pt_problem *prob, std::vector<EngineDesc> &hd, Eng
     return launch_check();
 }
 
+// Status and counters of a single-design workspace as a pt_stats (device).
+__global__ void k_write_stats(const Control *ctl, pt_stats *out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    out->status = ctl->status;
+    out->max_cg_iters = ctl->max_iters;
+    out->cg_iters_fine = (int64_t)ctl->iters_fine;
+    out->cg_iters_coarse = (int64_t)ctl->iters_coarse;
+    out->solves_fine = (int64_t)ctl->solves_fine;
+    out->solves_coarse = (int64_t)ctl->solves_coarse;
+    out->max_rel_residual = __longlong_as_double((long long)ctl->max_relres_bits);
+}
+
+// The workspace of pt_cycle_noalloc: one copy per GPU, held until the process
+// ends. In host code `scratch` is only a host-side stand-in for the device
+// array; kernels receive the device address hipGetSymbolAddress returns for
+// the current device, taken once per device and kept below.
+static __device__ __align__(256) unsigned char scratch[PT_NOALLOC_WS_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_workspace(void **out) {
+    int dev = 0;
+    PT_TRY(hip_ok(hipGetDevice(&dev)));
+    if (dev < 0 || dev >= kMaxDevices) return PT_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        PT_TRY(hip_ok(hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch))));
+        if (!ptr) return PT_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1306,6 +1344,9 @@ const char *pt_strerror(int code) {
         case PT_ENOCONV: return "a CG solve reached max_iter";
         case PT_EDOMAIN: return "non-finite input or result, or Theta <= 0";
         case PT_ESTATE: return "call order violated";
+        case PT_ESIZE:
+            return "problem too large: more workspace than the static array of "
+                   "pt_cycle_noalloc, or a launch the device cannot hold co-resident";
         default: return "unknown error";
     }
 }
@@ -1702,6 +1743,30 @@ int pt_autotune_batched(int n, const pt_problem *probs, const double *const *rho
     (void)hipEventDestroy(e1);
     *best = cur;
     if (best_ms) *best_ms = best_t;
+    return PT_OK;
+}
+
+int pt_cycle_noalloc(const pt_problem *prob, const double *rho, const double *guess_T,
+                     const double *guess_theta, const double *guess_lambda, double *S,
+                     double *uT_out, double *utheta_out, double *lambda_out, double *Theta_out,
+                     double *dTheta_drho, pt_stats *stats_out, hipStream_t stream) {
+    if (!valid_problem(prob)) return PT_EINVAL;
+    if (!rho || !S || !Theta_out || !dTheta_drho) return PT_EINVAL;
+    if (layout(prob).total > PT_NOALLOC_WS_BYTES) return PT_ESIZE;
+    void *ws = nullptr;
+    PT_TRY(noalloc_workspace(&ws));
+    const size_t bytes = PT_NOALLOC_WS_BYTES;
+    PT_TRY(pt_parareal_forward(prob, rho, guess_T, guess_theta, S, uT_out, utheta_out, Theta_out,
+                               ws, bytes, stream));
+    PT_TRY(pt_parareal_adjoint(prob, rho, S, Theta_out, guess_lambda, lambda_out, ws, bytes,
+                               stream));
+    PT_TRY(pt_sensitivities(prob, rho, ws, bytes, dTheta_drho, stream));
+    if (stats_out) {
+        // the status block sits at offset 0 of a single-design workspace
+        hipLaunchKernelGGL(k_write_stats, dim3(1), dim3(64), 0, stream,
+                           static_cast<const Control *>(ws), stats_out);
+        PT_TRY(launch_check());
+    }
     return PT_OK;
 }
 

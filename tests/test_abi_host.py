@@ -227,3 +227,17 @@ def test_filter_argument_errors_before_any_device_work(lib):
     assert lib.pt_filter_projection_backward(ctypes.byref(f), 0x100000, 0x200000, 0x300000,
                                              0x300000 + 8, None) == _pt.PT_EINVAL
 
+
+
+def test_cycle_noalloc_host_errors(lib):
+    """pt_cycle_noalloc rejects an invalid problem and one whose workspace
+    exceeds the static array before touching the device."""
+    fake = ctypes.c_void_p(16)
+    args = [fake, None, None, None, fake, None, None, None, fake, fake, None, None]
+    bad = base(pnorm=7).to_c()
+    assert lib.pt_cycle_noalloc(ctypes.byref(bad), *args) == _pt.PT_EINVAL
+    big = base(nx=256, ny=256, n_steps=512, n_slices=32)
+    assert _pt.pt_workspace_bytes(big) > _pt.PT_NOALLOC_WS_BYTES
+    c = big.to_c()
+    assert lib.pt_cycle_noalloc(ctypes.byref(c), *args) == _pt.PT_ESIZE
+    assert b"static" in lib.pt_strerror(_pt.PT_ESIZE)
