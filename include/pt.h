@@ -4,8 +4,8 @@
  *
  * One optimisation cycle is three calls on one HIP stream:
  *   pt_parareal_forward   modified Parareal for (T, theta)            Sec. 4.3-4.4, Alg. 1
- *   pt_parareal_adjoint   time-reversed vanilla Parareal for lambda   Sec. 4.4, Alg. 2, Eq. 4.9
- *   pt_sensitivities      grad Theta = g_1                            Eq. 4.8, Eq. 4.10
+ *   pt_parareal_adjoint   time-reversed vanilla Parareal for lambda   Sec. 4.4, Alg. 2, Eq. 4.14
+ *   pt_sensitivities      grad Theta = g_1                            Eq. 4.7, Eq. 4.16
  *
  * Discretisation (Sec. 2.2): unit square, nx x ny rectangular bilinear (Q1)
  * elements, hx = 1/nx, hy = 1/ny, out-of-plane depth 1, element-wise constant
@@ -82,7 +82,7 @@ typedef struct pt_problem {
     double t_final;            /* t_T > 0; dt = t_T / n_steps, dtau = t_T / n_slices              */
     int32_t n_steps;           /* N_t >= 1                                                        */
     int32_t n_slices;          /* N_tau >= 1, must divide N_t; M = N_t / N_tau      (Sec. 4.2)    */
-    int32_t pnorm;             /* p, even >= 2                                      (Eq. 2.9)     */
+    int32_t pnorm;             /* p, even >= 2                                      (Eq. 2.11)     */
     int32_t iterations;        /* Parareal iterations per pass, >= 1 (1 = one-shot, Alg. 3)       */
     double cg_rtol;            /* stop when ||b - A x||_2 <= cg_rtol ||b||_2, per system, > 0     */
     int32_t max_iter;          /* CG iteration cap per solve, >= 1                                */
@@ -127,7 +127,7 @@ size_t pt_state_bytes(const pt_problem *prob);
 
 /*
  * Primal pass: Parareal for u_n = (T_{Mn}, theta_{Mn}), n = 0..N_tau (Sec. 4.4,
- * Eq. 4.2 correction applied to T and theta; G_pri = Alg. 1 with dt -> dtau,
+ * Eq. 4.10 correction applied to T and theta; G_pri = Alg. 1 with dt -> dtau,
  * N_t -> N_tau, load at tau_{n+1}).
  *   rho          [N_e]              design, finite, >= 0 (rho^p with non-integer p needs rho >= 0)
  *   guess_T      [N_tau+1][N_n]     warm-restart guess u^k (Alg. 3), or NULL: cold start from the
@@ -167,7 +167,7 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
 
 /*
  * Adjoint pass: reversed Parareal for v_n = (lambda_{Mn+1}, g_{Mn+1}), v_{N_tau} = 0
- * (Sec. 4.4, Eq. 4.9; H_adj = Alg. 2 with source Theta^{1-p}/N_e T_n^{o(p-1)}, Eq. 4.6;
+ * (Sec. 4.4, Eq. 4.14; H_adj = Alg. 2 with source Theta^{1-p}/N_e T_n^{o(p-1)}, Eq. 4.6;
  * G_adj = Alg. 2 with dt -> dtau, N_t -> N_tau, n+-1 -> n+-M, so the coarse step from
  * v_n uses source and T at fine index m = M(n-1)+1 and T_{m-M} (T_0 = 0 if m-M < 0)).
  *   S, Theta       from pt_parareal_forward of the same cycle (unchanged since)
@@ -185,7 +185,7 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
  *
  * With propagator == PT_COARSE_MESH: G_adj(lambda, n) = P x, x the coarse
  * adjoint step from R lambda whose source is P^T of the fine source of Eq. 4.6
- * at T_m (m = M(n-1)+1); the sensitivity increment of Eq. 4.10 uses P x on
+ * at T_m (m = M(n-1)+1); the sensitivity increment of Eq. 4.16 uses P x on
  * the fine elements.
  */
 int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double *S,
@@ -196,7 +196,7 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
  * grad Theta = g-part of v_0 (Sec. 4.4 step 4); with PT_PLT the fine terms
  * of Theta~ are summed and scaled by Theta^{1-p}/p (Eq. 7.7):
  *   dTheta_drho[e] = -(1/N_t) sum_fine lambda_j,e^T (dC/drho_e (T_j - T_{j-1})/dt + dK/drho_e T_j)
- *                    - (1/N_tau) (coarse-correction terms)          (Eq. 4.8, Eq. 4.10)
+ *                    - (1/N_tau) (coarse-correction terms)          (Eq. 4.7, Eq. 4.16)
  *   dTheta_drho    [N_e] out
  */
 int pt_sensitivities(const pt_problem *prob, const double *rho, const void *ws,

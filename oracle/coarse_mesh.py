@@ -25,7 +25,7 @@ reading used here. With a coarsening factor f (nx and ny divisible by f):
   of Eq. 4.6 at T_m (m = M(n-1)+1 as in G_adj) carried to the coarse mesh by
   P^T, the transfer that also gives the coarse load (P^T f); then
   lambda' = P lambda_c' and g' = g - (1/N_tau) lambda'^T (dC (T_m - T_{m-M})/dtau
-  + dK T_m) on the fine elements (Eq. 4.10 with the coarse step's output).
+  + dK T_m) on the fine elements (Eq. 4.16 with the coarse step's output).
 
 The objective and the adjoint source are nodal sums over the fine nodes, so
 they are evaluated on the fine field (the coarse nodes with their own count

@@ -140,7 +140,7 @@ class Problem:
 
     @property
     def M(self) -> int:
-        """Coarsening factor M = N_t / N_tau (Sec. 3.2); must be an integer."""
+        """Coarsening factor M = N_t / N_tau (Sec. 4.2); must be an integer."""
         if self.n_steps % self.n_slices:
             raise ValueError("N_tau must divide N_t")
         return self.n_steps // self.n_slices
@@ -230,7 +230,7 @@ class Discretisation:
 
     def element_term(self, lam: np.ndarray, T: np.ndarray, T_prev: np.ndarray,
                      step: float) -> np.ndarray:
-        """Per-element lambda^T (dC/drho_e (T - T_prev)/step + dK/drho_e T) (Eq. 4.8)."""
+        """Per-element lambda^T (dC/drho_e (T - T_prev)/step + dK/drho_e T) (Eq. 4.7)."""
         le = lam[self.conn]
         te = T[self.conn]
         de = (T - T_prev)[self.conn] / step

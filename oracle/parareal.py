@@ -9,7 +9,7 @@ Primal (Sec. 4.2-4.4): u_n = (T_{Mn}, theta_{Mn}), u_0 = 0.
   intermediate state (the modification of Sec. 4.3).
   G_pri(u_n) is Alg. 1 once with dtau, N_tau and index n-1 replaced by n-M,
   so its load is q at tau_{n+1}.
-  Correction (Eq. 4.2): u^{k+1}_{n+1} = G(u^{k+1}_n) + F(u^k_n) - G(u^k_n),
+  Correction (Eq. 4.10): u^{k+1}_{n+1} = G(u^{k+1}_n) + F(u^k_n) - G(u^k_n),
   applied to T and to theta alike.
   The result S keeps the fine intermediate states of the last F sweep (from
   the uncorrected u^k_n) and puts the corrected T at the coarse points;
@@ -21,7 +21,7 @@ Adjoint (Sec. 4.4): v_n = (lambda_{Mn+1}, g_{Mn+1}), v_{N_tau} = 0.
   starting from lambda_{Mn+1} it produces lambda_m with m = M(n-1)+1, with
   source and T taken at fine index m and T_{m-M} in the capacity term
   (clamped to T_0 = 0 when m - M < 0).
-  Reversed correction (Eq. 4.9): v^{k+1}_{n-1} = G(v^{k+1}_n) + F(v^k_n) - G(v^k_n).
+  Reversed correction (Eq. 4.14): v^{k+1}_{n-1} = G(v^{k+1}_n) + F(v^k_n) - G(v^k_n).
   grad Theta = g-part of v_0 (Sec. 4.4, step 4).
 
 Initial guesses: either given arrays (a warm restart, Alg. 3) or the coarse

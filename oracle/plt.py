@@ -4,7 +4,7 @@ form of Sec. 7 (oracle, FP64, CPU).
 TEST INFRASTRUCTURE: used only by tests, the smoke check and the bench's CPU
 baseline.
 
-With G_pri = G_adj = 0 (Eq. 7.1) the corrections of Eq. 4.2 and Eq. 4.9
+With G_pri = G_adj = 0 (Eq. 7.1) the corrections of Eq. 4.10 and Eq. 4.14
 reduce to (Eq. 7.2)
     u^{k+1}_{n+1} = F_pri(u^k_n),      v^{k+1}_{n-1} = F_adj(v^k_n),
 with u^{k+1}_0 = 0 and v^{k+1}_{N_tau} = 0. As in the PLT method, u and v hold
@@ -12,7 +12,7 @@ only the states T_{Mn} and lambda_{Mn+1}. The objective is the modified one of
 Eq. 7.4,
     Theta~ = Theta^p = sum_{j=1}^{N_t} ||T_j||_p^p / (N_t N_e),
 evaluated from the fine trajectories after the pass. Its adjoint source is
-p/N_e T_j^{o(p-1)} (Eq. 7.5) and its sensitivity sum is that of Eq. 4.10 with
+p/N_e T_j^{o(p-1)} (Eq. 7.5) and its sensitivity sum is that of Eq. 4.16 with
 this source. Theta and grad Theta follow from Eq. 7.6-7.7:
     Theta = Theta~^{1/p},      grad Theta = Theta^{1-p}/p grad Theta~.
 

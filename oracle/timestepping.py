@@ -9,7 +9,7 @@ baseline.
   (dtau, N_tau) it is the coarse propagator G_pri.
 * ``h_adj``: Algorithm 2 -- one backward-Euler step of the adjoint terminal
   value problem (Eq. 4.5b with the source of Eq. 4.6) followed by the
-  cumulative sensitivity update (Eq. 4.10). With (dtau, N_tau) and indices
+  cumulative sensitivity update (Eq. 4.16). With (dtau, N_tau) and indices
   shifted by M it is G_adj.
 * ``forward_sequential`` / ``adjoint_sequential``: the reference method of
   Sec. 5.2 (H applied sequentially over all N_t steps), which Alg. 3 also uses
@@ -23,7 +23,7 @@ from .fem import Discretisation
 
 
 def pnorm_p(T: np.ndarray, p: int) -> float:
-    """||T||_p^p = sum_i T_i^p for even p (Eq. 2.9), over every node."""
+    """||T||_p^p = sum_i T_i^p for even p (Eq. 2.11), over every node."""
     return float(np.sum(T ** p))
 
 

@@ -1,6 +1,6 @@
 """Differentiable one-shot Parareal objective: a torch.autograd.Function whose
 forward is pt_parareal_forward and whose backward is the hand-written adjoint
-pass (pt_parareal_adjoint) plus pt_sensitivities (Sec. 4.1, Eq. 4.8; Sec. 4.4).
+pass (pt_parareal_adjoint) plus pt_sensitivities (Sec. 4.1, Eq. 4.7; Sec. 4.4).
 
 `OneShotParareal` keeps the warm-restart state of Alg. 3: every call uses the
 previous call's corrected coarse states u_n and adjoint states v_n as the

@@ -14,9 +14,9 @@
 // slice in one engine launch, then on the coarse mesh: the batched steps
 // G(R u^k_n) (one workgroup each), the sequential correction sweep (one
 // workgroup), and the corrected fine states F_n + P(G(u^{k+1}_n) - G(u^k_n))
-// (Eq. 4.2 / Eq. 4.9 with both coarse outputs prolonged by the same linear P).
+// (Eq. 4.10 / Eq. 4.14 with both coarse outputs prolonged by the same linear P).
 // The sensitivity part of the reversed correction is linear in the coarse
-// output difference; it is summed per fine element after the sweep (Eq. 4.10).
+// output difference; it is summed per fine element after the sweep (Eq. 4.16).
 //
 // Each coarse solve is Jacobi-preconditioned CG (Hestenes-Stiefel form) run by
 // one workgroup of 1024 threads, with the true residual checked at the end;
@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(kCT) k_cm_batched(const EngineDesc *__restrict
 // The sequential coarse chain on one workgroup (vectors in LDS, else slot 0).
 // cold = 1: the cold sweep u^0_{n+1} = G(u^0_n) from u_0 = 0 (primal) or
 // v^0_{n-1} = G(v^0_n) from v_{N_tau} = 0 (adjoint), written to Gk.
-// cold = 0: the correction sweep of Eq. 4.2 / Eq. 4.9 on the coarse mesh,
+// cold = 0: the correction sweep of Eq. 4.10 / Eq. 4.14 on the coarse mesh,
 //   hat u_{n+1} = G(hat u_n) + R F_n - G(R u^k_n), hat u_1 = R F_0,
 // with G(hat u_n) written to Gn (and the theta chain to Gn_th, out_th); the
 // primal reads F_n from S row M(n+1) and theta(F_n) from F_th, the adjoint
@@ -542,7 +542,7 @@ __global__ void k_cm_correct(const EngineDesc *__restrict__ D, CoarseMesh M, int
 
 // accG_e = sum_{n=1}^{N_tau-1} lambda_n^T (dC (T_m - T_{m-M})/dtau + dK T_m) on
 // fine element e, lambda_n = P(Gn[n] - Gk[n]), m = M(n-1)+1 (T_{m-M} = 0 when
-// m - M < 1): the coarse-correction part of the summed Eq. 4.10.
+// m - M < 1): the coarse-correction part of the summed Eq. 4.16.
 __global__ void k_cm_sens(const EngineDesc *__restrict__ D, CoarseMesh M) {
     const Consts &C = D->C;
     const Bufs &B = D->B;

@@ -4,7 +4,7 @@
 // A *lane* is a sequence of backward-Euler solves (C/delta + K) x = b: the
 // fine propagator of one time slice (M steps of Alg. 1 or Alg. 2 with dt), one
 // batched coarse step G(u^k_n), the cold coarse sweep, or the sequential
-// correction sweep (Eq. 4.2 / Eq. 4.9). A *group* of workgroups runs a queue of
+// correction sweep (Eq. 4.10 / Eq. 4.14). A *group* of workgroups runs a queue of
 // lanes one after another. All groups of a pass run concurrently; a lane waits
 // on a device flag only where the method has a true data dependence (the
 // sweep step n needs F_n and G(u^k_n); a cold-started slice needs its coarse
@@ -592,7 +592,7 @@ struct Ctl {
 };
 
 // Per-element sensitivity term lambda^T (dk K0 T + dc C0 (T - Tp)/delta) of the
-// element whose lower-left node is id (Eq. 4.8 summand for one element).
+// element whose lower-left node is id (Eq. 4.7 summand for one element).
 // States written earlier in the same launch by other workgroups (recomputed
 // checkpoint states, coh = true) are read with device-coherent loads.
 __device__ __forceinline__ double ld_state(const double *row, int q, bool coh) {
@@ -2061,7 +2061,7 @@ __global__ void k_finalize_adj(const EngineDesc *__restrict__ D) {
     }
 }
 
-// grad_e = -(1/N_t) sum_n acc[n][e] - (1/N_tau) accG[e]  (Eq. 4.10 summed,
+// grad_e = -(1/N_t) sum_n acc[n][e] - (1/N_tau) accG[e]  (Eq. 4.16 summed,
 // Sec. 4.4 step 4), times Theta^{1-p}/p with G = 0 (Eq. 7.7); blockIdx.y = design.
 __global__ void k_sensitivities(const EngineDesc *__restrict__ D) {
     const EngineDesc &E = D[blockIdx.y];

@@ -93,7 +93,7 @@ def grad_scale(theta: float, grad: np.ndarray) -> float:
     has a norm of the order Theta/sqrt(N_e); the workloads here have norms of
     0.5-1 times that scale. Where the gradient vanishes analytically (no
     Dirichlet node: a uniform temperature field, and K0 1 = 0 kills every
-    sensitivity term of Eq. 4.8) both sides return round-off of the solves, so
+    sensitivity term of Eq. 4.7) both sides return round-off of the solves, so
     the floor 1e-2 Theta/sqrt(N_e) turns the test into an absolute one on that
     natural scale."""
     n = float(np.linalg.norm(grad))

@@ -3,7 +3,7 @@ Parareal passes against closed forms, invariants and finite differences.
 
 Pin map (oracle function -> tests):
 * h_pri / forward_sequential: uniform closed form (P1), modal closed form (P2),
-  1-element objective; Eq. 2.7b, Eq. 2.9, Alg. 1.
+  1-element objective; Eq. 2.7b, Eq. 2.11, Alg. 1.
 * h_adj / adjoint_sequential: all-at-once transpose solve with an autograd
   objective gradient (P5), one-element closed form (P1), finite differences (P6).
 * element_term: finite differences with c-SIMP active (P6), one-element
@@ -47,7 +47,7 @@ def test_uniform_closed_form_sequential(timevar):
     S, th = O.forward_sequential(d)
     for n in range(1, Nt + 1):
         assert np.allclose(S[n - 1], _uniform_T(qf, P.dt, 1.3, n), rtol=1e-12, atol=1e-15)
-    # Theta from Eq. 2.9: (1/(N_t N_e) sum_j N_n T_j^p)^(1/p)
+    # Theta from Eq. 2.11: (1/(N_t N_e) sum_j N_n T_j^p)^(1/p)
     tp = sum(P.n_nodes * _uniform_T(qf, P.dt, 1.3, j) ** p for j in range(1, Nt + 1))
     assert th[-1] == pytest.approx((tp / (Nt * P.n_elem)) ** (1 / p), rel=1e-13)
 
