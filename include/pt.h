@@ -310,7 +310,9 @@ typedef struct pt_batch_tuning {
     int32_t sweep_groups;  /* sweep groups, >= 1                                              */
     int32_t resident;      /* 1: vectors held in registers (every design's tile must fit)   */
     int32_t grid;          /* workgroups of the launch, 0 = as many as are co-resident        */
-    int32_t reserved[3];
+    int32_t tile_max;      /* streaming (resident = 0): largest node tile a workgroup stages  */
+                           /* per pass, 256..16384, or 0 for the built-in 4096               */
+    int32_t reserved[2];
 } pt_batch_tuning;
 
 /* Workspace bytes of a batch of n designs; 0 if any problem is invalid, the
@@ -342,14 +344,22 @@ int pt_parareal_batched(int n, const pt_problem *probs, const double *const *rho
 int pt_batched_status(int n, const pt_problem *probs, const void *ws, hipStream_t stream,
                       pt_stats *out /* [n] */);
 
-/* Times whole warm cycles of this batch for a set of worker shapes (coordinate
- * descent over fine_wgs, sweep_wgs and sweep_groups, starting from the
- * defaults) and returns the fastest. Synchronous; runs one cold cycle first,
- * leaves ws holding a valid warm state and the outputs of the last cycle. */
+/* Picks the launch shape of this batch by timing whole warm cycles: a
+ * coordinate descent, two passes from the defaults, over resident vs
+ * streaming vectors, fine_wgs, sweep_wgs, sweep_groups and the streaming
+ * tile_max. Synchronous. It runs one cold cycle first; every timed cycle then
+ * restarts from that cycle's solution, which stays in ws as the warm state
+ * (the timed cycles do not replace it). A shape's time is the median of three
+ * cycles; shapes the batch cannot use, or whose cycle reports any device-side
+ * problem (PT_ENOCONV included), are skipped. Leaves the outputs of the last
+ * timed cycle.
+ *   best, best_ms   the fastest shape and its time
+ *   default_ms      may be NULL: the time of the built-in shape, from the same
+ *                   state (so best_ms <= default_ms) */
 int pt_autotune_batched(int n, const pt_problem *probs, const double *const *rho,
                         double *Theta_out, double *const *dTheta_drho, void *ws,
                         size_t ws_bytes, hipStream_t stream, pt_batch_tuning *best,
-                        double *best_ms);
+                        double *best_ms, double *default_ms);
 
 #ifdef __cplusplus
 }

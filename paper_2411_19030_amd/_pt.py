@@ -63,17 +63,18 @@ class PtBatchTuning(ctypes.Structure):
     _fields_ = [
         ("fine_wgs", ctypes.c_int32), ("sweep_wgs", ctypes.c_int32),
         ("sweep_groups", ctypes.c_int32), ("resident", ctypes.c_int32),
-        ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+        ("grid", ctypes.c_int32), ("tile_max", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
+    KEYS = ("fine_wgs", "sweep_wgs", "sweep_groups", "resident", "grid", "tile_max")
 
     def as_dict(self) -> dict:
-        return dict(fine_wgs=self.fine_wgs, sweep_wgs=self.sweep_wgs,
-                    sweep_groups=self.sweep_groups, resident=self.resident, grid=self.grid)
+        return {k: getattr(self, k) for k in self.KEYS}
 
     @staticmethod
     def from_dict(d: dict) -> "PtBatchTuning":
         t = PtBatchTuning()
-        for k in ("fine_wgs", "sweep_wgs", "sweep_groups", "resident", "grid"):
+        for k in PtBatchTuning.KEYS:
             setattr(t, k, int(d.get(k, 0)))
         return t
 
@@ -133,6 +134,7 @@ def load_library(path: str = LIB_PATH):
     lib.pt_batched_status.argtypes = [ctypes.c_int, P, vp, vp, ctypes.POINTER(PtStats)]
     lib.pt_batched_status.restype = ctypes.c_int
     lib.pt_autotune_batched.argtypes = [ctypes.c_int, P, pp, vp, pp, vp, ctypes.c_size_t, vp, TP,
+                                        ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]
     lib.pt_autotune_batched.restype = ctypes.c_int
     FP = ctypes.POINTER(PtFilter)
@@ -240,6 +242,51 @@ def _check(rc: int, where: str):
         raise PtError(rc, where)
 
 
+def _check_tensors(where: str, specs, raw=()):
+    """Raise ValueError unless every given tensor can be handed to the library.
+
+    specs: (tensor or None, name, numel) with numel None for "any size";
+    None tensors (optional arguments) are skipped. Each tensor must be a
+    contiguous torch.float64 tensor of exactly numel elements; `raw` lists
+    (tensor or None, name) byte buffers such as the workspace, of any dtype
+    and contiguous. All of them must live on one GPU. Dtype, layout and size
+    are checked for every argument before devices."""
+    import torch
+    present = []
+    for t, name, numel in specs:
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{where}: {name} must be a torch tensor, got {type(t).__name__}")
+        if t.dtype != torch.float64:
+            raise ValueError(f"{where}: {name} has dtype {t.dtype}, expected torch.float64")
+        if not t.is_contiguous():
+            raise ValueError(f"{where}: {name} is not contiguous")
+        if numel is not None and t.numel() != numel:
+            raise ValueError(f"{where}: {name} has {t.numel()} elements, expected {numel}")
+        present.append((t, name))
+    for t, name in raw:
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor) or not t.is_contiguous():
+            raise ValueError(f"{where}: {name} must be a contiguous torch tensor")
+        present.append((t, name))
+    dev = None
+    for t, name in present:
+        if not t.is_cuda:
+            raise ValueError(f"{where}: {name} is on {t.device}, expected a GPU tensor")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise ValueError(f"{where}: {name} is on {t.device}, the other arguments on {dev}")
+
+
+def _sizes(prob: "Problem") -> dict:
+    """Element counts of the arrays of one problem (include/pt.h)."""
+    Nn, Nt1 = prob.n_nodes, prob.n_slices + 1
+    return dict(Ne=prob.n_elem, U=Nt1 * Nn, th=Nt1, S=pt_state_bytes(prob) // 8)
+
+
 def pt_validate(prob: Problem) -> int:
     return load_library().pt_validate(ctypes.byref(prob.to_c()))
 
@@ -254,6 +301,11 @@ def pt_state_bytes(prob: Problem) -> int:
 
 def pt_parareal_forward(prob: Problem, rho, guess_T, guess_theta, S, uT_out, utheta_out,
                         Theta_out, ws, stream=None, check: bool = True) -> int:
+    z = _sizes(prob)
+    _check_tensors("pt_parareal_forward", [
+        (rho, "rho", z["Ne"]), (guess_T, "guess_T", z["U"]), (guess_theta, "guess_theta", z["th"]),
+        (S, "S", z["S"]), (uT_out, "uT_out", z["U"]), (utheta_out, "utheta_out", z["th"]),
+        (Theta_out, "Theta_out", 1)], [(ws, "ws")])
     c = prob.to_c()
     rc = load_library().pt_parareal_forward(
         ctypes.byref(c), _ptr(rho), _ptr(guess_T), _ptr(guess_theta), _ptr(S), _ptr(uT_out),
@@ -266,6 +318,11 @@ def pt_parareal_forward(prob: Problem, rho, guess_T, guess_theta, S, uT_out, uth
 
 def pt_parareal_adjoint(prob: Problem, rho, S, Theta, guess_lambda, lambda_out, ws,
                         stream=None, check: bool = True) -> int:
+    z = _sizes(prob)
+    _check_tensors("pt_parareal_adjoint", [
+        (rho, "rho", z["Ne"]), (S, "S", z["S"]), (Theta, "Theta", 1),
+        (guess_lambda, "guess_lambda", z["U"]), (lambda_out, "lambda_out", z["U"])],
+                   [(ws, "ws")])
     c = prob.to_c()
     rc = load_library().pt_parareal_adjoint(
         ctypes.byref(c), _ptr(rho), _ptr(S), _ptr(Theta), _ptr(guess_lambda), _ptr(lambda_out),
@@ -276,6 +333,10 @@ def pt_parareal_adjoint(prob: Problem, rho, S, Theta, guess_lambda, lambda_out, 
 
 
 def pt_sensitivities(prob: Problem, rho, ws, dTheta_drho, stream=None, check: bool = True) -> int:
+    z = _sizes(prob)
+    _check_tensors("pt_sensitivities", [(rho, "rho", z["Ne"]),
+                                        (dTheta_drho, "dTheta_drho", z["Ne"])],
+                   [(ws, "ws")])
     c = prob.to_c()
     rc = load_library().pt_sensitivities(
         ctypes.byref(c), _ptr(rho), _ptr(ws), ws.numel() * ws.element_size(), _ptr(dTheta_drho),
@@ -290,6 +351,15 @@ def pt_cycle_noalloc(prob: Problem, rho, guess_T, guess_theta, guess_lambda, S, 
                      stream=None, check: bool = True) -> int:
     """One whole cycle on the library's static workspace (no allocation);
     stats_out: optional device tensor of at least sizeof(pt_stats) bytes."""
+    z = _sizes(prob)
+    _check_tensors("pt_cycle_noalloc", [
+        (rho, "rho", z["Ne"]), (guess_T, "guess_T", z["U"]), (guess_theta, "guess_theta", z["th"]),
+        (guess_lambda, "guess_lambda", z["U"]), (S, "S", z["S"]), (uT_out, "uT_out", z["U"]),
+        (utheta_out, "utheta_out", z["th"]), (lambda_out, "lambda_out", z["U"]),
+        (Theta_out, "Theta_out", 1), (dTheta_drho, "dTheta_drho", z["Ne"])],
+                   [(stats_out, "stats_out")])
+    if stats_out is not None and stats_out.numel() * stats_out.element_size() < ctypes.sizeof(PtStats):
+        raise ValueError("pt_cycle_noalloc: stats_out is smaller than pt_stats")
     c = prob.to_c()
     rc = load_library().pt_cycle_noalloc(
         ctypes.byref(c), _ptr(rho), _ptr(guess_T), _ptr(guess_theta), _ptr(guess_lambda),
@@ -360,6 +430,16 @@ def _ptr_array(tensors):
     return (ctypes.c_void_p * len(tensors))(*[_ptr(t) for t in tensors])
 
 
+def _check_batch(where, probs, rhos, Theta_out, grads, ws):
+    n = len(probs)
+    if len(rhos) != n or len(grads) != n:
+        raise ValueError(f"{where}: {n} problems, {len(rhos)} densities, {len(grads)} gradients")
+    specs = [(Theta_out, "Theta_out", n)]
+    for k, p in enumerate(probs):
+        specs += [(rhos[k], f"rho[{k}]", p.n_elem), (grads[k], f"dTheta_drho[{k}]", p.n_elem)]
+    _check_tensors(where, specs, [(ws, "ws")])
+
+
 def pt_batched_workspace_bytes(probs) -> int:
     arr = _probs_array(probs)
     return int(load_library().pt_batched_workspace_bytes(len(probs), arr))
@@ -373,6 +453,7 @@ def pt_batch_default_tuning(n: int) -> dict:
 
 def pt_parareal_batched(probs, rhos, warm: bool, tuning: Optional[dict], Theta_out, grads, ws,
                         stream=None, check: bool = True) -> int:
+    _check_batch("pt_parareal_batched", probs, rhos, Theta_out, grads, ws)
     arr = _probs_array(probs)
     t = PtBatchTuning.from_dict(tuning) if tuning is not None else None
     rc = load_library().pt_parareal_batched(
@@ -393,14 +474,16 @@ def pt_batched_status(probs, ws, stream=None) -> list:
 
 
 def pt_autotune_batched(probs, rhos, Theta_out, grads, ws, stream=None) -> tuple:
+    """(best shape, its ms, the built-in shape's ms), timed from one state."""
+    _check_batch("pt_autotune_batched", probs, rhos, Theta_out, grads, ws)
     arr = _probs_array(probs)
     t = PtBatchTuning()
-    ms = ctypes.c_double()
+    ms, ms0 = ctypes.c_double(), ctypes.c_double()
     _check(load_library().pt_autotune_batched(
         len(probs), arr, _ptr_array(rhos), _ptr(Theta_out), _ptr_array(grads), _ptr(ws),
-        ws.numel() * ws.element_size(), _stream(stream), ctypes.byref(t), ctypes.byref(ms)),
-        "pt_autotune_batched")
-    return t.as_dict(), ms.value
+        ws.numel() * ws.element_size(), _stream(stream), ctypes.byref(t), ctypes.byref(ms),
+        ctypes.byref(ms0)), "pt_autotune_batched")
+    return t.as_dict(), ms.value, ms0.value
 
 
 # ---------------------------------------------------------------------------
@@ -419,12 +502,19 @@ def pt_filter_validate(f: PtFilter) -> int:
 
 
 def pt_filter_projection(f: PtFilter, chi, chi_fil, chi_phys, stream=None):
+    ne = f.nx * f.ny
+    _check_tensors("pt_filter_projection", [(chi, "chi", ne), (chi_fil, "chi_fil", ne),
+                                            (chi_phys, "chi_phys", ne)])
     _check(load_library().pt_filter_projection(ctypes.byref(f), _ptr(chi), _ptr(chi_fil),
                                                _ptr(chi_phys), _stream(stream)),
            "pt_filter_projection")
 
 
 def pt_filter_projection_backward(f: PtFilter, chi_fil, grad_phys, work, grad_chi, stream=None):
+    ne = f.nx * f.ny
+    _check_tensors("pt_filter_projection_backward", [
+        (chi_fil, "chi_fil", ne), (grad_phys, "grad_phys", ne), (work, "work", ne),
+        (grad_chi, "grad_chi", ne)])
     _check(load_library().pt_filter_projection_backward(
         ctypes.byref(f), _ptr(chi_fil), _ptr(grad_phys), _ptr(work), _ptr(grad_chi),
         _stream(stream)), "pt_filter_projection_backward")

@@ -42,12 +42,14 @@ class BatchedCycle:
         return self.Theta, self.grads
 
     def autotune(self, rhos: Sequence[torch.Tensor], stream=None) -> tuple:
-        """Picks worker shapes by timing warm cycles of this batch (synchronous)."""
-        best, ms = _pt.pt_autotune_batched(self.probs, [r.contiguous() for r in rhos],
-                                           self.Theta, self.grads, self.ws, stream)
+        """Picks the launch shape by timing warm cycles of this batch
+        (synchronous); returns (shape, its ms, the built-in shape's ms). The
+        workspace then holds the tuner's cold-cycle state for a warm cycle."""
+        best, ms, ms0 = _pt.pt_autotune_batched(self.probs, [r.contiguous() for r in rhos],
+                                                self.Theta, self.grads, self.ws, stream)
         self.tuning = best
         self.has_state = True
-        return best, ms
+        return best, ms, ms0
 
     def status(self, stream=None) -> list:
         return _pt.pt_batched_status(self.probs, self.ws, stream)

@@ -367,6 +367,7 @@ __global__ void __launch_bounds__(kCT) k_cm_batched(const EngineDesc *__restrict
     const Consts &C = D->C;
     const Bufs &B = D->B;
     const int n = blockIdx.x + 1;
+    if (B.ctl->status == kStatusOrder) return;  // adjoint with no forward before it
     const CmVecs V = LDS ? cm_vecs_lds(M) : cm_vecs(M, n);
     double *x = crow(M.Gk, M, n);
     if (!adjoint) {
@@ -410,6 +411,7 @@ __global__ void __launch_bounds__(kCT) k_cm_sweep(const EngineDesc *__restrict__
     int par = 0;
     const Consts &C = D->C;
     const Bufs &B = D->B;
+    if (B.ctl->status == kStatusOrder) return;  // adjoint with no forward before it
     const CmVecs V = LDS ? cm_vecs_lds(M) : cm_vecs(M, 0);
     const int Nt = C.Ntau;
     double *u = V.u;

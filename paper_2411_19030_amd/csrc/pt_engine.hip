@@ -691,13 +691,14 @@ __global__ void k_diag(const EngineDesc *__restrict__ D) {
     }
 }
 
-// Reset of each design's status block (blockIdx.x = design); the forward-done
-// marker survives into the adjoint call.
+// Reset of each design's status block (blockIdx.x = design). An adjoint call
+// (keep_markers = 1) keeps the forward-done marker and starts in the call-order
+// error state if no complete forward pass left it.
 __global__ void k_reset_ctl(const EngineDesc *__restrict__ D, int keep_markers) {
     if (threadIdx.x == 0) {
         Control *ctl = D[blockIdx.x].B.ctl;
         const int f = ctl->fwd_done;
-        ctl->status = 0;
+        ctl->status = (keep_markers && f != kFwdDone) ? kStatusOrder : 0;
         ctl->abort = 0;
         ctl->max_iters = 0;
         ctl->iters_fine = ctl->iters_coarse = ctl->solves_fine = ctl->solves_coarse = 0;
@@ -739,6 +740,11 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
 
     const int gid = S.wg_group[blockIdx.x];
     if (gid < 0) return;
+    // an adjoint pass with no forward pass before it does not run (every
+    // workgroup reads the same status, written before the launch)
+    if constexpr (!MULTI) {
+        if (E1.B.ctl->status == kStatusOrder) return;
+    }
     const Group G = S.groups[gid];
     const int rank = blockIdx.x - G.wg0;
     const int g = G.nwg;
@@ -2033,7 +2039,7 @@ __global__ void k_finalize_fwd(const EngineDesc *__restrict__ D) {
         const double Th = B.out_th[C.Ntau];
         *B.Theta_out = Th;
         if (!(Th > 0.0) || !isfinite(Th)) atomicCAS(&B.ctl->status, 0, -5);
-        B.ctl->fwd_done = 1;
+        B.ctl->fwd_done = kFwdDone;
     }
 }
 
@@ -2045,6 +2051,14 @@ __global__ void k_finalize_adj(const EngineDesc *__restrict__ D) {
     const Consts &C = E.C;
     const Bufs &B = E.B;
     const size_t Nn = C.Nn;
+    if (B.ctl->status == kStatusOrder) {
+        // no forward pass preceded this adjoint: nothing ran, lambda is undefined
+        const size_t n = (size_t)(C.Ntau + 1) * Nn;
+        for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < n;
+             id += (size_t)gridDim.x * blockDim.x)
+            B.out_L[id] = __longlong_as_double(0x7FF8000000000000LL);
+        return;
+    }
     if (C.Ntau == 1 || C.plt) {
         for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < Nn;
              id += (size_t)gridDim.x * blockDim.x) {
@@ -2057,7 +2071,7 @@ __global__ void k_finalize_adj(const EngineDesc *__restrict__ D) {
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         B.ctl->grad_scale = C.plt ? pow(*B.Theta, 1.0 - C.p) / (double)C.p : 1.0;
-        B.ctl->adj_done = 1;
+        B.ctl->adj_done = kAdjDone;
     }
 }
 
@@ -2067,6 +2081,13 @@ __global__ void k_sensitivities(const EngineDesc *__restrict__ D) {
     const EngineDesc &E = D[blockIdx.y];
     const Consts &C = E.C;
     const Bufs &B = E.B;
+    if (B.ctl->adj_done != kAdjDone) {
+        // no complete adjoint pass: the sensitivity sums are not this cycle's
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(&B.ctl->status, 0, kStatusOrder);
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < C.Ne; e += gridDim.x * blockDim.x)
+            B.grad[e] = __longlong_as_double(0x7FF8000000000000LL);
+        return;
+    }
     const double scale = B.ctl->grad_scale;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < C.Ne; e += gridDim.x * blockDim.x) {
         double s = 0.0;

@@ -545,12 +545,13 @@ int lds_cap_doubles(const Device &dev) {
     return (std::min(dev.lds_max, 160 * 1024) - 1024) / 8;
 }
 
-// Streaming-mode tile: the group's share of the nodes, cut to what fits LDS.
-int tile_for(int Nn, int nwg, int H, int cap_doubles) {
+// Streaming-mode tile: the group's share of the nodes, cut to what fits LDS
+// and to tile_max (0: the built-in 4096).
+int tile_for(int Nn, int nwg, int H, int cap_doubles, int tile_max = 0) {
     int ts = (Nn + nwg - 1) / nwg;
     ts = (ts + 255) / 256 * 256;
     while (ts > 256 && engine_lds_doubles(ts, H - 1) > (size_t)cap_doubles) ts -= 256;
-    ts = std::min(ts, std::max(256, env_int("PT_TILE_MAX", 4096)));
+    ts = std::min(ts, std::max(256, tile_max > 0 ? tile_max : env_int("PT_TILE_MAX", 4096)));
     ts = std::max(ts, 256);
     return ts;
 }
@@ -602,7 +603,7 @@ int launch_engine(bool fp32, int npt, const EngineDesc *D, const EngineDesc *sin
     const bool multi = single == nullptr;
     int cap = 0;
     PT_TRY(engine_capacity(fp32, npt, multi, lds_bytes, dev, cap));
-    if (cap < grid || grid > kMaxGrid) return PT_EHIP;
+    if (cap < grid || grid > kMaxGrid) return PT_ESIZE;
     const void *kern = engine_kernel(fp32, npt, multi);
     Launch Xv = X;
     const EngineDesc *Dv = D;
@@ -1067,6 +1068,7 @@ pt_batch_tuning default_tuning(int n) {
     t.sweep_groups = env_int("PT_BATCH_SWEEP_GROUPS", std::max(1, std::min(n, 8)));
     t.resident = env_int("PT_BATCH_RESIDENT", 0);
     t.grid = env_int("PT_BATCH_GRID", 0);
+    t.tile_max = env_int("PT_BATCH_TILE_MAX", 0);
     return t;
 }
 
@@ -1074,7 +1076,8 @@ bool valid_tuning(const pt_batch_tuning *t) {
     return t->fine_wgs >= 1 && t->fine_wgs <= kMaxGroup && t->sweep_wgs >= 1 &&
            t->sweep_wgs <= kMaxGroup && t->sweep_groups >= 1 &&
            t->sweep_groups < kMaxBatchGroups && (t->resident == 0 || t->resident == 1) &&
-           t->grid >= 0 && t->grid <= kMaxGrid;
+           t->grid >= 0 && t->grid <= kMaxGrid &&
+           (t->tile_max == 0 || (t->tile_max >= 256 && t->tile_max <= 16384));
 }
 
 // Plans and runs one multi-design engine launch. `hd` holds the designs'
@@ -1103,8 +1106,8 @@ int run_batched_engine(std::vector<EngineDesc> &hd, const pt_batch_tuning &T, bo
             if ((C.Nn + t0 - 1) / t0 != T.fine_wgs || (C.Nn + t1 - 1) / t1 != T.sweep_wgs)
                 return PT_EINVAL;
         } else {
-            t0 = tile_for(C.Nn, T.fine_wgs, H, cap_d);
-            t1 = tile_for(C.Nn, T.sweep_wgs, H, cap_d);
+            t0 = tile_for(C.Nn, T.fine_wgs, H, cap_d, T.tile_max);
+            t1 = tile_for(C.Nn, T.sweep_wgs, H, cap_d, T.tile_max);
         }
         E.plan.tile0 = t0;
         E.plan.tile1 = t1;
@@ -1318,6 +1321,10 @@ int noalloc_workspace(void **out) {
     *out = g_scratch_ptr[dev];
     return PT_OK;
 }
+
+int batched_cycle(int n, const pt_problem *probs, const double *const *rho, int warm,
+                  const pt_batch_tuning *tuning, double *Theta_out, double *const *dTheta_drho,
+                  void *ws, size_t ws_bytes, hipStream_t stream, bool save_guess);
 
 }  // namespace
 
@@ -1599,6 +1606,31 @@ int pt_parareal_batched(int n, const pt_problem *probs, const double *const *rho
                         const pt_batch_tuning *tuning, double *Theta_out,
                         double *const *dTheta_drho, void *ws, size_t ws_bytes,
                         hipStream_t stream) {
+    return batched_cycle(n, probs, rho, warm, tuning, Theta_out, dTheta_drho, ws, ws_bytes,
+                         stream, true);
+}
+
+int pt_batched_status(int n, const pt_problem *probs, const void *ws, hipStream_t stream,
+                      pt_stats *out) {
+    if (!valid_batch(n, probs) || !ws || !out) return PT_EINVAL;
+    const BatchLayout Lay = batch_layout(n, probs);
+    PT_TRY(hip_ok(hipStreamSynchronize(stream)));
+    for (int k = 0; k < n; ++k)
+        PT_TRY(read_status(static_cast<const char *>(ws) + Lay.d[k].ctl, &out[k]));
+    return PT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One optimisation cycle of every design of a batch. With save_guess the
+// corrected u and lambda become the next warm cycle's guesses (Alg. 3);
+// without, the guesses in ws stay as they are (the autotuner's timed cycles
+// all restart from one state).
+int batched_cycle(int n, const pt_problem *probs, const double *const *rho, int warm,
+                  const pt_batch_tuning *tuning, double *Theta_out, double *const *dTheta_drho,
+                  void *ws, size_t ws_bytes, hipStream_t stream, bool save_guess) {
     if (!valid_batch(n, probs)) return PT_EINVAL;
     if (!rho || !Theta_out || !dTheta_drho || !ws || (warm != 0 && warm != 1)) return PT_EINVAL;
     for (int k = 0; k < n; ++k)
@@ -1661,88 +1693,114 @@ int pt_parareal_batched(int n, const pt_problem *probs, const double *const *rho
     PT_TRY(run_batched_engine(hd, T, true, ws, Lay, stream));
     hipLaunchKernelGGL(k_finalize_adj, dim3(64, n), dim3(256), 0, stream, D);
     hipLaunchKernelGGL(k_sensitivities, dim3(128, n), dim3(256), 0, stream, D);
-    hipLaunchKernelGGL(k_save_guess, dim3(128, n), dim3(256), 0, stream, D);
+    if (save_guess) hipLaunchKernelGGL(k_save_guess, dim3(128, n), dim3(256), 0, stream, D);
     return launch_check();
 }
 
-int pt_batched_status(int n, const pt_problem *probs, const void *ws, hipStream_t stream,
-                      pt_stats *out) {
-    if (!valid_batch(n, probs) || !ws || !out) return PT_EINVAL;
-    const BatchLayout Lay = batch_layout(n, probs);
-    PT_TRY(hip_ok(hipStreamSynchronize(stream)));
-    for (int k = 0; k < n; ++k)
-        PT_TRY(read_status(static_cast<const char *>(ws) + Lay.d[k].ctl, &out[k]));
-    return PT_OK;
-}
+}  // namespace
+
+extern "C" {
 
 int pt_autotune_batched(int n, const pt_problem *probs, const double *const *rho,
                         double *Theta_out, double *const *dTheta_drho, void *ws,
                         size_t ws_bytes, hipStream_t stream, pt_batch_tuning *best,
-                        double *best_ms) {
+                        double *best_ms, double *default_ms) {
     if (!valid_batch(n, probs) || !best) return PT_EINVAL;
     if (capturing(stream)) return PT_EINVAL;
-    pt_batch_tuning cur = default_tuning(n);
-    // the guesses every timed cycle restarts from
-    PT_TRY(pt_parareal_batched(n, probs, rho, 0, &cur, Theta_out, dTheta_drho, ws, ws_bytes,
-                               stream));
+    const pt_batch_tuning dflt = default_tuning(n);
+    // the state every timed cycle restarts from
+    PT_TRY(batched_cycle(n, probs, rho, 0, &dflt, Theta_out, dTheta_drho, ws, ws_bytes, stream,
+                         true));
     PT_TRY(hip_ok(hipStreamSynchronize(stream)));
+    std::vector<pt_stats> st(n);
+    PT_TRY(pt_batched_status(n, probs, ws, stream, st.data()));
+    for (const auto &x : st)
+        if (x.status != PT_OK) return x.status;
     hipEvent_t e0, e1;
     PT_TRY(hip_ok(hipEventCreate(&e0)));
-    PT_TRY(hip_ok(hipEventCreate(&e1)));
-    std::vector<pt_stats> st(n);
-    auto time_cycle = [&](const pt_batch_tuning &t, double &ms) -> int {
-        PT_TRY(hip_ok(hipEventRecord(e0, stream)));
-        int rc = pt_parareal_batched(n, probs, rho, 1, &t, Theta_out, dTheta_drho, ws, ws_bytes,
-                                     stream);
-        if (rc != PT_OK) return rc;
-        PT_TRY(hip_ok(hipEventRecord(e1, stream)));
-        PT_TRY(hip_ok(hipEventSynchronize(e1)));
-        float f = 0.0f;
-        PT_TRY(hip_ok(hipEventElapsedTime(&f, e0, e1)));
-        PT_TRY(pt_batched_status(n, probs, ws, stream, st.data()));
-        for (const auto &s : st)
-            if (s.status != PT_OK && s.status != PT_ENOCONV) return s.status;
-        ms = f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return PT_EHIP;
+    }
+    constexpr int kRepeats = 3;
+    // median of kRepeats warm cycles; a shape the batch cannot use, or any
+    // device-side problem of a design, makes the shape unusable (ms = +inf)
+    auto time_shape = [&](const pt_batch_tuning &t, double &ms) -> int {
+        ms = INFINITY;
+        if (!valid_tuning(&t)) return PT_OK;
+        double ts[kRepeats];
+        for (int r = 0; r < kRepeats; ++r) {
+            PT_TRY(hip_ok(hipEventRecord(e0, stream)));
+            const int rc = batched_cycle(n, probs, rho, 1, &t, Theta_out, dTheta_drho, ws,
+                                         ws_bytes, stream, false);
+            if (rc == PT_EINVAL || rc == PT_ESIZE) return PT_OK;
+            PT_TRY(rc);
+            PT_TRY(hip_ok(hipEventRecord(e1, stream)));
+            PT_TRY(hip_ok(hipEventSynchronize(e1)));
+            float f = 0.0f;
+            PT_TRY(hip_ok(hipEventElapsedTime(&f, e0, e1)));
+            PT_TRY(pt_batched_status(n, probs, ws, stream, st.data()));
+            for (const auto &x : st)
+                if (x.status != PT_OK) return PT_OK;
+            ts[r] = f;
+        }
+        std::sort(ts, ts + kRepeats);
+        ms = ts[kRepeats / 2];
         return PT_OK;
     };
-    double best_t = 1e30;
-    int rc0 = time_cycle(cur, best_t);
-    if (rc0 != PT_OK) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return rc0;
-    }
-    // coordinate descent over the worker shapes
-    const int fine_opts[] = {1, 2, 4, 8};
-    const int sweep_opts[] = {8, 16, 32};
-    const int group_opts[] = {std::max(1, n / 8), std::max(1, n / 4), std::max(1, n / 2), n};
-    auto consider = [&](pt_batch_tuning t) {
-        double ms = 0.0;
-        if (!valid_tuning(&t)) return;
-        if (time_cycle(t, ms) == PT_OK && ms < best_t) {
+    pt_batch_tuning cur = dflt;
+    double best_t = INFINITY, t_dflt = INFINITY;
+    int rc = time_shape(dflt, t_dflt);
+    best_t = t_dflt;
+    auto consider = [&](pt_batch_tuning t) -> int {
+        if (memcmp(&t, &cur, sizeof(t)) == 0) return PT_OK;
+        double ms = INFINITY;
+        PT_TRY(time_shape(t, ms));
+        if (ms < best_t) {
             best_t = ms;
             cur = t;
         }
+        return PT_OK;
     };
-    for (int f : fine_opts) {
-        pt_batch_tuning t = cur;
-        t.fine_wgs = f;
-        if (f != cur.fine_wgs) consider(t);
-    }
-    for (int s : sweep_opts) {
-        pt_batch_tuning t = cur;
-        t.sweep_wgs = s;
-        if (s != cur.sweep_wgs) consider(t);
-    }
-    for (int g : group_opts) {
-        pt_batch_tuning t = cur;
-        t.sweep_groups = std::min(g, kMaxBatchGroups - 1);
-        if (t.sweep_groups != cur.sweep_groups) consider(t);
+    const int fine_opts[] = {1, 2, 4, 8, 16};
+    const int sweep_opts[] = {4, 8, 16, 32};
+    const int group_opts[] = {std::max(1, n / 8), std::max(1, n / 4), std::max(1, n / 2), n};
+    const int tile_opts[] = {0, 2048, 1024};
+    for (int pass = 0; pass < 2 && rc == PT_OK; ++pass) {
+        for (int r = 0; r <= 1 && rc == PT_OK; ++r) {
+            pt_batch_tuning t = cur;
+            t.resident = r;
+            rc = consider(t);
+        }
+        for (int f : fine_opts) {
+            pt_batch_tuning t = cur;
+            t.fine_wgs = f;
+            if (rc == PT_OK) rc = consider(t);
+        }
+        for (int w : sweep_opts) {
+            pt_batch_tuning t = cur;
+            t.sweep_wgs = w;
+            if (rc == PT_OK) rc = consider(t);
+        }
+        for (int g : group_opts) {
+            pt_batch_tuning t = cur;
+            t.sweep_groups = std::min(g, kMaxBatchGroups - 1);
+            if (rc == PT_OK) rc = consider(t);
+        }
+        for (int tm : tile_opts) {
+            pt_batch_tuning t = cur;
+            if (t.resident) break;
+            t.tile_max = tm;
+            if (rc == PT_OK) rc = consider(t);
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (rc != PT_OK) return rc;
+    if (!(best_t < INFINITY)) return PT_ENOCONV;  // no shape ran the batch cleanly
     *best = cur;
     if (best_ms) *best_ms = best_t;
+    if (default_ms) *default_ms = t_dflt;
     return PT_OK;
 }
 

@@ -52,6 +52,14 @@ struct Group {
     int queue;          // shared queue index, -1 for a private list
 };
 
+// Call-order markers of a single-design workspace: a complete forward pass
+// leaves fwd_done = kFwdDone, a complete adjoint pass adj_done = kAdjDone. An
+// adjoint without a forward, or sensitivities without an adjoint, report
+// kStatusOrder (PT_ESTATE) and write NaN outputs instead of running.
+constexpr int kFwdDone = 0x46574431;
+constexpr int kAdjDone = 0x41444A31;
+constexpr int kStatusOrder = -6;
+
 // Device-side control/status block at the start of the workspace.
 struct Control {
     int status;            // first device-side error (PT_* code), 0 if none
@@ -60,7 +68,8 @@ struct Control {
     int pad0;
     unsigned long long iters_fine, iters_coarse, solves_fine, solves_coarse;
     unsigned long long max_relres_bits;  // max final ||r||/||b|| as double bits
-    int fwd_done, adj_done;              // call-order markers (written by finalize kernels)
+    int fwd_done, adj_done;              // call-order markers: kFwdDone / kAdjDone once the
+                                         // pass finished (finalize kernels), else anything
     int epoch;
     int pad1;
     double grad_scale;  // factor of the summed sensitivities: Theta^{1-p}/p with G = 0, else 1

@@ -241,3 +241,54 @@ def test_cycle_noalloc_host_errors(lib):
     c = big.to_c()
     assert lib.pt_cycle_noalloc(ctypes.byref(c), *args) == _pt.PT_ESIZE
     assert b"static" in lib.pt_strerror(_pt.PT_ESIZE)
+
+
+def test_binding_rejects_unusable_tensors(lib):
+    """The Python binding refuses tensors the kernels would misread (a float32
+    density, a CPU pointer, a wrong size, a strided view) with ValueError,
+    before anything reaches the library."""
+    import torch
+    f64 = torch.float64
+    p = base()
+    Ne, Nn, Nt1 = p.n_elem, p.n_nodes, p.n_slices + 1
+    rows = _pt.pt_state_bytes(p) // (8 * Nn)
+    rho = torch.full((Ne,), 0.3, dtype=f64)
+    S = torch.zeros(rows, Nn, dtype=f64)
+    U = torch.zeros(Nt1, Nn, dtype=f64)
+    th = torch.zeros(Nt1, dtype=f64)
+    Th = torch.zeros((), dtype=f64)
+    g = torch.zeros(Ne, dtype=f64)
+    ws = torch.zeros(64, dtype=torch.uint8)
+
+    def fwd(r=rho, gT=None, gth=None, S_=S):
+        _pt.pt_parareal_forward(p, r, gT, gth, S_, U, th, Th, ws)
+
+    with pytest.raises(ValueError, match="dtype torch.float32"):
+        fwd(r=rho.float())
+    with pytest.raises(ValueError, match="elements"):
+        fwd(r=torch.zeros(Ne + 1, dtype=f64))
+    with pytest.raises(ValueError, match="elements"):
+        fwd(gT=torch.zeros(Nt1 - 1, Nn, dtype=f64), gth=th)
+    with pytest.raises(ValueError, match="contiguous"):
+        fwd(r=torch.zeros(2 * Ne, dtype=f64)[::2])
+    with pytest.raises(ValueError, match="elements"):
+        fwd(S_=torch.zeros(rows - 1, Nn, dtype=f64))
+    # right dtype, layout and sizes, but host memory
+    with pytest.raises(ValueError, match="GPU tensor"):
+        fwd()
+    with pytest.raises(ValueError, match="elements"):
+        _pt.pt_parareal_adjoint(p, rho, S, Th, torch.zeros(Nn, dtype=f64), U, ws)
+    with pytest.raises(ValueError, match="float32"):
+        _pt.pt_sensitivities(p, rho, ws, g.float())
+    with pytest.raises(ValueError, match="GPU tensor"):
+        _pt.pt_sensitivities(p, rho, ws, g)
+    with pytest.raises(ValueError, match="elements"):
+        _pt.pt_cycle_noalloc(p, rho, None, None, None, S, U, th, U, Th, torch.zeros(3, dtype=f64))
+    with pytest.raises(ValueError, match="densities"):
+        _pt.pt_parareal_batched([p, p], [rho], False, None, torch.zeros(2, dtype=f64), [g, g], ws)
+    with pytest.raises(ValueError, match="dTheta_drho\\[1\\]"):
+        _pt.pt_parareal_batched([p, p], [rho, rho], False, None, torch.zeros(2, dtype=f64),
+                                [g, g.float()], ws)
+    flt = _pt.make_filter(8, 8, 0.2, 8.0, 0.5)
+    with pytest.raises(ValueError, match="elements"):
+        _pt.pt_filter_projection(flt, rho, None, torch.zeros(Ne - 1, dtype=f64))

@@ -226,3 +226,33 @@ def test_batch_fp32_64_designs_full_size(gpu):
         assert et <= 1e-6 and eg <= 1e-5
         checked += 1
     assert checked >= 5
+
+
+def test_autotuned_shape_keeps_parity_and_beats_the_default(gpu):
+    """pt_autotune_batched times every candidate from one state (the cold cycle's
+    solution, which it leaves in the workspace), so the shape it returns is at
+    least as fast as the built-in one measured from that state. A warm cycle in
+    the tuned shape then restarts from that state and matches the oracle's
+    warm cycle from its own cold cycle."""
+    import torch
+
+    from paper_2411_19030_amd._pt import pt_batch_default_tuning
+    from paper_2411_19030_amd.batched import BatchedCycle
+    shapes = [s for s in SMALL if s[0] >= 9]
+    probs = _problems(shapes, cg_rtol=1e-13, max_iter=20000)
+    rhos_np = [density_uniform_noise(nx, ny, 300 + k) for k, (nx, ny, _, _) in enumerate(shapes)]
+    rhos = [torch.tensor(r, device=gpu) for r in rhos_np]
+    cyc = BatchedCycle(probs, gpu)
+    best, best_ms, default_ms = cyc.autotune(rhos)
+    print("tuned", best, best_ms, "default", pt_batch_default_tuning(len(probs)), default_ms,
+          flush=True)
+    assert 0.0 < best_ms <= default_ms
+    th, gr = _run(cyc, rhos_np, True, gpu)
+    assert all(s["status"] == 0 for s in cyc.status())
+    for k, (nx, ny, nt, ns) in enumerate(shapes):
+        cfg = dict(nx=nx, ny=ny, n_steps=nt, n_slices=ns, pnorm=8)
+        cold = _oracle(cfg, rhos_np[k])
+        o = _oracle(cfg, rhos_np[k], cold["guess"])
+        et, eg = _errors(th[k], gr[k], o)
+        print("tuned warm", shapes[k], et, eg, flush=True)
+        assert et <= 1e-10 and eg <= 1e-10

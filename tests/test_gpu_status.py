@@ -65,3 +65,43 @@ def test_capped_coarse_solves_report_enoconv(gpu, prop):
     for k in ("S", "uT", "lam", "grad"):
         assert np.all(np.isfinite(g[k])), k
     assert np.isfinite(g["Theta"]) and g["Theta"] > 0
+
+
+PT_ESTATE = -6
+
+
+@pytest.mark.parametrize("prop", [0, 1, 2])
+def test_call_order_violations_report_estate(gpu, prop):
+    """An adjoint pass with no forward pass before it, and sensitivities with
+    no adjoint pass before them, run nothing: pt_query_status reports
+    PT_ESTATE and the outputs are NaN. The calls in order then work."""
+    import torch
+
+    from paper_2411_19030_amd.cycle import Cycle
+    cyc = Cycle(gpu_problem(_cfg(propagator=prop)), "cuda")
+    cyc.ws.zero_()
+    rho = torch.tensor(density_uniform_noise(32, 32, 5), dtype=torch.float64, device="cuda")
+    cyc.adjoint(rho)
+    st = cyc.status()
+    assert st["status"] == PT_ESTATE, st
+    assert torch.isnan(cyc.lam).all()
+    cyc.sensitivities(rho)
+    assert cyc.status()["status"] == PT_ESTATE
+    assert torch.isnan(cyc.grad).all()
+    # forward, then sensitivities without the adjoint pass
+    cyc.forward(rho)
+    assert cyc.status()["status"] == 0
+    cyc.sensitivities(rho)
+    assert cyc.status()["status"] == PT_ESTATE
+    assert torch.isnan(cyc.grad).all()
+    # the three calls in order
+    cyc.forward(rho)
+    cyc.adjoint(rho)
+    cyc.sensitivities(rho)
+    st = cyc.status()
+    assert st["status"] == 0, st
+    assert torch.isfinite(cyc.grad).all() and torch.isfinite(cyc.lam).all()
+    # a second adjoint and sensitivities on the same forward are still in order
+    cyc.adjoint(rho)
+    cyc.sensitivities(rho)
+    assert cyc.status()["status"] == 0

@@ -94,6 +94,8 @@ def test_noalloc_matches_caller_workspace_twice_second_smaller(gpu):
 def test_noalloc_rejects_a_problem_beyond_the_static_workspace(gpu):
     p = gpu_problem(dict(nx=256, ny=256, n_steps=512, n_slices=32))
     assert _pt.pt_workspace_bytes(p) > _pt.PT_NOALLOC_WS_BYTES
-    z = torch.zeros(1, dtype=F64, device=gpu)
-    rc = _pt.pt_cycle_noalloc(p, z, None, None, None, z, None, None, None, z, z, check=False)
+    out = _outputs(p, gpu)
+    rho = torch.full((p.n_elem,), 0.3, dtype=F64, device=gpu)
+    rc = _pt.pt_cycle_noalloc(p, rho, None, None, None, out["S"], None, None, None,
+                              out["Theta"], out["grad"], check=False)
     assert rc == _pt.PT_ESIZE
