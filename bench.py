@@ -10,10 +10,15 @@ seeded rho = 0.3 + U(-0.1, 0.1), q = 1, Jacobi-PCG to relative residual
 the same design. Work per cycle = N_e * N_t cell updates.
 
 Prints one JSON line. `roofline` reports the lane engine (the kernel that runs
-each whole pass) against HBM peak with the algorithmic byte model:
-per node and CG iteration 12 words, plus 4 words per node and fine step in the
-primal pass and 7 in the adjoint pass (FP64). `cpu_baseline` times the FP64
-oracle (one thread) on a cold cycle of the same workload.
+each whole pass, one launch per pass) against HBM peak: `achieved` is the
+algorithmic byte model -- per node and CG iteration 12 words, plus 4 words per
+node and fine step in the primal pass and 7 in the adjoint pass (FP64), with
+the pass's measured CG iteration counts -- per launch over the mean launch
+time; `traffic` is the launch's measured HBM bytes (rocprofv3 FETCH_SIZE and
+WRITE_SIZE, calibrated on a plain copy), null when the engine sources changed
+since, and `measured_hbm_frac` the bandwidth those bytes mean. `cpu_baseline`
+times the FP64 oracle on a warm cycle of the same workload, in one thread and
+slice-parallel over worker processes.
 """
 from __future__ import annotations
 
@@ -36,6 +41,12 @@ WORKLOAD = "plain_fp64_256"
 # cycle; valid only for the engine sources with this hash (see profiles/).
 TRAFFIC = {"sources_sha1": "ed70104b3096415b11e7a4c400b2b77bbcd135fd",
            "bytes_per_launch": 0.5 * (28.66e9 + 28.68e9)}
+
+
+def traffic_per_launch():
+    """Measured HBM bytes of one engine launch, or None once the engine sources
+    differ from those the counters were taken on."""
+    return TRAFFIC["bytes_per_launch"] if sources_sha1() == TRAFFIC["sources_sha1"] else None
 
 
 # The sources k_engine is built from: its kernel, its layouts and the host
@@ -71,7 +82,8 @@ def parse():
                              "paper_100", "one_shot_chain", "plt_fp64_256", "cmesh_fp64_256"],
                     help="the headline workload (default), or one of the other workloads "
                          "measured on its own")
-    ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-sample-only", type=int, default=0, metavar="WORKERS",
+                    help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (counter calibration)")
     return ap.parse_args()
@@ -90,41 +102,120 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "repeats": 3}))
 
 
-def cpu_sample() -> dict:
-    """Oracle cold cycle on the benchmark workload (runs in a 1-thread child)."""
-    import numpy as np  # noqa: F401
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_problem(w):
+    import oracle as O
+    return O.Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
+                     p=w["p"], k0=w["k0"], kmin=w["kmin"], pk=w["pk"], c0=w["c0"],
+                     cmin=w["cmin"], pc=w["pc"], q=w["q"], t_final=w["t_final"], bc=w["bc"])
+
+
+# slice-parallel oracle workers (fork start): the discretisation with its
+# factors, and the forward's S and Theta for the adjoint, are inherited
+_POOL_STATE = {}
+
+
+def _f_pri_task(item):
+    import oracle as O
+    n, T, th = item
+    return O.F_pri(_POOL_STATE["d"], T, th, n)
+
+
+def _f_adj_task(item):
+    import oracle as O
+    n, lam, g = item
+    return O.F_adj(_POOL_STATE["d"], _POOL_STATE["S"], _POOL_STATE["Theta"], lam, g, n)
+
+
+def cpu_sample(workers: int) -> dict:
+    """The FP64 oracle on the benchmark workload, the GPU's unit of work: one
+    warm one-iteration cycle (forward + adjoint + sensitivities) restarting
+    from the oracle's own cold cycle (untimed).
+    workers == 1: every step in this process (mode i, sequential).
+    workers > 1: the paper's structure (Sec. 4.3, Sec. 5.2): a pool of worker
+    processes runs the fine propagators of all slices, this process the
+    coarse sweeps (mode ii, slice-parallel). Factorisations happen before
+    the timed cycle in both modes (they belong to the design, not the cycle)."""
+    import multiprocessing as mp
+
+    import numpy as np
 
     import oracle as O
     from workloads import workload, workload_density
     w = workload(WORKLOAD)
-    P = O.Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
-                  p=w["p"], k0=w["k0"], kmin=w["kmin"], pk=w["pk"], c0=w["c0"],
-                  cmin=w["cmin"], pc=w["pc"], q=w["q"], t_final=w["t_final"], bc=w["bc"])
-    rho = workload_density(WORKLOAD)
+    P = _oracle_problem(w)
+    d = O.Discretisation(P, workload_density(WORKLOAD))
+    d._factor(P.dt)
+    d._factor(P.dtau)
+    cold_f = O.parareal_forward(d, 1)
+    cold_a = O.parareal_adjoint(d, cold_f["S"], cold_f["Theta"], 1)
+    gT, gth, gl = cold_f["uT"], cold_f["utheta"], cold_a["lam"]
+    del cold_f, cold_a
+    _POOL_STATE["d"] = d
+    ctx = mp.get_context("fork")
     t0 = time.perf_counter()
-    d = O.Discretisation(P, rho)
-    fw = O.parareal_forward(d, 1)
-    ad = O.parareal_adjoint(d, fw["S"], fw["Theta"], 1)
+    if workers <= 1:
+        fw = O.parareal_forward(d, 1, gT, gth)
+        ad = O.parareal_adjoint(d, fw["S"], fw["Theta"], 1, gl)
+    else:
+        with ctx.Pool(workers) as pool:
+            fw = O.parareal_forward(d, 1, gT, gth,
+                                    fmap=lambda items: pool.map(_f_pri_task, items))
+        _POOL_STATE["S"], _POOL_STATE["Theta"] = fw["S"], fw["Theta"]
+        with ctx.Pool(workers) as pool:
+            ad = O.parareal_adjoint(d, fw["S"], fw["Theta"], 1, gl,
+                                    fmap=lambda items: pool.map(_f_adj_task, items))
     t = time.perf_counter() - t0
     cells = w["nx"] * w["ny"] * w["n_steps"]
-    return dict(seconds=t, cells=cells, Theta=fw["Theta"], grad_norm=float(
-        np.linalg.norm(ad["grad"])))
+    return dict(seconds=t, cells=cells, workers=workers, Theta=fw["Theta"],
+                grad_norm=float(np.linalg.norm(ad["grad"])))
 
 
 def cpu_baseline() -> dict:
+    """Oracle cell-updates/s on this host: mode (i) one thread, and mode (ii)
+    min(N_tau, 16, cores) worker processes, each a fresh child with BLAS
+    pinned to one thread per process."""
+    from workloads import workload
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         env[k] = "1"
-    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample-only"],
-                         capture_output=True, text=True, env=env, timeout=900)
-    if out.returncode != 0:
-        raise RuntimeError(out.stderr[-2000:])
-    r = json.loads(out.stdout.strip().splitlines()[-1])
-    return {"value": r["cells"] / r["seconds"], "unit": "cell-updates/s", "cores": 1,
+    cores = os.cpu_count() or 1
+    pool = max(1, min(workload(WORKLOAD)["n_slices"], 16, cores))
+
+    def child(workers):
+        out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample-only",
+                              str(workers)], capture_output=True, text=True, env=env,
+                             timeout=900)
+        if out.returncode != 0:
+            raise RuntimeError(out.stderr[-2000:])
+        return json.loads(out.stdout.strip().splitlines()[-1])
+
+    seq = child(1)
+    par = child(pool)
+    host = f"{_cpu_model()}, {cores} logical CPUs"
+    return {"value": seq["cells"] / seq["seconds"], "unit": "cell-updates/s", "cores": 1,
             "kind": "oracle",
-            "sample": (f"one cold one-iteration cycle (forward + adjoint + sensitivities) of "
-                       f"the {WORKLOAD} workload by the FP64 oracle, sparse LU per step, one "
-                       f"thread: {r['seconds']:.1f} s for {r['cells']} cell updates")}
+            "sample": (f"one warm one-iteration cycle (forward + adjoint + sensitivities) of the "
+                       f"{WORKLOAD} workload by the FP64 oracle (sparse LU per step) in one "
+                       f"thread, restarting from the oracle's cold cycle: {seq['seconds']:.1f} s "
+                       f"for {seq['cells']} cell updates; host {host}"),
+            "host": host,
+            "slice_parallel": {"value": par["cells"] / par["seconds"], "cores": pool,
+                               "seconds": par["seconds"],
+                               "sample": (f"the same warm cycle with the fine propagators of "
+                                          f"all slices on {pool} worker processes and the "
+                                          f"coarse sweeps in the master (the paper's "
+                                          f"structure)")}}
 
 
 def precision_compare(prob, rho, gT, gth, gl, accuracy=1e-6, repeats=3) -> dict:
@@ -651,7 +742,7 @@ def large_run(name: str, steps: int) -> dict:
 def main():
     args = parse()
     if args.cpu_sample_only:
-        print(json.dumps(cpu_sample()))
+        print(json.dumps(cpu_sample(args.cpu_sample_only)))
         return
     if args.copy_calibration:
         copy_calibration()
@@ -764,7 +855,11 @@ def main():
     it_a = st_a["cg_iters_fine"] + st_a["cg_iters_coarse"]
     bytes_f = 8.0 * Nn * (12 * it_f + 4 * Nt)
     bytes_a = 8.0 * Nn * (12 * it_a + 7 * Nt)
-    achieved = (bytes_f + bytes_a) / ((t_fwd + t_adj) * 1e-3) / 1e9
+    # one engine launch per pass: per launch, the mean of the two
+    alg_per_launch = 0.5 * (bytes_f + bytes_a)
+    launch_s = 0.5 * (t_fwd + t_adj) * 1e-3
+    achieved = alg_per_launch / launch_s / 1e9
+    traffic = traffic_per_launch()
     out = {
         "metric": "fine-step cell-updates/s (fwd+adjoint+sens per cycle), % HBM peak, vs FP64",
         "value": cells / (ms * 1e-3),
@@ -783,9 +878,13 @@ def main():
                    "parareal_iterations": 1, "guess": "previous (cold) cycle",
                    "precision": "fp64", "preconditioner": "jacobi"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (TRAFFIC["bytes_per_launch"]
-                                 if sources_sha1() == TRAFFIC["sources_sha1"] else None)},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "per": "engine launch (one per pass; mean of the forward and adjoint)",
+                     "algorithmic_bytes_per_launch": alg_per_launch,
+                     "launch_ms": launch_s * 1e3,
+                     "measured_hbm_GBps": (traffic / launch_s / 1e9 if traffic else None),
+                     "measured_hbm_frac": (traffic / launch_s / 1e9 / HBM_PEAK_GBS
+                                           if traffic else None)},
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
         "phase_ms": {"forward": t_fwd, "adjoint": t_adj, "sensitivities": t_sen},
         "cg_iterations": {"forward": it_f, "adjoint": it_a},

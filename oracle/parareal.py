@@ -54,10 +54,14 @@ def F_pri(d: Discretisation, T: np.ndarray, theta: float, n: int):
 
 
 def parareal_forward(d: Discretisation, iterations: int = 1, guess_T=None,
-                     guess_theta=None, G=None):
+                     guess_theta=None, G=None, fmap=None):
     """Modified Parareal for (T, theta).
 
     G: the coarse propagator (default G_pri; any function of (d, T, theta, n)).
+    fmap: evaluates the fine propagators of one sweep, a function of the list
+    [(n, T, theta)] returning [F_pri(d, T, theta, n)] in the same order. The
+    slices are independent (Sec. 4.2), so a parallel map gives the same
+    numbers; by default they run here one after another.
     Returns dict with S (N_t, N_n), uT (N_tau+1, N_n), utheta (N_tau+1,),
     Theta, and the initial guess that was used.
     """
@@ -88,8 +92,12 @@ def parareal_forward(d: Discretisation, iterations: int = 1, guess_T=None,
     S = np.zeros((P.n_steps, P.n_nodes))
     for _ in range(iterations):
         FT, Fth = [], []
+        if fmap is None:
+            outs = (F_pri(d, uT[n], uth[n], n) for n in range(Nt))
+        else:
+            outs = iter(fmap([(n, uT[n], uth[n]) for n in range(Nt)]))
         for n in range(Nt):
-            T, th, tr = F_pri(d, uT[n], uth[n], n)
+            T, th, tr = next(outs)
             FT.append(T)
             Fth.append(th)
             for i in range(1, M):
@@ -142,11 +150,14 @@ def F_adj(d: Discretisation, S: np.ndarray, Theta: float, lam: np.ndarray,
 
 
 def parareal_adjoint(d: Discretisation, S: np.ndarray, Theta: float,
-                     iterations: int = 1, guess_lambda=None, G=None):
+                     iterations: int = 1, guess_lambda=None, G=None, fmap=None):
     """Time-reversed vanilla Parareal for (lambda, g).
 
     G: the coarse propagator (default G_adj; any function of
     (d, S, Theta, lam, g, n)).
+    fmap: evaluates the fine adjoint propagators of one sweep, a function of
+    the list [(n, lam, g)] returning [F_adj(d, S, Theta, lam, g, n)] in the
+    same order (by default one after another here).
     Returns dict with lam (N_tau+1, N_n) where lam[n] estimates lambda_{Mn+1}
     (lam[N_tau] = 0), grad = g-part of v_0, and the guess that was used.
     """
@@ -171,8 +182,13 @@ def parareal_adjoint(d: Discretisation, S: np.ndarray, Theta: float,
     guess = np.array(vl)
     for _ in range(iterations):
         Fl, Fg = {}, {}
-        for n in range(1, Nt + 1):
-            Fl[n], Fg[n] = F_adj(d, S, Theta, vl[n], vg[n], n)
+        if fmap is None:
+            for n in range(1, Nt + 1):
+                Fl[n], Fg[n] = F_adj(d, S, Theta, vl[n], vg[n], n)
+        else:
+            outs = fmap([(n, vl[n], vg[n]) for n in range(1, Nt + 1)])
+            for n, (lam, g) in zip(range(1, Nt + 1), outs):
+                Fl[n], Fg[n] = lam, g
         if Gkl is None:
             Gkl, Gkg = {}, {}
             for n in range(1, Nt + 1):
