@@ -88,6 +88,8 @@ def test_finite_differences_small_sequential(gpu):
 
 
 def test_finite_differences_diff_fp64_512(gpu):
-    """The 512 x 512, 1024-step workload, exact sequential mode, 16 directions."""
+    """The 512 x 512, 1024-step workload, exact sequential mode, 16 directions.
+    The worst relative error measured is 6.3e-6; the bar 1e-4 leaves a factor
+    of 16 for the solves' residual carried into the difference quotient."""
     w = workload("diff_fp64_512")
-    _fd_check(gpu, nx=w["nx"], n_steps=w["n_steps"], seed=w["seed"], ndir=16, tol=1e-3)
+    _fd_check(gpu, nx=w["nx"], n_steps=w["n_steps"], seed=w["seed"], ndir=16, tol=1e-4)

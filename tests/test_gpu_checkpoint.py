@@ -12,10 +12,13 @@ the fine lanes of both passes run on groups of the same fixed shape. Hence:
 - the stored rows are the oracle's T_{Mn} and T_{Mn+1}.
 
 The large-design configuration (smooth Gaussian density, multigrid, FP32 inner
-CG with FP64 refinement, checkpoints) is checked at 512 x 512 against stored
-oracle samples (tests/golden/oracle_large_law_512.txt, written by
-tests/golden/make_oracle_samples.py from the oracle only). The bar is 1e-5,
-and 1e-6 on Theta.
+CG with FP64 refinement, checkpoints) is checked against stored oracle samples
+(written by tests/golden/make_oracle_samples.py from the oracle only) at
+512 x 512 (tests/golden/oracle_large_law_512.txt) and on the full 2048 x 2048
+grid with 512 steps in 32 slices (tests/golden/oracle_large_2048_512.txt: the
+large design's M = 16 and two waves of 16 recomputing slices). The bar is
+1e-5, and 1e-6 on Theta. At 2048 x 2048 the same cycle is also compared with
+the FP64 multigrid cycle that stores every state (see that test for its bar).
 """
 import os
 
@@ -138,3 +141,96 @@ def test_large_law_512_against_stored_oracle_samples(gpu):
     errs["grad_norm"] = abs(np.linalg.norm(g["grad"]) - gold["grad_norm"]) / gold["grad_norm"]
     print(errs, flush=True)
     assert errs["Theta"] <= 1e-6 and max(errs.values()) <= 1e-5
+
+
+def _sampled_errors(g, gold, M, Ntau, Nn):
+    """Errors of GPU outputs (torch tensors on the device, S checkpointed)
+    at the fixture's sample indices, relative to the fixture's maxima."""
+    import torch
+    dev = g["grad"].device
+    errs = {"Theta": abs(float(g["Theta"]) - gold["Theta"]) / gold["Theta"],
+            "utheta": float(np.abs(g["utheta"].cpu().numpy() - gold["utheta"]).max() /
+                            gold["Theta"])}
+    idx = gold["S_idx"]
+    rows, cols = idx // Nn, idx % Nn
+    assert np.all(((rows + 1) % M == 0) | (rows % M == 0))
+    ckrow = np.where((rows + 1) % M == 0, (rows + 1) // M - 1, Ntau + rows // M)
+    flat = torch.tensor(ckrow * Nn + cols, device=dev)
+    vals = g["S"].reshape(-1)[flat].cpu().numpy()
+    errs["S"] = float(np.abs(vals - gold["S_val"]).max() / gold["S_absmax"])
+    for key in ("uT", "lam", "grad"):
+        vals = g[key].reshape(-1)[torch.tensor(gold[key + "_idx"], device=dev)].cpu().numpy()
+        errs[key] = float(np.abs(vals - gold[key + "_val"]).max() / gold[key + "_absmax"])
+    gn = float(torch.linalg.norm(g["grad"]))
+    errs["grad_norm"] = abs(gn - gold["grad_norm"]) / gold["grad_norm"]
+    return errs
+
+
+def _large_cycle(gpu, precision, storage, rtol=1e-10):
+    """One cold cycle of the large design at 2048 x 2048 (N_t = 512 in 32
+    slices, multigrid); the outputs stay on the device."""
+    import torch
+
+    from paper_2411_19030_amd import Problem
+    from paper_2411_19030_amd.cycle import Cycle
+    w = workload("large_2048_512")
+    prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
+                   pnorm=8, cg_rtol=rtol, max_iter=20000, precond=1, precision=precision,
+                   storage=storage)
+    cyc = Cycle(prob, gpu)
+    rho = torch.tensor(workload_density("large_2048_512"), dtype=torch.float64, device=gpu)
+    cyc.run(rho)
+    torch.cuda.synchronize()
+    st = cyc.status()
+    out = dict(S=cyc.S, uT=cyc.uT, utheta=cyc.utheta, lam=cyc.lam, Theta=cyc.Theta,
+               grad=cyc.grad, status=st)
+    del cyc.ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def test_large_2048_against_stored_oracle_samples(gpu):
+    """The large design's solver settings (multigrid, FP32 + refinement,
+    checkpoints) on the full 2048 x 2048 grid, cold cycle, against the oracle."""
+    from tests.golden.make_oracle_samples import load
+    gold = load(os.path.join(HERE, "golden", "oracle_large_2048_512.txt"))
+    print("2048 x 2048, 512 steps in 32 slices: multigrid, FP32 + refinement, checkpoints",
+          flush=True)
+    g = _large_cycle(gpu, precision=1, storage=1)
+    assert g["status"]["status"] == 0, g["status"]
+    errs = _sampled_errors(g, gold, 16, 32, 2049 * 2049)
+    print(errs, g["status"], flush=True)
+    assert errs["Theta"] <= 1e-6 and max(errs.values()) <= 1e-5
+
+
+def test_large_2048_fp32_checkpoint_matches_fp64_store_all(gpu):
+    """FP32 inner CG with FP64 refinement and checkpoints against the FP64
+    multigrid cycle storing every state, both on the GPU at 2048 x 2048. Each
+    solves every system to the same FP64 true-residual tolerance (1e-10), so
+    the states differ by what that tolerance leaves, about 100 cg_rtol each
+    against the exact solution (see the full-size FP64 tests): bar 1e-7 on
+    every stored state (relative to its maximum, S on the checkpointed rows)
+    and 1e-8 on Theta. The gradient sums lambda^T dK/drho T over all 512 fine
+    steps, so it gathers the differences of every step (measured 2.5e-7
+    against 1.9e-9 on the slice-end lambda): bar 1e-6 on its 2-norm."""
+    import torch
+    print("2048 x 2048: FP32 + refinement with checkpoints", flush=True)
+    ck = _large_cycle(gpu, precision=1, storage=1)
+    print("2048 x 2048: FP64 storing every state", flush=True)
+    sa = _large_cycle(gpu, precision=0, storage=0)
+    assert ck["status"]["status"] == 0 and sa["status"]["status"] == 0
+    M, Ntau = 16, 32
+
+    def rel(a, b):
+        return float((a - b).abs().max() / b.abs().max())
+
+    errs = {"Theta": abs(float(ck["Theta"]) - float(sa["Theta"])) / float(sa["Theta"]),
+            "utheta": rel(ck["utheta"], sa["utheta"]),
+            "S_coarse": rel(ck["S"][:Ntau], sa["S"][M - 1::M]),
+            "S_first": rel(ck["S"][Ntau:], sa["S"][0::M]),
+            "uT": rel(ck["uT"], sa["uT"]), "lam": rel(ck["lam"], sa["lam"]),
+            "grad": float(torch.linalg.norm(ck["grad"] - sa["grad"]) /
+                          torch.linalg.norm(sa["grad"]))}
+    print(errs, flush=True)
+    assert errs["Theta"] <= 1e-8 and errs["grad"] <= 1e-6
+    assert max(v for k, v in errs.items() if k != "grad") <= 1e-7
