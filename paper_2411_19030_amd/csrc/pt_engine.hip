@@ -54,6 +54,10 @@ __device__ __forceinline__ double ipow(double x, int n) {
     return r;
 }
 
+// pow through a call of its own: inlined, the library routine's registers
+// raise the engine's peak pressure and push round values into scratch
+__device__ __noinline__ double pow_call(double x, double y) { return pow(x, y); }
+
 __device__ __forceinline__ long long now_ticks() {
     return (long long)__builtin_amdgcn_s_memrealtime();
 }
@@ -1134,18 +1138,18 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
         (void)gmg_round;
 
         // Resident rounds: the raw halo values (r, w, s of the neighbours'
-        // boundary nodes, and D^{-1} there) for the next round are loaded right
-        // after the barrier, together with the partial sums, so both round trips
-        // overlap; the halo z is formed once alpha and beta are known.
+        // boundary nodes) for the next round are loaded right after the
+        // barrier, together with the partial sums, so both round trips overlap;
+        // the halo z is formed once alpha and beta are known, with D^{-1} of the
+        // halo nodes staged in LDS once per solve (FIRST).
         constexpr int kHP = 2;
-        Real hpr[kHP], hpw[kHP], hps[kHP], hpd[kHP];
+        Real hpr[kHP], hpw[kHP], hps[kHP];
         bool hp_ok = false;
         auto halo_prefetch = [&](const StepInfo &st, bool need_s) {
             if constexpr (NPT > 0) {
                 const int a = min(rank * TS, C.Nn);
                 const int b = min(a + TS, C.Nn);
                 const int ppar = (nbar - 1) & 1;  // parity of the round just published
-                const double *dinv = st.fine ? B.dinv_f : B.dinv_c;
                 hp_ok = 2 * H <= kThreads * kHP;
                 // per-call index math: hoisted out of the lane loop it would be
                 // held in spilled registers, and each reload would wait for the
@@ -1155,7 +1159,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
 #pragma unroll
                 for (int u = 0; u < kHP; ++u) {
                     const int q = tid + u * kThreads;
-                    hpr[u] = hpw[u] = hps[u] = hpd[u] = (Real)0;
+                    hpr[u] = hpw[u] = hps[u] = (Real)0;
                     if (hp_ok && q < 2 * H) {
                         const bool left = q < H;
                         const int id = left ? a - H + q : b + (q - H);
@@ -1167,7 +1171,6 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                             hpr[u] = ldc(base + k);
                             hpw[u] = ldc(base + XS + k);
                             if (need_s) hps[u] = ldc(base + 2 * XS + k);
-                            hpd[u] = (Real)dinv[id];
                         }
                     }
                 }
@@ -1209,7 +1212,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
         if (is_adj) {
             const double Th = *B.Theta;
             // the source of Theta (Eq. 4.6), or of Theta~ = Theta^p (Eq. 7.5)
-            c.src_scale = C.plt ? (double)C.p / (double)C.Ne : pow(Th, 1.0 - C.p) / (double)C.Ne;
+            c.src_scale = C.plt ? (double)C.p / (double)C.Ne : pow_call(Th, 1.0 - C.p) / (double)C.Ne;
             if (!(Th > 0.0) || !isfinite(Th)) set_status(ctl, -5);
         }
         if (L.kind == F_PRI) {
@@ -1493,6 +1496,9 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                             if (q < len) {
                                 LZ[q] = dv[u] * rv[u];
                                 if (id >= a && id < b) LR[id - a] = rv[u];
+                                // D^{-1} of the halo nodes, behind the tile's own
+                                // (left halo first): fixed for the whole solve
+                                else LR[TS + (q < H ? q : q - (b - a))] = dv[u];
                             }
                         }
                     }
@@ -1623,7 +1629,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                             const int q = threadIdx.x + u * kThreads;
                             if (q < 2 * H) {
                                 const Real sv = first ? hpw[u] : hpw[u] + (Real)be * hps[u];
-                                const Real z = hpd[u] * (hpr[u] - (Real)al * sv);
+                                const Real z = LD[TS + q] * (hpr[u] - (Real)al * sv);
                                 LZ[q < H ? q : (b - lo) + (q - H)] = z;
                             }
                         }
@@ -1641,7 +1647,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                             const Real wh = ldc(base + XS + k);
                             const Real sh = first ? (Real)0 : ldc(base + 2 * XS + k);
                             const Real sv = first ? wh : wh + (Real)be * sh;
-                            z = (Real)dinv[id] * (rh - (Real)al * sv);
+                            z = LD[TS + q] * (rh - (Real)al * sv);
                         }
                         LZ[left ? q : (b - lo) + (q - H)] = z;
                     }
@@ -1953,7 +1959,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                     const double inv = st.fine ? C.inv_NtNe : C.inv_NtauNe;
                     // with G = 0 a fine lane keeps its slice's part of Theta~ instead
                     const double thG = C.plt ? c.theta + tot[0] * inv
-                                             : pow(ipow(c.theta, C.p) + tot[0] * inv, C.inv_p);
+                                             : pow_call(ipow(c.theta, C.p) + tot[0] * inv, C.inv_p);
                     if (L.kind == SWEEP_PRI) {
                         const int n = st.n;
                         const double thu = thG + B.F_th[n] - B.Gk_th[n];
