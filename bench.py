@@ -52,7 +52,7 @@ def traffic_per_launch():
 # The sources k_engine is built from: its kernel, its layouts and the host
 # planner that shapes its launch. The coarse-mesh and filter kernels are not
 # among them.
-ENGINE_SOURCES = ("pt_engine.hip", "pt_gmg.hip", "pt_internal.h", "pt_host.hip")
+ENGINE_SOURCES = ("pt_engine.hip", "pt_gmg.hip", "pt_cm_lane.hip", "pt_internal.h", "pt_host.hip")
 
 
 def sources_sha1() -> str:

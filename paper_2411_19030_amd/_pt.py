@@ -377,7 +377,7 @@ def stats_from_bytes(raw: bytes) -> dict:
 
 
 LANE_KINDS = ["F_PRI", "GK_PRI", "SWEEP_PRI", "COLD_PRI", "F_ADJ", "GK_ADJ", "SWEEP_ADJ",
-              "COLD_ADJ"]
+              "COLD_ADJ", "CM_GK_PRI", "CM_SWEEP_PRI", "CM_GK_ADJ", "CM_SWEEP_ADJ"]
 
 
 def pt_query_trace(prob: Problem, ws, stream=None) -> list:

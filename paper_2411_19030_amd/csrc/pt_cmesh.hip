@@ -10,22 +10,22 @@
 //     output P x, theta' = (theta^p + ||P x||_p^p / (N_tau N_e))^{1/p} (Alg. 1);
 //   G_adj^c(lambda, n): (C_c/dtau + K_c) x = C_c/dtau R lambda + P^T s(T_m),
 //     s the fine source of Eq. 4.6 at m = M(n-1)+1, output P x (Alg. 2).
-// A Parareal pass with these propagators runs the fine propagators of every
-// slice in one engine launch, then on the coarse mesh: the batched steps
-// G(R u^k_n) (one workgroup each), the sequential correction sweep (one
-// workgroup), and the corrected fine states F_n + P(G(u^{k+1}_n) - G(u^k_n))
-// (Eq. 4.10 / Eq. 4.14 with both coarse outputs prolonged by the same linear P).
-// The sensitivity part of the reversed correction is linear in the coarse
-// output difference; it is summed per fine element after the sweep (Eq. 4.16).
+// The batched steps G(R u^k_n) and the sequential correction sweep run as
+// lanes of the engine launch that runs the fine propagators (the coarse-mesh
+// lanes of the engine). This file holds the coarse-mesh set-up (coefficients
+// and assembled stencils), the cold sweep u^0_{n+1} = G(u^0_n) that gives a
+// cold start its guesses, and the kernels after the launch: the corrected fine
+// states F_n + P(G(u^{k+1}_n) - G(u^k_n)) (Eq. 4.10 / Eq. 4.14 with both coarse
+// outputs prolonged by the same linear P) and the sensitivity part of the
+// reversed correction, linear in the coarse output difference and summed per
+// fine element (Eq. 4.16).
 //
-// Each coarse solve is Jacobi-preconditioned CG (Hestenes-Stiefel form) run by
-// one workgroup of 1024 threads, with the true residual checked at the end;
-// reductions are in a fixed order, so results are bitwise reproducible. The
-// solve's vectors sit in LDS when they fit (about 3400 coarse nodes, e.g. the
-// 51^2 mesh of a 100^2 design), else in global memory, with the same
-// arithmetic. A workgroup barrier costs far less than a cross-workgroup one,
-// but one CU's memory path bounds the solve on large coarse meshes (about
-// 58 us per iteration at 129^2 with global vectors).
+// The cold sweep's solves are Jacobi-preconditioned CG (Hestenes-Stiefel form)
+// run by one workgroup of 1024 threads, with the true residual checked at the
+// end; reductions are in a fixed order. The solve's vectors sit in LDS when
+// they fit (about 3400 coarse nodes, e.g. the 51^2 mesh of a 100^2 design),
+// else in global memory, with the same arithmetic. It runs once, before the
+// first cycle of a cold start.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -356,57 +356,13 @@ __device__ __forceinline__ double *crow(double *base, const CoarseMesh &M, int n
     return base + (size_t)n * M.Nc;
 }
 
-// Batched coarse steps G(R u^k_n), n = blockIdx.x + 1 (1 .. N_tau - 1):
-// primal from (in_T[n], in_th[n]) into Gk[n], Gk_th[n]; adjoint from in_L[n]
-// into Gk[n]. One workgroup per step; its vectors in LDS, else in slot n.
+// The cold coarse sweep on one workgroup (vectors in LDS, else slot 0):
+// u^0_{n+1} = G(u^0_n) from u_0 = 0 (primal, with the theta chain into Gk_th)
+// or v^0_{n-1} = G(v^0_n) from v_{N_tau} = 0 (adjoint), outputs into Gk. Each
+// solve starts from its input.
 template <bool LDS>
-__global__ void __launch_bounds__(kCT) k_cm_batched(const EngineDesc *__restrict__ D,
-                                                    CoarseMesh M, int adjoint) {
-    __shared__ double red[2 * 2 * kCW];
-    int par = 0;
-    const Consts &C = D->C;
-    const Bufs &B = D->B;
-    const int n = blockIdx.x + 1;
-    if (B.ctl->status == kStatusOrder) return;  // adjoint with no forward before it
-    const CmVecs V = LDS ? cm_vecs_lds(M) : cm_vecs(M, n);
-    double *x = crow(M.Gk, M, n);
-    if (!adjoint) {
-        const double *u = B.in_T + (size_t)n * C.Nn;
-        const double qn = B.qt[C.M * (n + 1)];
-        auto ru = [&](int I) { return u[fine_of(C, M, I)]; };
-        // R u in the slot's u vector, so the stencil can read it by coarse index
-        for (int I = threadIdx.x; I < M.Nc; I += kCT) V.u[I] = ru(I);
-        __syncthreads();
-        cm_pcg(
-            C, M, B.ctl, V, x, [&](int I) { return cm_row(M, M.C9, V.u, I) + qn * M.fc[I]; },
-            [&](int I) { return V.u[I]; }, red, par);
-        const double th = cm_theta(C, M, B, x, B.in_th[n], red, par);
-        if (threadIdx.x == 0) B.Gk_th[n] = th;
-    } else {
-        const double *l = B.in_L + (size_t)n * C.Nn;
-        const int m = C.M * (n - 1) + 1;
-        const double *Tm = cm_srow(C, B, m);
-        const double scale = pow(*B.Theta, 1.0 - C.p) / (double)C.Ne;
-        for (int I = threadIdx.x; I < M.Nc; I += kCT) V.u[I] = l[fine_of(C, M, I)];
-        __syncthreads();
-        cm_pcg(
-            C, M, B.ctl, V, x,
-            [&](int I) { return cm_row(M, M.C9, V.u, I) + cm_source(C, M, B.mask, Tm, scale, I); },
-            [&](int I) { return V.u[I]; }, red, par);
-    }
-}
-
-// The sequential coarse chain on one workgroup (vectors in LDS, else slot 0).
-// cold = 1: the cold sweep u^0_{n+1} = G(u^0_n) from u_0 = 0 (primal) or
-// v^0_{n-1} = G(v^0_n) from v_{N_tau} = 0 (adjoint), written to Gk.
-// cold = 0: the correction sweep of Eq. 4.10 / Eq. 4.14 on the coarse mesh,
-//   hat u_{n+1} = G(hat u_n) + R F_n - G(R u^k_n), hat u_1 = R F_0,
-// with G(hat u_n) written to Gn (and the theta chain to Gn_th, out_th); the
-// primal reads F_n from S row M(n+1) and theta(F_n) from F_th, the adjoint
-// F_n from FL. Each solve starts from G(u^k_n) + (hat u_n - R u^k_n).
-template <bool LDS>
-__global__ void __launch_bounds__(kCT) k_cm_sweep(const EngineDesc *__restrict__ D,
-                                                  CoarseMesh M, int adjoint, int cold) {
+__global__ void __launch_bounds__(kCT) k_cm_cold(const EngineDesc *__restrict__ D, CoarseMesh M,
+                                                 int adjoint) {
     __shared__ double red[2 * 2 * kCW];
     int par = 0;
     const Consts &C = D->C;
@@ -415,87 +371,33 @@ __global__ void __launch_bounds__(kCT) k_cm_sweep(const EngineDesc *__restrict__
     const CmVecs V = LDS ? cm_vecs_lds(M) : cm_vecs(M, 0);
     const int Nt = C.Ntau;
     double *u = V.u;
+    for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = 0.0;
+    __syncthreads();
     if (!adjoint) {
-        double th;
-        int n0;
-        if (cold) {
-            for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = 0.0;
-            th = 0.0;
-            n0 = 0;
-        } else {
-            const double *F0 = cm_srow(C, B, C.M);
-            for (int I = threadIdx.x; I < M.Nc; I += kCT)
-                u[I] = M.dinv[I] == 0.0 ? 0.0 : F0[fine_of(C, M, I)];
-            th = B.F_th[0];
-            if (threadIdx.x == 0) B.out_th[1] = th;
-            n0 = 1;
-        }
-        __syncthreads();
-        for (int n = n0; n < Nt; ++n) {
+        double th = 0.0;
+        for (int n = 0; n < Nt; ++n) {
             const double qn = B.qt[C.M * (n + 1)];
-            double *x = crow(cold ? M.Gk : M.Gn, M, n);
-            const double *gk = crow(M.Gk, M, n);
-            const double *uk = B.in_T ? B.in_T + (size_t)n * C.Nn : nullptr;
+            double *x = crow(M.Gk, M, n);
             cm_pcg(
                 C, M, B.ctl, V, x, [&](int I) { return cm_row(M, M.C9, u, I) + qn * M.fc[I]; },
-                [&](int I) {
-                    if (cold) return u[I];
-                    return gk[I] + (u[I] - (uk ? uk[fine_of(C, M, I)] : 0.0));
-                },
-                red, par);
-            const double thG = cm_theta(C, M, B, x, th, red, par);
-            if (cold) {
-                if (threadIdx.x == 0) B.Gk_th[n] = thG;
-                th = thG;
-                for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = x[I];
-            } else {
-                th = thG + B.F_th[n] - B.Gk_th[n];
-                if (threadIdx.x == 0) {
-                    B.Gn_th[n] = thG;
-                    B.out_th[n + 1] = th;
-                }
-                const double *Fn = cm_srow(C, B, C.M * (n + 1));
-                for (int I = threadIdx.x; I < M.Nc; I += kCT)
-                    u[I] = M.dinv[I] == 0.0 ? 0.0 : x[I] + Fn[fine_of(C, M, I)] - gk[I];
-            }
+                [&](int I) { return u[I]; }, red, par);
+            th = cm_theta(C, M, B, x, th, red, par);
+            if (threadIdx.x == 0) B.Gk_th[n] = th;
+            for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = x[I];
             __syncthreads();
         }
     } else {
         const double scale = pow(*B.Theta, 1.0 - C.p) / (double)C.Ne;
-        int n0;
-        if (cold) {
-            for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = 0.0;
-            n0 = Nt;
-        } else {
-            const double *FN = B.FL + (size_t)Nt * C.Nn;
-            for (int I = threadIdx.x; I < M.Nc; I += kCT)
-                u[I] = M.dinv[I] == 0.0 ? 0.0 : FN[fine_of(C, M, I)];
-            n0 = Nt - 1;
-        }
-        __syncthreads();
-        for (int n = n0; n >= 1; --n) {
-            const int m = C.M * (n - 1) + 1;
-            const double *Tm = cm_srow(C, B, m);
-            double *x = crow(cold ? M.Gk : M.Gn, M, n);
-            const double *gk = crow(M.Gk, M, n);
-            const double *lk = B.in_L ? B.in_L + (size_t)n * C.Nn : nullptr;
+        for (int n = Nt; n >= 1; --n) {
+            const double *Tm = cm_srow(C, B, C.M * (n - 1) + 1);
+            double *x = crow(M.Gk, M, n);
             cm_pcg(
                 C, M, B.ctl, V, x,
                 [&](int I) {
                     return cm_row(M, M.C9, u, I) + cm_source(C, M, B.mask, Tm, scale, I);
                 },
-                [&](int I) {
-                    if (cold) return u[I];
-                    return gk[I] + (u[I] - (lk ? lk[fine_of(C, M, I)] : 0.0));
-                },
-                red, par);
-            if (cold) {
-                for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = x[I];
-            } else {
-                const double *Fn = B.FL + (size_t)n * C.Nn;
-                for (int I = threadIdx.x; I < M.Nc; I += kCT)
-                    u[I] = M.dinv[I] == 0.0 ? 0.0 : x[I] + Fn[fine_of(C, M, I)] - gk[I];
-            }
+                [&](int I) { return u[I]; }, red, par);
+            for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = x[I];
             __syncthreads();
         }
     }
@@ -608,12 +510,8 @@ int cm_launch(const CoarseMesh &M, dim3 grid, hipStream_t stream, Args... args) 
 }
 
 template <bool LDS>
-struct SweepK {
-    static auto kernel() { return &k_cm_sweep<LDS>; }
-};
-template <bool LDS>
-struct BatchedK {
-    static auto kernel() { return &k_cm_batched<LDS>; }
+struct ColdK {
+    static auto kernel() { return &k_cm_cold<LDS>; }
 };
 
 }  // namespace
@@ -626,23 +524,15 @@ int cm_setup(const EngineDesc *D, const CoarseMesh &M, hipStream_t stream) {
 
 int cm_cold(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
             double *rows, double *th, hipStream_t stream) {
-    const int rc = cm_launch<SweepK>(M, dim3(1), stream, D, M, adjoint ? 1 : 0, 1);
+    const int rc = cm_launch<ColdK>(M, dim3(1), stream, D, M, adjoint ? 1 : 0);
     if (rc != PT_OK) return rc;
     hipLaunchKernelGGL(k_cm_guess, dim3(std::min((Nn + 255) / 256, 1024), Ntau + 1), dim3(256),
                        0, stream, D, M, adjoint ? 1 : 0, rows, th);
     return cm_check();
 }
 
-int cm_batched(const EngineDesc *D, const CoarseMesh &M, int Ntau, bool adjoint,
+int cm_correct(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint, int Ne,
                hipStream_t stream) {
-    if (Ntau < 2) return PT_OK;
-    return cm_launch<BatchedK>(M, dim3(Ntau - 1), stream, D, M, adjoint ? 1 : 0);
-}
-
-int cm_sweep_correct(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
-                     int Ne, hipStream_t stream) {
-    const int rc = cm_launch<SweepK>(M, dim3(1), stream, D, M, adjoint ? 1 : 0, 0);
-    if (rc != PT_OK) return rc;
     hipLaunchKernelGGL(k_cm_correct, dim3(std::min((Nn + 255) / 256, 1024), Ntau), dim3(256), 0,
                        stream, D, M, adjoint ? 1 : 0);
     if (adjoint)

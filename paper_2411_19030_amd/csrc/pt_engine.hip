@@ -627,6 +627,7 @@ __device__ __forceinline__ double sens_term(const Consts &C, const Bufs &B, cons
 }  // namespace
 
 #include "pt_gmg.hip"
+#include "pt_cm_lane.hip"
 
 // ---------------------------------------------------------------------------
 // Setup kernels
@@ -736,9 +737,12 @@ __global__ void k_copy_f64(double *dst, const double *src, size_t n) {
 // ---------------------------------------------------------------------------
 // MULTI: lanes of several designs read their descriptor from D; otherwise the
 // single design's descriptor E1 is a kernel argument (cheaper scalar access).
-template <int NPT, typename Real, bool MULTI>
+// CMESH: the launch holds coarse-mesh lanes (single design only); they run
+// from the uploaded descriptor D.
+template <int NPT, typename Real, bool MULTI, bool CMESH = false>
 __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restrict__ D, Launch S,
                                                      EngineDesc E1) {
+    static_assert(!(MULTI && CMESH), "coarse-mesh lanes run in single-design launches");
     extern __shared__ double lds[];
     __shared__ double red[kWaves * 4];
 
@@ -796,6 +800,24 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
             lane_id = G.lane0 + pos;
         }
         const Lane L = S.lanes[lane_id];
+        if constexpr (CMESH) {
+            if (is_cm_kind(L.kind)) {
+                ctl = E1.B.ctl;
+                const long long r =
+                    cm_lane(D, L.kind, L.slice, rank, g, G.vec, bar, part, nbar,
+                            S.trace + (size_t)lane_id * S.trace_stride, S.trace_stride - TR_HDR);
+                if (r < 0) {
+                    ok = false;
+                    break;
+                }
+                nbar = (unsigned)r;
+                continue;
+            }
+            // no register value of a resident lane outlives its lane: with
+            // them dead at the coarse-mesh call, the call saves none of them
+#pragma unroll
+            for (int k = 0; k < NR; ++k) rp[k] = rr[k] = rw[k] = rs[k] = 0;
+        }
         const EngineDesc &E = [&]() -> const EngineDesc & {
             if constexpr (MULTI) return D[L.design];
             else return E1;
@@ -1181,7 +1203,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
         };
         (void)halo_prefetch;
 
-        const bool is_adj = L.kind >= F_ADJ;
+        const bool is_adj = is_adjoint_kind(L.kind);
         const bool tracer = (rank == 0 && threadIdx.x == 0);
         unsigned long long *trec = S.trace + (size_t)lane_id * S.trace_stride;
         unsigned long long iters_all = 0;

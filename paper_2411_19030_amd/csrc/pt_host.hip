@@ -179,7 +179,7 @@ void carve_design(Carver &c, const pt_problem *p, DesignLayout &L, bool batched)
         L.cm_fc = c.take(d * Nc);
         L.cm_Gk = c.take(d * Nt1 * Nc);
         L.cm_Gn = c.take(d * Nt1 * Nc);
-        L.cm_vec = c.take(d * (size_t)p->n_slices * kCoarseMeshVecs * Nc);
+        L.cm_vec = c.take(d * kCoarseMeshVecs * Nc);
     }
     if (!batched) {
         L.Uprev = c.take(d * Nt1 * Nn);
@@ -556,7 +556,14 @@ int tile_for(int Nn, int nwg, int H, int cap_doubles, int tile_max = 0) {
     return ts;
 }
 
-const void *engine_kernel(bool fp32, int npt, bool multi) {
+const void *engine_kernel(bool fp32, int npt, bool multi, bool cmesh = false) {
+    if (cmesh) {
+        // coarse-mesh launches: resident lanes always take the 8-node form
+        if (fp32) return npt == 0 ? (const void *)k_engine<0, float, false, true>
+                                  : (const void *)k_engine<8, float, false, true>;
+        return npt == 0 ? (const void *)k_engine<0, double, false, true>
+                        : (const void *)k_engine<8, double, false, true>;
+    }
     if (multi) {
         if (fp32) return npt == 0 ? (const void *)k_engine<0, float, true>
                                   : (const void *)k_engine<8, float, true>;
@@ -578,8 +585,8 @@ const void *engine_kernel(bool fp32, int npt, bool multi) {
 
 // Workgroups of the engine that fit on the device at once.
 int engine_capacity(bool fp32, int npt, bool multi, size_t lds_bytes, const Device &dev,
-                    int &cap) {
-    const void *kern = engine_kernel(fp32, npt, multi);
+                    int &cap, bool cmesh = false) {
+    const void *kern = engine_kernel(fp32, npt, multi, cmesh);
     PT_TRY(hip_ok(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds_bytes)));
     int occ = 0;
@@ -599,12 +606,12 @@ static_assert(sizeof(EngineDesc) + sizeof(Launch) + sizeof(void *) <= 4096,
 // nullptr for a multi-design launch that reads D.
 int launch_engine(bool fp32, int npt, const EngineDesc *D, const EngineDesc *single,
                   const Launch &X, int grid, size_t lds_bytes, const Device &dev,
-                  hipStream_t stream) {
+                  hipStream_t stream, bool cmesh = false) {
     const bool multi = single == nullptr;
     int cap = 0;
-    PT_TRY(engine_capacity(fp32, npt, multi, lds_bytes, dev, cap));
+    PT_TRY(engine_capacity(fp32, npt, multi, lds_bytes, dev, cap, cmesh));
     if (cap < grid || grid > kMaxGrid) return PT_ESIZE;
-    const void *kern = engine_kernel(fp32, npt, multi);
+    const void *kern = engine_kernel(fp32, npt, multi, cmesh);
     Launch Xv = X;
     const EngineDesc *Dv = D;
     EngineDesc E1;
@@ -743,8 +750,9 @@ struct LanePlan {
 };
 
 // Runs one single-design engine launch with descriptor D (already uploaded).
+// cm: the coarse mesh of a launch with coarse-mesh lanes (else nullptr).
 int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &plans, void *ws,
-               const Layout &Lay, hipStream_t stream) {
+               const Layout &Lay, hipStream_t stream, const CoarseMesh *cm = nullptr) {
     const Consts &C = E.C;
     Control *ctl = E.B.ctl;
     Device dev;
@@ -779,7 +787,8 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
         for (size_t k = 0; k < plans.size(); ++k) {
             auto &p = plans[k];
             if (p.latency) {
-                nwg[k] = std::max(g_min, std::min(sweep_wgs_res, grid / 4));
+                nwg[k] = p.fixed_nwg > 0 ? std::max(g_min, p.fixed_nwg)
+                                         : std::max(g_min, std::min(sweep_wgs_res, grid / 4));
                 nwg[k] = std::max(1, std::min(nwg[k], max_wg_per_lane));
                 ngroups[k] = p.count;
                 lat_wgs += nwg[k] * p.count;
@@ -846,7 +855,7 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
             auto &p = plans[k];
             if (p.latency) {
                 ngroups[k] = p.count;
-                nwg[k] = std::max(1, std::min(sweep_wgs, grid / 2));
+                nwg[k] = p.fixed_nwg > 0 ? p.fixed_nwg : std::max(1, std::min(sweep_wgs, grid / 2));
             } else if (p.fixed_nwg > 0) {
                 ngroups[k] = (p.queues <= 0 || p.queues > p.count) ? p.count : p.queues;
                 nwg[k] = p.fixed_nwg;
@@ -889,10 +898,19 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
     if (resident) {
         npt = 1;
         while (npt * NT < max_tile) npt *= 2;
+        if (cm) npt = 8;  // the coarse-mesh launches' one resident form
     }
     if (C.gmg && (C.gmg_chunk < 256 || C.gmg_chunk_init < 256)) return PT_EINVAL;
-    const size_t lds_bytes =
+    size_t lds_bytes =
         C.gmg ? gmg_lds_bytes(C) : engine_lds_doubles(max_tile, C.W) * sizeof(double);
+    if (cm) {
+        // a coarse-mesh lane stages two windows of its coarse tile and halo
+        for (size_t k = 0; k < plans.size(); ++k)
+            if (is_cm_kind(plans[k].kind) && plans[k].count > 0) {
+                const size_t tc = ((size_t)cm->Nc + nwg[k] - 1) / nwg[k];
+                lds_bytes = std::max(lds_bytes, 2 * (tc + 2 * ((size_t)cm->Wc + 1)) * sizeof(double));
+            }
+    }
     if (lds_bytes > (size_t)dev.lds_max) return PT_EINVAL;
 
     PlanArgs P{};
@@ -950,7 +968,7 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
     PT_TRY(launch_check());
     PT_TRY(reset_launch_state(ws, Lay.s, 1, stream));
     const Launch X = make_launch(ws, Lay.s, ctl, C.timeout_ticks);
-    return launch_engine(C.fp32 != 0, npt, D, &E, X, grid, lds_bytes, dev, stream);
+    return launch_engine(C.fp32 != 0, npt, D, &E, X, grid, lds_bytes, dev, stream, cm != nullptr);
 }
 
 // Fine lanes of a single-design pass. With checkpoints (or PT_FINE_WGS set)
@@ -1182,106 +1200,98 @@ bool valid_batch(int n, const pt_problem *probs) {
 }
 
 // Passes with coarse propagators on the coarse spatial mesh (PT_COARSE_MESH).
-// Per iteration: one engine launch of every slice's fine propagator from the
-// guesses u^k_n, then on the coarse mesh the batched steps G(R u^k_n) (first
-// warm iteration; later ones reuse the previous sweep's outputs, and a cold
-// start takes them from the cold sweep), the sequential correction sweep, and
-// the corrected fine states. A cold start first runs the coarse cold sweep and
-// prolongs it into the fine guesses.
-int coarse_mesh_forward(const pt_problem *prob, std::vector<EngineDesc> &hd, EngineDesc *D,
-                        const Layout &Lay, void *ws, const double *guess_T,
-                        const double *guess_theta, hipStream_t stream) {
+// Per iteration one engine launch runs every slice's fine propagator from the
+// guesses u^k_n, the batched coarse-mesh steps G(R u^k_n) (first warm
+// iteration, queued with the fine lanes; later iterations reuse the previous
+// sweep's outputs, a cold start the cold sweep's) and the coarse-mesh
+// correction sweep on a group of its own, which follows the slices' flags;
+// the corrected fine states (and the adjoint's coarse-correction
+// sensitivities) follow the launch. A cold start first runs the coarse cold
+// sweep and prolongs it into the fine guesses.
+int cm_sweep_wgs() { return std::max(1, env_int("PT_CM_SWEEP_WGS", 24)); }
+
+int coarse_mesh_pass(const pt_problem *prob, std::vector<EngineDesc> &hd, EngineDesc *D,
+                     const Layout &Lay, void *ws, const double *guess, const double *guess_theta,
+                     bool adjoint, hipStream_t stream) {
     EngineDesc &E = hd[0];
     const Consts &C = E.C;
     Bufs &B = E.B;
     const int Ntau = C.Ntau;
     const size_t Nt1 = (size_t)Ntau + 1, Nn = C.Nn;
-    CoarseMesh M = make_coarse_mesh(ws, Lay.d, prob);
+    CoarseMesh &M = E.cm;
+    M = make_coarse_mesh(ws, Lay.d, prob);
     double *Uprev = at<double>(ws, Lay.d.Uprev), *Uprev_th = at<double>(ws, Lay.d.Uprev_th);
     double *Ga_th = at<double>(ws, Lay.d.Gk_th), *Gb_th = at<double>(ws, Lay.d.Gn_th);
-    if (Ntau > 1) PT_TRY(cm_setup(D, M, stream));
+    if (Ntau > 1) {
+        PT_TRY(upload_descs(hd, D, stream));
+        PT_TRY(cm_setup(D, M, stream));
+    }
+    const bool lead = lead_fine(C, Ntau, false);
     for (int it = 0; it < prob->iterations; ++it) {
         LaunchInfo &I = E.I;
         I = LaunchInfo{};
         I.has_dc = (prob->c0 != prob->cmin) ? 1 : 0;
         I.epoch = 1;
-        B.Gk_th = Ga_th;
-        B.Gn_th = Gb_th;
-        const bool cold0 = guess_T == nullptr && it == 0 && Ntau > 1;
-        const double *inT = it == 0 ? guess_T : Uprev;
-        const double *inth = it == 0 ? guess_theta : Uprev_th;
+        if (!adjoint) {
+            B.Gk_th = Ga_th;
+            B.Gn_th = Gb_th;
+        }
+        const bool cold0 = guess == nullptr && it == 0 && Ntau > 1;
+        const double *in = it == 0 ? guess : Uprev;
+        const double *in_th = it == 0 ? guess_theta : Uprev_th;
         if (cold0) {
+            B.in_L = nullptr;
             B.in_T = nullptr;
             B.in_th = nullptr;
             PT_TRY(upload_descs(hd, D, stream));
-            PT_TRY(cm_cold(D, M, C.Nn, Ntau, false, Uprev, Uprev_th, stream));
-            inT = Uprev;
-            inth = Uprev_th;
+            PT_TRY(cm_cold(D, M, C.Nn, Ntau, adjoint, Uprev, adjoint ? nullptr : Uprev_th,
+                           stream));
+            in = Uprev;
+            in_th = Uprev_th;
         }
-        B.in_T = inT;
-        B.in_th = inth;
+        if (adjoint) {
+            B.in_L = in;
+        } else {
+            B.in_T = in;
+            B.in_th = in_th;
+        }
+        I.gk_lanes = (it == 0 && !cold0 && Ntau > 1) ? 1 : 0;
         PT_TRY(upload_descs(hd, D, stream));
         std::vector<LanePlan> plans;
-        plans.push_back(fine_plan(F_PRI, Ntau, 0, +1, C, prob));
-        PT_TRY(run_engine(E, D, plans, ws, Lay, stream));
+        const int fk = adjoint ? F_ADJ : F_PRI;
+        if (adjoint)
+            plans.push_back(lead ? fine_plan(fk, Ntau - 1, Ntau - 1, -1, C, prob)
+                                 : fine_plan(fk, Ntau, Ntau, -1, C, prob));
+        else
+            plans.push_back(lead ? fine_plan(fk, Ntau - 1, 1, +1, C, prob)
+                                 : fine_plan(fk, Ntau, 0, +1, C, prob));
+        if (I.gk_lanes)
+            plans.push_back({adjoint ? CM_GK_ADJ : CM_GK_PRI, Ntau - 1, adjoint ? Ntau - 1 : 1,
+                             adjoint ? -1 : +1, env_double("PT_GK_WEIGHT", 4.0), false,
+                             env_int("PT_GQUEUES", 0)});
         if (Ntau > 1) {
-            if (it == 0 && !cold0) PT_TRY(cm_batched(D, M, Ntau, false, stream));
-            PT_TRY(cm_sweep_correct(D, M, C.Nn, Ntau, false, C.Ne, stream));
+            plans.push_back({adjoint ? CM_SWEEP_ADJ : CM_SWEEP_PRI, 1, 0, +1, 0.0, true, 0});
+            plans.back().fixed_nwg = cm_sweep_wgs();
+            if (lead) {
+                plans.back().lead_kind = fk;
+                plans.back().lead_slice = adjoint ? Ntau : 0;
+            }
         }
+        PT_TRY(run_engine(E, D, plans, ws, Lay, stream, Ntau > 1 ? &M : nullptr));
+        if (Ntau > 1) PT_TRY(cm_correct(D, M, C.Nn, Ntau, adjoint, C.Ne, stream));
         if (it + 1 < prob->iterations) {
-            hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Uprev, B.out_T,
-                               Nt1 * Nn);
-            hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(256), 0, stream, Uprev_th, B.out_th, Nt1);
+            double *out = adjoint ? B.out_L : B.out_T;
+            hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Uprev, out, Nt1 * Nn);
+            if (!adjoint)
+                hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(256), 0, stream, Uprev_th, B.out_th,
+                                   Nt1);
             PT_TRY(launch_check());
             std::swap(M.Gk, M.Gn);
             std::swap(Ga_th, Gb_th);
         }
     }
-    hipLaunchKernelGGL(k_finalize_fwd, dim3(256, 1), dim3(256), 0, stream, D);
-    return launch_check();
-}
-
-int coarse_mesh_adjoint(const pt_problem *prob, std::vector<EngineDesc> &hd, EngineDesc *D,
-                        const Layout &Lay, void *ws, const double *guess_lambda,
-                        hipStream_t stream) {
-    EngineDesc &E = hd[0];
-    const Consts &C = E.C;
-    Bufs &B = E.B;
-    const int Ntau = C.Ntau;
-    const size_t Nt1 = (size_t)Ntau + 1, Nn = C.Nn;
-    CoarseMesh M = make_coarse_mesh(ws, Lay.d, prob);
-    double *Lprev = at<double>(ws, Lay.d.Uprev);
-    if (Ntau > 1) PT_TRY(cm_setup(D, M, stream));
-    for (int it = 0; it < prob->iterations; ++it) {
-        LaunchInfo &I = E.I;
-        I = LaunchInfo{};
-        I.has_dc = (prob->c0 != prob->cmin) ? 1 : 0;
-        I.epoch = 1;
-        const bool cold0 = guess_lambda == nullptr && it == 0 && Ntau > 1;
-        const double *inL = it == 0 ? guess_lambda : Lprev;
-        if (cold0) {
-            B.in_L = nullptr;
-            PT_TRY(upload_descs(hd, D, stream));
-            PT_TRY(cm_cold(D, M, C.Nn, Ntau, true, Lprev, nullptr, stream));
-            inL = Lprev;
-        }
-        B.in_L = inL;
-        PT_TRY(upload_descs(hd, D, stream));
-        std::vector<LanePlan> plans;
-        plans.push_back(fine_plan(F_ADJ, Ntau, Ntau, -1, C, prob));
-        PT_TRY(run_engine(E, D, plans, ws, Lay, stream));
-        if (Ntau > 1) {
-            if (it == 0 && !cold0) PT_TRY(cm_batched(D, M, Ntau, true, stream));
-            PT_TRY(cm_sweep_correct(D, M, C.Nn, Ntau, true, C.Ne, stream));
-        }
-        if (it + 1 < prob->iterations) {
-            hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Lprev, B.out_L,
-                               Nt1 * Nn);
-            PT_TRY(launch_check());
-            std::swap(M.Gk, M.Gn);
-        }
-    }
-    hipLaunchKernelGGL(k_finalize_adj, dim3(256, 1), dim3(256), 0, stream, D);
+    if (adjoint) hipLaunchKernelGGL(k_finalize_adj, dim3(256, 1), dim3(256), 0, stream, D);
+    else hipLaunchKernelGGL(k_finalize_fwd, dim3(256, 1), dim3(256), 0, stream, D);
     return launch_check();
 }
 
@@ -1405,7 +1415,7 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
         B.out_T = outT;
         B.out_th = outth;
         B.Theta_out = Theta_out;
-        return coarse_mesh_forward(prob, hd, D, Lay, ws, guess_T, guess_theta, stream);
+        return coarse_mesh_pass(prob, hd, D, Lay, ws, guess_T, guess_theta, false, stream);
     }
     for (int it = 0; it < prob->iterations; ++it) {
         LaunchInfo &I = E.I;
@@ -1493,7 +1503,7 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
         B.S = const_cast<double *>(S);
         B.Theta = Theta;
         B.out_L = outL;
-        return coarse_mesh_adjoint(prob, hd, D, Lay, ws, guess_lambda, stream);
+        return coarse_mesh_pass(prob, hd, D, Lay, ws, guess_lambda, nullptr, true, stream);
     }
     for (int it = 0; it < prob->iterations; ++it) {
         LaunchInfo &I = E.I;

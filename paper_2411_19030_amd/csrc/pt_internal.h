@@ -27,8 +27,19 @@ enum LaneKind : int {
     F_ADJ = 4,      // fine adjoint propagator of slice n: M steps (Alg. 2, dt)
     GK_ADJ = 5,     // coarse adjoint step from the guess v^k_n
     SWEEP_ADJ = 6,  // reversed correction sweep
-    COLD_ADJ = 7    // cold coarse sweep v^0_{n-1} = G(v^0_n)
+    COLD_ADJ = 7,   // cold coarse sweep v^0_{n-1} = G(v^0_n)
+    // coarse propagators on the coarse spatial mesh (propagator PT_COARSE_MESH)
+    CM_GK_PRI = 8,     // batched coarse-mesh step G(R u^k_n)
+    CM_SWEEP_PRI = 9,  // correction sweep on the coarse mesh
+    CM_GK_ADJ = 10,    // batched coarse-mesh adjoint step G(R v^k_n)
+    CM_SWEEP_ADJ = 11  // reversed correction sweep on the coarse mesh
 };
+
+__host__ __device__ inline bool is_cm_kind(int kind) { return kind >= CM_GK_PRI; }
+// lanes of the adjoint pass
+__host__ __device__ inline bool is_adjoint_kind(int kind) {
+    return (kind >= F_ADJ && kind <= COLD_ADJ) || kind == CM_GK_ADJ || kind == CM_SWEEP_ADJ;
+}
 
 // Flag slots (one per slice index per producer kind)
 enum FlagKind : int { FL_F = 0, FL_GK = 1, FL_COLD = 2, FL_SWEEP = 3 };
@@ -182,12 +193,29 @@ struct DesignPlan {
     int adjoint;             // lane kinds of the adjoint pass
 };
 
+// Coarse-spatial-mesh propagators (propagator PT_COARSE_MESH): the coarse
+// mesh has nx/2 x ny/2 elements; coarse node (I, J) is fine node (2I, 2J).
+constexpr int kCoarseMeshThreads = 1024;  // the cold sweep's workgroup
+constexpr int kCoarseMeshVecs = 6;        // r, z, p, q, b, u of its solves
+
+struct CoarseMesh {
+    int nxc, nyc, Wc, Nc, Nec;  // elements per side, nodes per row, nodes, elements
+    double *kE, *cE;            // coarse element k and c (means of the fine SIMP values)
+    double *A9;                 // [9][Nc] rows of C_c/dtau + K_c without Dirichlet rows/columns
+    double *C9;                 // [9][Nc] rows of C_c/dtau (Dirichlet rows zero)
+    double *dinv;               // [Nc] 1/diag of A (0 on Dirichlet nodes)
+    double *fc;                 // [Nc] int N_I (0 on Dirichlet nodes)
+    double *Gk, *Gn;            // [Ntau+1][Nc] coarse outputs G(R u^k_n), G(u^{k+1}_n)
+    double *vec;                // [kCoarseMeshVecs][Nc] the cold sweep's solve vectors
+};
+
 // Everything a workgroup needs about one design, read from device memory.
 struct EngineDesc {
     Consts C;
     Bufs B;
     LaunchInfo I;
     DesignPlan plan;
+    CoarseMesh cm;  // coarse spatial mesh (propagator PT_COARSE_MESH), else unused
 };
 
 // Launch-wide arrays shared by every design of one engine launch.
@@ -219,30 +247,12 @@ enum {
     TR_HDR = 12
 };
 
-// Coarse-spatial-mesh propagators (propagator PT_COARSE_MESH): the coarse
-// mesh has nx/2 x ny/2 elements; coarse node (I, J) is fine node (2I, 2J).
-constexpr int kCoarseMeshThreads = 1024;  // one workgroup per coarse solve
-constexpr int kCoarseMeshVecs = 6;        // r, z, p, q, b, u of one solve slot
-
-struct CoarseMesh {
-    int nxc, nyc, Wc, Nc, Nec;  // elements per side, nodes per row, nodes, elements
-    double *kE, *cE;            // coarse element k and c (means of the fine SIMP values)
-    double *A9;                 // [9][Nc] rows of C_c/dtau + K_c without Dirichlet rows/columns
-    double *C9;                 // [9][Nc] rows of C_c/dtau (Dirichlet rows zero)
-    double *dinv;               // [Nc] 1/diag of A (0 on Dirichlet nodes)
-    double *fc;                 // [Nc] int N_I (0 on Dirichlet nodes)
-    double *Gk, *Gn;            // [Ntau+1][Nc] coarse outputs G(R u^k_n), G(u^{k+1}_n)
-    double *vec;                // [Ntau][kCoarseMeshVecs][Nc] solve slots
-};
-
 // Host entry points of the coarse-mesh kernels (pt_cmesh.hip); D is the
 // uploaded single-design descriptor. Each returns PT_OK or PT_EHIP.
 int cm_setup(const EngineDesc *D, const CoarseMesh &M, hipStream_t stream);
 int cm_cold(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
             double *rows, double *th, hipStream_t stream);
-int cm_batched(const EngineDesc *D, const CoarseMesh &M, int Ntau, bool adjoint,
+int cm_correct(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint, int Ne,
                hipStream_t stream);
-int cm_sweep_correct(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
-                     int Ne, hipStream_t stream);
 
 }  // namespace pt
