@@ -187,8 +187,12 @@ __device__ __forceinline__ void block_sum(double (&v)[Q], double *red) {
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
         v[q] = x;
     }
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
+    // per-call address math: a hoisted LDS address is held in a spilled
+    // register, and its reload waits for every store still in flight
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0)
         for (int q = 0; q < Q; ++q) red[wave * Q + q] = v[q];
     lds_sync();
     for (int q = 0; q < Q; ++q) {
@@ -1635,9 +1639,8 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                     const int ppar = (nbar - 1) & 1;  // parity of the previous round
                     int tid = threadIdx.x;
                     asm volatile("" : "+v"(tid));  // per-round index math (not hoisted)
-                    // x of the tile is read and written only by its owning thread
-                    // during the rounds: plain (cached) accesses; leaving the
-                    // rounds releases them before any other workgroup reads x
+                    // x of the tile is read only by its owning thread during
+                    // the rounds (plain loads of its own device-coherent stores)
                     double xo[NR];
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
@@ -1648,7 +1651,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                     if (hp_ok) {
 #pragma unroll
                         for (int u = 0; u < kHP; ++u) {
-                            const int q = threadIdx.x + u * kThreads;
+                            const int q = tid + u * kThreads;
                             if (q < 2 * H) {
                                 const Real sv = first ? hpw[u] : hpw[u] + (Real)be * hps[u];
                                 const Real z = LD[TS + q] * (hpr[u] - (Real)al * sv);
@@ -1686,7 +1689,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                             const Real zi = dk * rr[k];
                             const Real pn = first ? zi : zi + (Real)be * rp[k];
                             const Real sn = first ? rw[k] : rw[k] + (Real)be * rs[k];
-                            X[id] = xo[k] + al * (double)pn;
+                            stc(X + id, xo[k] + al * (double)pn);
                             rr[k] -= (Real)al * sn;
                             rp[k] = pn;
                             rs[k] = sn;
@@ -1816,10 +1819,11 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                 const int par = nbar & 1;
                 // one partial per thread: one thread storing all three reused a
                 // register that an earlier store still read, and waited for it
-                if (threadIdx.x < 3) {
-                    const double v =
-                        threadIdx.x == 0 ? loc[0] : (threadIdx.x == 1 ? loc[1] : loc[2]);
-                    stc(my_part(par) + threadIdx.x, v);
+                int tid3 = threadIdx.x;
+                asm volatile("" : "+v"(tid3));  // per-round address (see block_sum)
+                if (tid3 < 3) {
+                    const double v = tid3 == 0 ? loc[0] : (tid3 == 1 ? loc[1] : loc[2]);
+                    stc(my_part(par) + tid3, v);
                 }
                 ok = barrier(false);
                 if (!ok) break;
@@ -1842,25 +1846,18 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                     const bool check =
                         !trunc && (C.fp32 ? (c.iter < C.max_iter)
                                           : (C.verify && rn <= C.rtol * c.bnorm && c.restarts < 3));
+                    // (the rounds store x device-coherently, and the round's
+                    // barrier has drained those stores: the residual and the
+                    // adjoint post-solve phase read the neighbours' x at once)
                     if (check) {
                         // recompute r = b - A x in FP64, restart CG if needed
                         c.verifying = true;
                         c.restarts += 1;
                         c.phase = PH_INIT;
-                        if constexpr (NPT > 0) {
-                            // the residual reads the neighbours' x: release the rounds' stores
-                            ok = barrier(true);
-                            if (!ok) break;
-                        }
                     } else {
                         c.phase = PH_POST;
                         if (!trunc && rn > C.rtol * c.bnorm && rank == 0 && threadIdx.x == 0)
                             set_status(ctl, -4);
-                        if constexpr (NPT > 0) {
-                            // adjoint POST reads the neighbours' x
-                            ok = barrier(true);
-                            if (!ok) break;
-                        }
                     }
                 } else {
                     const double gnew = tot[0];
