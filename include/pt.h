@@ -18,7 +18,7 @@
  * both row-major with x fastest. All arrays are contiguous FP64.
  *
  * Ownership: every array argument is a DEVICE pointer owned by the caller,
- * except the two fields of pt_problem marked HOST. The library allocates no
+ * except the fields of pt_problem marked HOST. The library allocates no
  * device memory: all scratch lives in the caller's workspace `ws`
  * (pt_workspace_bytes), or, for pt_cycle_noalloc only, in one static device
  * array per GPU. Apart from that array it keeps no global state between
@@ -73,6 +73,46 @@ enum { PT_STORE_ALL = 0, PT_CHECKPOINT = 1 };
  * pt_parareal_forward). */
 enum { PT_PARAREAL = 0, PT_PLT = 1, PT_COARSE_MESH = 2 };
 
+/* Execution settings of the calls: launch shapes, lane scheduling, solver
+ * details and diagnostics. None of them changes the method; the solver
+ * details change CG paths (results within cg_rtol), the others results at
+ * most by rounding. pt_default_tuning fills the defaults (in brackets below);
+ * pt_problem.tuning == NULL means the defaults. The library reads no
+ * environment variables. */
+typedef struct pt_tuning {
+    int32_t wg_per_cu;         /* engine workgroups per compute unit                        (1)  */
+    int32_t resident;          /* -1: resident groups (vectors in registers) where they pay;    */
+                               /*  0: streaming groups only; 1: resident wherever they fit  (-1) */
+    int32_t resident_npt_max;  /* nodes per thread of a resident tile, 1..8                 (8)  */
+    int32_t sweep_wgs;         /* workgroups of a correction-sweep group; 0: by problem size (0) */
+    int32_t cm_sweep_wgs;      /* workgroups of a coarse-mesh correction-sweep group        (24) */
+    int32_t fine_wgs;          /* > 0: fine lanes on groups of this many workgroups, alike  */
+                               /* in both passes; 0: by problem size                         (0) */
+    int32_t fine_groups;       /* > 0: groups for the fine lanes; 0: by their work share    (0)  */
+    int32_t gk_groups;         /* > 0: groups for the batched coarse steps; 0: by share     (0)  */
+    double gk_weight;          /* work of a batched coarse step relative to a fine step     (4)  */
+    int32_t lead_fine;         /* 1: a sweep's group first runs the slice the sweep starts  */
+                               /* from                                                       (1) */
+    int32_t shared_queue;      /* 1: resident fine and batched coarse lanes share a queue   (1)  */
+    int32_t tile_max;          /* largest streaming tile in nodes, >= 256                   (4096) */
+    int32_t ck_slots;          /* PT_CHECKPOINT: fine-lane groups (recompute slots), >= 1   (16) */
+    int32_t extrap;            /* 1: fine steps start from 2 T_{j-1} - T_{j-2}               (0) */
+    int32_t sweep_x0;          /* 1: a sweep step starts from G(u^k_n) + (u^{k+1}_n - u^k_n),  */
+                               /* 0: from u^{k+1}_n                                          (1) */
+    int32_t verify;            /* 1: the true residual decides a solve's convergence       (1)  */
+    double inner_rtol;         /* PT_FP32_REFINE: residual reduction of one FP32 solve     (1e-5) */
+    int32_t gmg_tail;          /* PT_GMG: levels of at most this many nodes run on one     */
+                               /* workgroup                                                (4096) */
+    int32_t gmg_sweeps;        /* PT_GMG: smoothing pairs on the coarsest level            (16)  */
+    double gmg_omega;          /* PT_GMG: smoother damping times 1/(Gershgorin bound)      (1.3) */
+    int32_t cm_lds;            /* PT_COARSE_MESH: 1: the cold coarse sweep keeps its        */
+                               /* vectors in LDS when they fit                               (1) */
+    int32_t phase_timers;      /* 1: per-round phase times in the lane trace of FP64 launches */
+                               /* without coarse-mesh lanes (slows the rounds)              (0) */
+    double wait_timeout_s;     /* a device wait gives up after this long (PT_EHIP);        */
+                               /* 0: 20 s (60 s in batched launches)                         (0) */
+} pt_tuning;
+
 typedef struct pt_problem {
     int32_t nx, ny;            /* elements along x and y, >= 1                                   */
     double k0, kmin, pk;       /* k(rho) = kmin + (k0 - kmin) rho^pk            (Eq. 2.6)         */
@@ -102,6 +142,7 @@ typedef struct pt_problem {
     int32_t coarse_iters;      /* 0: coarse steps solved to cg_rtol; k > 0: a cheaper coarse     */
                                /* propagator, exactly k Jacobi-PCG iterations from the step's    */
                                /* input state (PT_FP64, PT_JACOBI and PT_PARAREAL only)         */
+    const pt_tuning *tuning;   /* HOST, optional execution settings; NULL: pt_default_tuning    */
 } pt_problem;
 
 typedef struct pt_stats {
@@ -120,6 +161,9 @@ size_t pt_workspace_bytes(const pt_problem *prob);
 
 /* Host-side argument check only; returns PT_OK or PT_EINVAL. */
 int pt_validate(const pt_problem *prob);
+
+/* The default execution settings (see pt_tuning). PT_EINVAL if out is NULL. */
+int pt_default_tuning(pt_tuning *out);
 
 /* Bytes of the state array S: N_t rows of N_n doubles (PT_STORE_ALL) or 2 N_tau
  * rows (PT_CHECKPOINT); 0 if the problem is invalid. */
@@ -320,7 +364,7 @@ typedef struct pt_batch_tuning {
  * propagator != PT_PARAREAL (PT_PLT, PT_COARSE_MESH) or coarse_iters != 0. */
 size_t pt_batched_workspace_bytes(int n, const pt_problem *probs);
 
-/* The built-in worker shapes for n designs (environment overrides included). */
+/* The built-in worker shapes for n designs. */
 int pt_batch_default_tuning(int n, pt_batch_tuning *out);
 
 /*

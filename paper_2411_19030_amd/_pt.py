@@ -26,11 +26,40 @@ PT_JACOBI, PT_GMG = 0, 1
 PT_STORE_ALL, PT_CHECKPOINT = 0, 1
 PT_PARAREAL, PT_PLT, PT_COARSE_MESH = 0, 1, 2
 
-EXPORTS = ["pt_workspace_bytes", "pt_state_bytes", "pt_validate", "pt_parareal_forward", "pt_parareal_adjoint",
+EXPORTS = ["pt_workspace_bytes", "pt_state_bytes", "pt_validate", "pt_default_tuning",
+           "pt_parareal_forward", "pt_parareal_adjoint",
            "pt_sensitivities", "pt_query_status", "pt_query_trace", "pt_strerror",
            "pt_batched_workspace_bytes", "pt_batch_default_tuning", "pt_parareal_batched",
            "pt_batched_status", "pt_autotune_batched", "pt_filter_validate",
            "pt_filter_projection", "pt_filter_projection_backward", "pt_cycle_noalloc"]
+
+
+class PtTuning(ctypes.Structure):
+    """Mirror of pt_tuning (execution settings; defaults from pt_default_tuning)."""
+    _fields_ = [
+        ("wg_per_cu", ctypes.c_int32), ("resident", ctypes.c_int32),
+        ("resident_npt_max", ctypes.c_int32), ("sweep_wgs", ctypes.c_int32),
+        ("cm_sweep_wgs", ctypes.c_int32), ("fine_wgs", ctypes.c_int32),
+        ("fine_groups", ctypes.c_int32), ("gk_groups", ctypes.c_int32),
+        ("gk_weight", ctypes.c_double), ("lead_fine", ctypes.c_int32),
+        ("shared_queue", ctypes.c_int32), ("tile_max", ctypes.c_int32),
+        ("ck_slots", ctypes.c_int32), ("extrap", ctypes.c_int32),
+        ("sweep_x0", ctypes.c_int32), ("verify", ctypes.c_int32),
+        ("inner_rtol", ctypes.c_double), ("gmg_tail", ctypes.c_int32),
+        ("gmg_sweeps", ctypes.c_int32), ("gmg_omega", ctypes.c_double),
+        ("cm_lds", ctypes.c_int32), ("phase_timers", ctypes.c_int32),
+        ("wait_timeout_s", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def default_tuning() -> dict:
+    """The library's default execution settings as a dict."""
+    t = PtTuning()
+    _check(load_library().pt_default_tuning(ctypes.byref(t)), "pt_default_tuning")
+    return t.as_dict()
 
 
 class PtProblem(ctypes.Structure):
@@ -47,6 +76,7 @@ class PtProblem(ctypes.Structure):
         ("storage", ctypes.c_int32), ("bc", ctypes.c_int32),
         ("dirichlet_mask", ctypes.POINTER(ctypes.c_uint8)),
         ("propagator", ctypes.c_int32), ("coarse_iters", ctypes.c_int32),
+        ("tuning", ctypes.POINTER(PtTuning)),
     ]
 
 
@@ -109,6 +139,8 @@ def load_library(path: str = LIB_PATH):
     lib.pt_validate.restype = ctypes.c_int
     lib.pt_state_bytes.argtypes = [P]
     lib.pt_state_bytes.restype = ctypes.c_size_t
+    lib.pt_default_tuning.argtypes = [ctypes.POINTER(PtTuning)]
+    lib.pt_default_tuning.restype = ctypes.c_int
     lib.pt_parareal_forward.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.pt_parareal_forward.restype = ctypes.c_int
     lib.pt_parareal_adjoint.argtypes = [P, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
@@ -182,6 +214,7 @@ class Problem:
     bc: object = "left_centre"  # name or boolean/uint8 node mask
     propagator: int = PT_PARAREAL  # PT_PARAREAL, PT_PLT or PT_COARSE_MESH
     coarse_iters: int = 0       # > 0: coarse steps are this many CG iterations
+    tuning: Optional[dict] = None  # execution settings over the defaults (pt_tuning fields)
     _keep: list = field(default_factory=list, repr=False, compare=False)
 
     @property
@@ -221,6 +254,18 @@ class Problem:
             c.dirichlet_mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         c.propagator = int(self.propagator)
         c.coarse_iters = int(self.coarse_iters)
+        if self.tuning:
+            t = PtTuning()
+            _check(load_library().pt_default_tuning(ctypes.byref(t)), "pt_default_tuning")
+            names = {k for k, _ in PtTuning._fields_}
+            for k, v in self.tuning.items():
+                if k not in names:
+                    raise ValueError(f"unknown tuning field {k!r}")
+                setattr(t, k, v)
+            self._keep.append(t)
+            c.tuning = ctypes.pointer(t)
+        else:
+            c.tuning = ctypes.POINTER(PtTuning)()
         return c
 
 

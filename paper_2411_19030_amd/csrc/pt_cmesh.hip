@@ -478,11 +478,9 @@ __global__ void k_cm_sens(const EngineDesc *__restrict__ D, CoarseMesh M) {
 
 int cm_check() { return hipGetLastError() == hipSuccess ? PT_OK : PT_EHIP; }
 
-// LDS-resident solve vectors when they fit the workgroup's LDS;
-// PT_CM_LDS=0 keeps them in global memory at every size.
-size_t cm_lds_bytes(const CoarseMesh &M) {
-    const char *e = getenv("PT_CM_LDS");
-    if (e && atoi(e) == 0) return 0;
+// LDS-resident solve vectors when allowed and they fit the workgroup's LDS.
+size_t cm_lds_bytes(const CoarseMesh &M, bool use_lds) {
+    if (!use_lds) return 0;
     int dev = 0, cap = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -494,8 +492,8 @@ size_t cm_lds_bytes(const CoarseMesh &M) {
 
 // Launches kernel K<true> with the vectors in LDS when they fit, else K<false>.
 template <template <bool> class K, typename... Args>
-int cm_launch(const CoarseMesh &M, dim3 grid, hipStream_t stream, Args... args) {
-    const size_t lds = cm_lds_bytes(M);
+int cm_launch(const CoarseMesh &M, bool use_lds, dim3 grid, hipStream_t stream, Args... args) {
+    const size_t lds = cm_lds_bytes(M, use_lds);
     if (lds > 0) {
         auto kern = K<true>::kernel();
         if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -523,8 +521,8 @@ int cm_setup(const EngineDesc *D, const CoarseMesh &M, hipStream_t stream) {
 }
 
 int cm_cold(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
-            double *rows, double *th, hipStream_t stream) {
-    const int rc = cm_launch<ColdK>(M, dim3(1), stream, D, M, adjoint ? 1 : 0);
+            double *rows, double *th, bool use_lds, hipStream_t stream) {
+    const int rc = cm_launch<ColdK>(M, use_lds, dim3(1), stream, D, M, adjoint ? 1 : 0);
     if (rc != PT_OK) return rc;
     hipLaunchKernelGGL(k_cm_guess, dim3(std::min((Nn + 255) / 256, 1024), Ntau + 1), dim3(256),
                        0, stream, D, M, adjoint ? 1 : 0, rows, th);

@@ -742,11 +742,14 @@ __global__ void k_copy_f64(double *dst, const double *src, size_t n) {
 // MULTI: lanes of several designs read their descriptor from D; otherwise the
 // single design's descriptor E1 is a kernel argument (cheaper scalar access).
 // CMESH: the launch holds coarse-mesh lanes (single design only); they run
-// from the uploaded descriptor D.
-template <int NPT, typename Real, bool MULTI, bool CMESH = false>
+// from the uploaded descriptor D. TIMED: per-round phase times go to the lane
+// trace (a separate instance: reading the clock is a scalar memory access, and
+// the waits for it and the timers' registers cost a round about a microsecond).
+template <int NPT, typename Real, bool MULTI, bool CMESH = false, bool TIMED = false>
 __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restrict__ D, Launch S,
                                                      EngineDesc E1) {
     static_assert(!(MULTI && CMESH), "coarse-mesh lanes run in single-design launches");
+    static_assert(!(TIMED && (MULTI || CMESH)), "phase timers in plain single-design launches");
     extern __shared__ double lds[];
     __shared__ double red[kWaves * 4];
 
@@ -775,10 +778,13 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
     for (int k = 0; k < NR; ++k) rp[k] = rr[k] = rw[k] = rs[k] = 0;
     Real *XCH = reinterpret_cast<Real *>(S.xch);
 
-    // phase timers of the current lane (kept by thread 0 of rank 0, written to the trace)
+    // phase timers of the current lane (kept by thread 0 of rank 0, written to
+    // the trace) in the TIMED instance
+    constexpr bool timers = TIMED;
     unsigned long long t_work = 0, t_bar = 0, t_red = 0, t_flag = 0;
-    long long t_mark = now_ticks();
-    const bool timer = (rank == 0 && threadIdx.x == 0);
+    long long t_mark = 0;
+    if constexpr (timers) t_mark = now_ticks();
+    const bool timer = timers && (rank == 0 && threadIdx.x == 0);
     auto my_part = [&](int parity) { return part + ((size_t)parity * kMaxGroup + rank) * 4; };
     auto all_part = [&](int parity) { return part + (size_t)parity * kMaxGroup * 4; };
 
@@ -896,33 +902,43 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
         (void)publish;
         auto barrier = [&](bool release) -> bool {
             ++nbar;
-            const long long t0 = now_ticks();
-            const bool r = group_barrier(bar, nbar * (unsigned)g, ctl, tmo, release);
-            const long long t1 = now_ticks();
-            if (timer) {
-                t_work += t0 - t_mark;
-                t_bar += t1 - t0;
-                t_mark = t1;
+            if constexpr (!timers) {
+                return group_barrier(bar, nbar * (unsigned)g, ctl, tmo, release);
+            } else {
+                const long long t0 = now_ticks();
+                const bool r = group_barrier(bar, nbar * (unsigned)g, ctl, tmo, release);
+                const long long t1 = now_ticks();
+                if (timer) {
+                    t_work += t0 - t_mark;
+                    t_bar += t1 - t0;
+                    t_mark = t1;
+                }
+                return r;
             }
-            return r;
         };
         auto mark_red = [&]() {
-            const long long t = now_ticks();
-            if (timer) {
-                t_red += t - t_mark;
-                t_mark = t;
+            if constexpr (timers) {
+                const long long t = now_ticks();
+                if (timer) {
+                    t_red += t - t_mark;
+                    t_mark = t;
+                }
             }
         };
         auto waitf = [&](int idx) -> bool {
-            const long long t0 = now_ticks();
-            const bool r = wait_flag(B.flags, idx, I.epoch, ctl, tmo);
-            const long long t1 = now_ticks();
-            if (timer) {
-                t_work += t0 - t_mark;
-                t_flag += t1 - t0;
-                t_mark = t1;
+            if constexpr (!timers) {
+                return wait_flag(B.flags, idx, I.epoch, ctl, tmo);
+            } else {
+                const long long t0 = now_ticks();
+                const bool r = wait_flag(B.flags, idx, I.epoch, ctl, tmo);
+                const long long t1 = now_ticks();
+                if (timer) {
+                    t_work += t0 - t_mark;
+                    t_flag += t1 - t0;
+                    t_mark = t1;
+                }
+                return r;
             }
-            return r;
         };
 
         // One preconditioned round of CG with the multigrid preconditioner B
@@ -1218,7 +1234,7 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
             trec[TR_NWG] = g;
             trec[TR_TILE] = TS;
             trec[TR_START] = (unsigned long long)now_ticks();
-            t_mark = now_ticks();
+            if constexpr (timers) t_mark = now_ticks();
         }
 
         Ctl c;

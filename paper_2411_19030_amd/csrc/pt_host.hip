@@ -24,14 +24,52 @@ constexpr long long kGmgLdsBytes = 158 * 1024;  // dynamic LDS of the multigrid 
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-int env_int(const char *name, int dflt) {
-    const char *e = getenv(name);
-    return e ? atoi(e) : dflt;
+pt_tuning default_settings() {
+    pt_tuning t;
+    memset(&t, 0, sizeof(t));
+    t.wg_per_cu = 1;
+    t.resident = -1;
+    t.resident_npt_max = 8;
+    t.sweep_wgs = 0;
+    t.cm_sweep_wgs = 24;
+    t.fine_wgs = 0;
+    t.fine_groups = 0;
+    t.gk_groups = 0;
+    t.gk_weight = 4.0;
+    t.lead_fine = 1;
+    t.shared_queue = 1;
+    t.tile_max = 4096;
+    t.ck_slots = 16;
+    t.extrap = 0;
+    t.sweep_x0 = 1;
+    t.verify = 1;
+    t.inner_rtol = 1e-5;
+    t.gmg_tail = 4096;
+    t.gmg_sweeps = 16;
+    t.gmg_omega = 1.3;
+    t.cm_lds = 1;
+    t.phase_timers = 0;
+    t.wait_timeout_s = 0.0;
+    return t;
 }
 
-double env_double(const char *name, double dflt) {
-    const char *e = getenv(name);
-    return e ? atof(e) : dflt;
+// The problem's execution settings (its own, or the defaults).
+pt_tuning tuning_of(const pt_problem *p) { return p->tuning ? *p->tuning : default_settings(); }
+
+bool bool01(int v) { return v == 0 || v == 1; }
+
+bool valid_settings(const pt_tuning &t) {
+    return t.wg_per_cu >= 1 && t.wg_per_cu <= 4 && t.resident >= -1 && t.resident <= 1 &&
+           t.resident_npt_max >= 1 && t.resident_npt_max <= 8 && t.sweep_wgs >= 0 &&
+           t.sweep_wgs <= kMaxGroup && t.cm_sweep_wgs >= 1 && t.cm_sweep_wgs <= kMaxGroup &&
+           t.fine_wgs >= 0 && t.fine_wgs <= kMaxGroup && t.fine_groups >= 0 &&
+           t.gk_groups >= 0 && t.gk_weight > 0.0 && isfinite(t.gk_weight) &&
+           bool01(t.lead_fine) && bool01(t.shared_queue) && t.tile_max >= 256 &&
+           t.ck_slots >= 1 && bool01(t.extrap) && bool01(t.sweep_x0) && bool01(t.verify) &&
+           t.inner_rtol > 0.0 && t.inner_rtol < 1.0 && t.gmg_tail >= 0 && t.gmg_sweeps >= 1 &&
+           t.gmg_sweeps <= 1000 && t.gmg_omega > 0.0 && isfinite(t.gmg_omega) &&
+           bool01(t.cm_lds) && bool01(t.phase_timers) && t.wait_timeout_s >= 0.0 &&
+           isfinite(t.wait_timeout_s);
 }
 
 
@@ -74,6 +112,7 @@ bool valid_problem(const pt_problem *p) {
     if (p->propagator == PT_COARSE_MESH && ((p->nx % 2) || (p->ny % 2) || p->coarse_iters != 0))
         return false;
     if (p->coarse_iters < 0 || p->coarse_iters > 100000) return false;
+    if (p->tuning && !valid_settings(*p->tuning)) return false;
     if (p->coarse_iters > 0 &&
         (p->precision != PT_FP64 || p->propagator != PT_PARAREAL || p->precond != PT_JACOBI))
         return false;
@@ -112,7 +151,7 @@ Hierarchy hierarchy(const pt_problem *p) {
 // Checkpointed storage: fine adjoint lanes run on at most ck_slots groups,
 // each with scratch for the M-2 states its slice recomputes.
 int ck_slots(const pt_problem *p) {
-    return std::max(1, std::min(p->n_slices, env_int("PT_CK_SLOTS", 16)));
+    return std::max(1, std::min(p->n_slices, tuning_of(p).ck_slots));
 }
 
 size_t state_rows(const pt_problem *p) {
@@ -300,11 +339,12 @@ Consts make_consts(const pt_problem *p) {
     C.M = p->n_steps / p->n_slices;
     C.p = p->pnorm;
     C.max_iter = p->max_iter;
-    C.verify = getenv("PT_VERIFY") ? atoi(getenv("PT_VERIFY")) : 1;
-    C.extrap = getenv("PT_EXTRAP") ? atoi(getenv("PT_EXTRAP")) : 0;
+    const pt_tuning T = tuning_of(p);
+    C.verify = T.verify;
+    C.extrap = T.extrap;
     C.fp32 = p->precision == PT_FP32_REFINE ? 1 : 0;
     C.max_restarts = 40;
-    C.inner_rtol = getenv("PT_INNER_RTOL") ? atof(getenv("PT_INNER_RTOL")) : 1e-5;
+    C.inner_rtol = T.inner_rtol;
     C.hx = 1.0 / p->nx;
     C.hy = 1.0 / p->ny;
     const double rx = C.hy / C.hx, ry = C.hx / C.hy;
@@ -323,9 +363,7 @@ Consts make_consts(const pt_problem *p) {
     C.inv_NtauNe = 1.0 / ((double)p->n_slices * (double)C.Ne);
     C.inv_p = 1.0 / p->pnorm;
     // a device wait gives up after this many seconds (100 MHz realtime clock)
-    double tmo = 20.0;
-    if (const char *e = getenv("PT_WAIT_TIMEOUT_S")) tmo = atof(e);
-    if (!(tmo > 0.0)) tmo = 20.0;
+    const double tmo = T.wait_timeout_s > 0.0 ? T.wait_timeout_s : 20.0;
     C.timeout_ticks = (long long)(tmo * 1e8);
     C.k0 = p->k0;
     C.kmin = p->kmin;
@@ -342,15 +380,15 @@ Consts make_consts(const pt_problem *p) {
     for (int l = 0; l < kMaxLevels; ++l) C.gmg_off[l] = h.off[l];
     C.gmg_nodes = h.nodes;
     // levels with more nodes than this are smoothed by the whole group
-    const long long tail = env_int("PT_GMG_TAIL", 4096);
+    const long long tail = T.gmg_tail;
     C.gmg_Lg = 0;
     for (int l = 0; l < h.L; ++l)
         if ((long long)((p->nx >> l) + 1) * ((p->ny >> l) + 1) > tail) C.gmg_Lg = l + 1;
     // an odd count leaves the coarsest solution in the second buffer
-    C.gmg_tail_sweeps = 2 * std::max(1, env_int("PT_GMG_SWEEPS", 16)) + 1;
-    C.gmg_omega = env_double("PT_GMG_OMEGA", 1.3);
+    C.gmg_tail_sweeps = 2 * T.gmg_sweeps + 1;
+    C.gmg_omega = T.gmg_omega;
     C.ckpt = p->storage == PT_CHECKPOINT ? 1 : 0;
-    C.sweep_x0 = env_int("PT_SWEEP_X0", 1);
+    C.sweep_x0 = T.sweep_x0;
     C.plt = p->propagator == PT_PLT ? 1 : 0;
     C.coarse_iters = p->coarse_iters;
     if (C.gmg || C.ckpt) C.extrap = 0;
@@ -547,16 +585,19 @@ int lds_cap_doubles(const Device &dev) {
 
 // Streaming-mode tile: the group's share of the nodes, cut to what fits LDS
 // and to tile_max (0: the built-in 4096).
-int tile_for(int Nn, int nwg, int H, int cap_doubles, int tile_max = 0) {
+int tile_for(int Nn, int nwg, int H, int cap_doubles, int tile_max) {
     int ts = (Nn + nwg - 1) / nwg;
     ts = (ts + 255) / 256 * 256;
     while (ts > 256 && engine_lds_doubles(ts, H - 1) > (size_t)cap_doubles) ts -= 256;
-    ts = std::min(ts, std::max(256, tile_max > 0 ? tile_max : env_int("PT_TILE_MAX", 4096)));
+    ts = std::min(ts, std::max(256, tile_max > 0 ? tile_max : 4096));
     ts = std::max(ts, 256);
     return ts;
 }
 
-const void *engine_kernel(bool fp32, int npt, bool multi, bool cmesh = false) {
+const void *engine_kernel(bool fp32, int npt, bool multi, bool cmesh = false, bool timed = false) {
+    if (timed)  // FP64 single-design launches without coarse-mesh lanes; resident: 8 nodes
+        return npt == 0 ? (const void *)k_engine<0, double, false, false, true>
+                        : (const void *)k_engine<8, double, false, false, true>;
     if (cmesh) {
         // coarse-mesh launches: resident lanes always take the 8-node form
         if (fp32) return npt == 0 ? (const void *)k_engine<0, float, false, true>
@@ -585,8 +626,8 @@ const void *engine_kernel(bool fp32, int npt, bool multi, bool cmesh = false) {
 
 // Workgroups of the engine that fit on the device at once.
 int engine_capacity(bool fp32, int npt, bool multi, size_t lds_bytes, const Device &dev,
-                    int &cap, bool cmesh = false) {
-    const void *kern = engine_kernel(fp32, npt, multi, cmesh);
+                    int &cap, bool cmesh = false, bool timed = false) {
+    const void *kern = engine_kernel(fp32, npt, multi, cmesh, timed);
     PT_TRY(hip_ok(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds_bytes)));
     int occ = 0;
@@ -606,12 +647,12 @@ static_assert(sizeof(EngineDesc) + sizeof(Launch) + sizeof(void *) <= 4096,
 // nullptr for a multi-design launch that reads D.
 int launch_engine(bool fp32, int npt, const EngineDesc *D, const EngineDesc *single,
                   const Launch &X, int grid, size_t lds_bytes, const Device &dev,
-                  hipStream_t stream, bool cmesh = false) {
+                  hipStream_t stream, bool cmesh = false, bool timed = false) {
     const bool multi = single == nullptr;
     int cap = 0;
-    PT_TRY(engine_capacity(fp32, npt, multi, lds_bytes, dev, cap, cmesh));
+    PT_TRY(engine_capacity(fp32, npt, multi, lds_bytes, dev, cap, cmesh, timed));
     if (cap < grid || grid > kMaxGrid) return PT_ESIZE;
-    const void *kern = engine_kernel(fp32, npt, multi, cmesh);
+    const void *kern = engine_kernel(fp32, npt, multi, cmesh, timed);
     Launch Xv = X;
     const EngineDesc *Dv = D;
     EngineDesc E1;
@@ -752,28 +793,31 @@ struct LanePlan {
 // Runs one single-design engine launch with descriptor D (already uploaded).
 // cm: the coarse mesh of a launch with coarse-mesh lanes (else nullptr).
 int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &plans, void *ws,
-               const Layout &Lay, hipStream_t stream, const CoarseMesh *cm = nullptr) {
+               const Layout &Lay, const pt_tuning &T, hipStream_t stream,
+               const CoarseMesh *cm = nullptr) {
     const Consts &C = E.C;
     Control *ctl = E.B.ctl;
     Device dev;
     PT_TRY(device_info(dev));
     const int H = C.W + 1;
     const int lds_cap_d = lds_cap_doubles(dev);
-    int grid = dev.cus * std::max(1, env_int("PT_WG_PER_CU", 1));
+    int grid = dev.cus * T.wg_per_cu;
+    // per-round phase times: FP64 launches without coarse-mesh lanes only
+    const bool timed = T.phase_timers != 0 && !C.fp32 && !cm;
     // sweep group: 40 workgroups. A resident sweep of full solves to a tight
     // tolerance is the longest lane of the pass: it gets about 1200 nodes per
     // workgroup within 40..56 (measured best at 256^2 and 100^2 with rtol
     // 1e-10); shorter sweeps (truncated or loose solves) leave the fine lanes
     // critical, and there more sweep workgroups only slow the fine lanes
-    const int sweep_wgs = env_int("PT_SWEEP_WGS", 40);
+    const int sweep_wgs = T.sweep_wgs > 0 ? T.sweep_wgs : 40;
     const bool long_sweep = C.coarse_iters == 0 && C.rtol < 1e-9;
-    const int sweep_wgs_res = env_int(
-        "PT_SWEEP_WGS", long_sweep ? std::min(56, std::max(40, C.Nn / 1200)) : 40);
+    const int sweep_wgs_res =
+        T.sweep_wgs > 0 ? T.sweep_wgs : long_sweep ? std::min(56, std::max(40, C.Nn / 1200)) : 40;
 
     const int NT = kThreads;
-    const int res_npt_max = std::max(1, std::min(8, env_int("PT_RES_NPT", 8)));
+    const int res_npt_max = T.resident_npt_max;
     const int g_min = (C.Nn + NT * res_npt_max - 1) / (NT * res_npt_max);
-    bool resident = env_int("PT_RESIDENT", 1) != 0 && g_min <= grid / 4 &&
+    bool resident = T.resident != 0 && g_min <= grid / 4 &&
                     (C.Nn + g_min - 1) / g_min >= H && !C.gmg && !C.ckpt;
     // a tile must be at least one halo (H nodes) long
     const int max_wg_per_lane = std::max(1, C.Nn / H);
@@ -804,7 +848,7 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
         // streaming form (all lanes at once, HBM-bound) ahead
         int lanes = 0;
         for (const auto &p : plans) lanes += p.latency ? 0 : p.count;
-        if (lat_wgs == 0 && avail < lanes && env_int("PT_RESIDENT", -1) != 1) resident = false;
+        if (lat_wgs == 0 && avail < lanes && T.resident != 1) resident = false;
     }
     if (resident) {
         int nq = 0;
@@ -881,7 +925,7 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
         }
         for (size_t k = 0; k < plans.size(); ++k) {
             per_group[k] = (plans[k].count + ngroups[k] - 1) / ngroups[k];
-            tile[k] = tile_for(C.Nn, nwg[k], H, lds_cap_d);
+            tile[k] = tile_for(C.Nn, nwg[k], H, lds_cap_d, T.tile_max);
         }
     }
     int used = 0, max_tile = 256, total_groups = 0;
@@ -898,7 +942,7 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
     if (resident) {
         npt = 1;
         while (npt * NT < max_tile) npt *= 2;
-        if (cm) npt = 8;  // the coarse-mesh launches' one resident form
+        if (cm || timed) npt = 8;  // the one resident form of these launches
     }
     if (C.gmg && (C.gmg_chunk < 256 || C.gmg_chunk_init < 256)) return PT_EINVAL;
     size_t lds_bytes =
@@ -919,7 +963,7 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
     // resident fine and batched coarse lanes of one shape: one shared queue in
     // sweep order instead of private lists (balances lanes of unequal length)
     int qa = -1, qb = -1;
-    if (resident && env_int("PT_SHARED_QUEUE", 1) != 0) {
+    if (resident && T.shared_queue != 0) {
         for (size_t k = 0; k < plans.size(); ++k) {
             if (plans[k].latency || plans[k].count == 0) continue;
             if (qa < 0) qa = (int)k;
@@ -968,7 +1012,8 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
     PT_TRY(launch_check());
     PT_TRY(reset_launch_state(ws, Lay.s, 1, stream));
     const Launch X = make_launch(ws, Lay.s, ctl, C.timeout_ticks);
-    return launch_engine(C.fp32 != 0, npt, D, &E, X, grid, lds_bytes, dev, stream, cm != nullptr);
+    return launch_engine(C.fp32 != 0, npt, D, &E, X, grid, lds_bytes, dev, stream, cm != nullptr,
+                         timed);
 }
 
 // Fine lanes of a single-design pass. With checkpoints (or PT_FINE_WGS set)
@@ -978,8 +1023,9 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
 // ck_slots.
 LanePlan fine_plan(int kind, int count, int slice0, int dir, const Consts &C,
                    const pt_problem *p) {
-    LanePlan lp{kind, count, slice0, dir, (double)C.M, false, env_int("PT_FQUEUES", 0)};
-    const int fixed = env_int("PT_FINE_WGS", 0);
+    const pt_tuning T = tuning_of(p);
+    LanePlan lp{kind, count, slice0, dir, (double)C.M, false, T.fine_groups};
+    const int fixed = T.fine_wgs;
     if (C.ckpt || fixed > 0) {
         lp.queues = ck_slots(p);
         lp.fixed_nwg = fixed > 0 ? fixed : 8;
@@ -991,9 +1037,9 @@ LanePlan fine_plan(int kind, int count, int slice0, int dir, const Consts &C,
 // (F_0, or the last slice in the adjoint); its group runs that slice itself
 // rather than waiting for a fine group. Not with a fixed fine-lane shape
 // (checkpoints), where both passes must run every fine slice alike.
-bool lead_fine(const Consts &C, int Ntau, bool plt) {
-    if (plt || Ntau < 2 || C.ckpt || env_int("PT_FINE_WGS", 0) > 0) return false;
-    return env_int("PT_LEAD_FINE", 1) != 0;
+bool lead_fine(const Consts &C, int Ntau, bool plt, const pt_tuning &T) {
+    if (plt || Ntau < 2 || C.ckpt || T.fine_wgs > 0) return false;
+    return T.lead_fine != 0;
 }
 
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
@@ -1081,12 +1127,12 @@ __global__ void k_build_groups(GroupArgs A, Group *groups, int *wg_group) {
 
 pt_batch_tuning default_tuning(int n) {
     pt_batch_tuning t{};
-    t.fine_wgs = env_int("PT_BATCH_FINE_WGS", 2);
-    t.sweep_wgs = env_int("PT_BATCH_SWEEP_WGS", 16);
-    t.sweep_groups = env_int("PT_BATCH_SWEEP_GROUPS", std::max(1, std::min(n, 8)));
-    t.resident = env_int("PT_BATCH_RESIDENT", 0);
-    t.grid = env_int("PT_BATCH_GRID", 0);
-    t.tile_max = env_int("PT_BATCH_TILE_MAX", 0);
+    t.fine_wgs = 2;
+    t.sweep_wgs = 16;
+    t.sweep_groups = std::max(1, std::min(n, 8));
+    t.resident = 0;
+    t.grid = 0;
+    t.tile_max = 0;
     return t;
 }
 
@@ -1208,8 +1254,6 @@ bool valid_batch(int n, const pt_problem *probs) {
 // the corrected fine states (and the adjoint's coarse-correction
 // sensitivities) follow the launch. A cold start first runs the coarse cold
 // sweep and prolongs it into the fine guesses.
-int cm_sweep_wgs() { return std::max(1, env_int("PT_CM_SWEEP_WGS", 24)); }
-
 int coarse_mesh_pass(const pt_problem *prob, std::vector<EngineDesc> &hd, EngineDesc *D,
                      const Layout &Lay, void *ws, const double *guess, const double *guess_theta,
                      bool adjoint, hipStream_t stream) {
@@ -1226,7 +1270,8 @@ int coarse_mesh_pass(const pt_problem *prob, std::vector<EngineDesc> &hd, Engine
         PT_TRY(upload_descs(hd, D, stream));
         PT_TRY(cm_setup(D, M, stream));
     }
-    const bool lead = lead_fine(C, Ntau, false);
+    const pt_tuning T = tuning_of(prob);
+    const bool lead = lead_fine(C, Ntau, false, T);
     for (int it = 0; it < prob->iterations; ++it) {
         LaunchInfo &I = E.I;
         I = LaunchInfo{};
@@ -1245,7 +1290,7 @@ int coarse_mesh_pass(const pt_problem *prob, std::vector<EngineDesc> &hd, Engine
             B.in_th = nullptr;
             PT_TRY(upload_descs(hd, D, stream));
             PT_TRY(cm_cold(D, M, C.Nn, Ntau, adjoint, Uprev, adjoint ? nullptr : Uprev_th,
-                           stream));
+                           T.cm_lds != 0, stream));
             in = Uprev;
             in_th = Uprev_th;
         }
@@ -1267,17 +1312,16 @@ int coarse_mesh_pass(const pt_problem *prob, std::vector<EngineDesc> &hd, Engine
                                  : fine_plan(fk, Ntau, 0, +1, C, prob));
         if (I.gk_lanes)
             plans.push_back({adjoint ? CM_GK_ADJ : CM_GK_PRI, Ntau - 1, adjoint ? Ntau - 1 : 1,
-                             adjoint ? -1 : +1, env_double("PT_GK_WEIGHT", 4.0), false,
-                             env_int("PT_GQUEUES", 0)});
+                             adjoint ? -1 : +1, T.gk_weight, false, T.gk_groups});
         if (Ntau > 1) {
             plans.push_back({adjoint ? CM_SWEEP_ADJ : CM_SWEEP_PRI, 1, 0, +1, 0.0, true, 0});
-            plans.back().fixed_nwg = cm_sweep_wgs();
+            plans.back().fixed_nwg = T.cm_sweep_wgs;
             if (lead) {
                 plans.back().lead_kind = fk;
                 plans.back().lead_slice = adjoint ? Ntau : 0;
             }
         }
-        PT_TRY(run_engine(E, D, plans, ws, Lay, stream, Ntau > 1 ? &M : nullptr));
+        PT_TRY(run_engine(E, D, plans, ws, Lay, T, stream, Ntau > 1 ? &M : nullptr));
         if (Ntau > 1) PT_TRY(cm_correct(D, M, C.Nn, Ntau, adjoint, C.Ne, stream));
         if (it + 1 < prob->iterations) {
             double *out = adjoint ? B.out_L : B.out_T;
@@ -1342,6 +1386,12 @@ extern "C" {
 
 int pt_validate(const pt_problem *prob) { return valid_problem(prob) ? PT_OK : PT_EINVAL; }
 
+int pt_default_tuning(pt_tuning *out) {
+    if (!out) return PT_EINVAL;
+    *out = default_settings();
+    return PT_OK;
+}
+
 size_t pt_workspace_bytes(const pt_problem *prob) {
     if (!valid_problem(prob)) return 0;
     return layout(prob).total;
@@ -1379,6 +1429,7 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
     const Layout Lay = layout(prob);
     if (ws_bytes < Lay.total) return PT_ENOMEM;
     const Consts C = make_consts(prob);
+    const pt_tuning T = tuning_of(prob);
     const size_t Nn = C.Nn, Nt1 = C.Ntau + 1;
     const size_t sz_U = Nt1 * Nn * sizeof(double), sz_S = state_rows(prob) * Nn * sizeof(double);
     if (guess_T) {
@@ -1438,12 +1489,11 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
         PT_TRY(upload_descs(hd, D, stream));
         std::vector<LanePlan> plans;
         // the sweep cannot start before F_0: its group runs F_0 itself
-        const bool lead = lead_fine(C, Ntau, plt);
+        const bool lead = lead_fine(C, Ntau, plt, T);
         plans.push_back(lead ? fine_plan(F_PRI, Ntau - 1, 1, +1, C, prob)
                              : fine_plan(F_PRI, Ntau, 0, +1, C, prob));
         if (I.gk_lanes)
-            plans.push_back({GK_PRI, Ntau - 1, 1, +1, env_double("PT_GK_WEIGHT", 4.0), false,
-                             env_int("PT_GQUEUES", 0)});
+            plans.push_back({GK_PRI, Ntau - 1, 1, +1, T.gk_weight, false, T.gk_groups});
         if (I.cold) plans.push_back({COLD_PRI, 1, 0, +1, 0.0, true, 0});
         if (Ntau > 1 && !plt) {
             plans.push_back({SWEEP_PRI, 1, 0, +1, 0.0, true, 0});
@@ -1452,7 +1502,7 @@ int pt_parareal_forward(const pt_problem *prob, const double *rho, const double 
                 plans.back().lead_slice = 0;
             }
         }
-        PT_TRY(run_engine(E, D, plans, ws, Lay, stream));
+        PT_TRY(run_engine(E, D, plans, ws, Lay, T, stream));
         if (it + 1 < prob->iterations) {
             hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Uprev, outT, Nt1 * Nn);
             if (!plt)
@@ -1474,6 +1524,7 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
     const Layout Lay = layout(prob);
     if (ws_bytes < Lay.total) return PT_ENOMEM;
     const Consts C = make_consts(prob);
+    const pt_tuning T = tuning_of(prob);
     const size_t Nn = C.Nn, Nt1 = C.Ntau + 1;
     const size_t sz_U = Nt1 * Nn * sizeof(double);
     if (guess_lambda) {
@@ -1521,12 +1572,11 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
         PT_TRY(upload_descs(hd, D, stream));
         std::vector<LanePlan> plans;
         // the reversed sweep consumes slices from N_tau downwards
-        const bool lead = lead_fine(C, Ntau, plt);
+        const bool lead = lead_fine(C, Ntau, plt, T);
         plans.push_back(lead ? fine_plan(F_ADJ, Ntau - 1, Ntau - 1, -1, C, prob)
                              : fine_plan(F_ADJ, Ntau, Ntau, -1, C, prob));
         if (I.gk_lanes)
-            plans.push_back({GK_ADJ, Ntau - 1, Ntau - 1, -1, env_double("PT_GK_WEIGHT", 4.0),
-                             false, env_int("PT_GQUEUES", 0)});
+            plans.push_back({GK_ADJ, Ntau - 1, Ntau - 1, -1, T.gk_weight, false, T.gk_groups});
         if (I.cold) plans.push_back({COLD_ADJ, 1, 0, +1, 0.0, true, 0});
         if (Ntau > 1 && !plt) {
             plans.push_back({SWEEP_ADJ, 1, 0, +1, 0.0, true, 0});
@@ -1535,7 +1585,7 @@ int pt_parareal_adjoint(const pt_problem *prob, const double *rho, const double 
                 plans.back().lead_slice = Ntau;
             }
         }
-        PT_TRY(run_engine(E, D, plans, ws, Lay, stream));
+        PT_TRY(run_engine(E, D, plans, ws, Lay, T, stream));
         if (it + 1 < prob->iterations) {
             hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, stream, Lprev, outL, Nt1 * Nn);
             PT_TRY(launch_check());
@@ -1661,7 +1711,8 @@ int batched_cycle(int n, const pt_problem *probs, const double *const *rho, int 
         const DesignLayout &L = Lay.d[k];
         E.C = make_consts(&probs[k]);
         // lanes of later designs may wait seconds for the shared sweep workers
-        if (!getenv("PT_WAIT_TIMEOUT_S")) E.C.timeout_ticks = (long long)(60.0 * 1e8);
+        if (!(tuning_of(&probs[k]).wait_timeout_s > 0.0))
+            E.C.timeout_ticks = (long long)(60.0 * 1e8);
         E.B = make_bufs(ws, L, Lay.s, k);
         E.B.rho = rho[k];
         E.B.S = at<double>(ws, L.S);

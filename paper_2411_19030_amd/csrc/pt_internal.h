@@ -240,6 +240,7 @@ struct Launch {
 // every step. Ticks are the 100 MHz s_memrealtime clock.
 enum {
     TR_KIND = 0, TR_SLICE, TR_NWG, TR_TILE, TR_ROUNDS, TR_ITERS, TR_START,
+    // phase times (launches with phase timers, else 0):
     TR_T_WORK,    // ticks between the end of one barrier and the arrival at the next
     TR_T_BAR,     // ticks inside group barriers (drain + arrival + wait)
     TR_T_RED,     // ticks reading partial sums after barriers
@@ -251,7 +252,7 @@ enum {
 // uploaded single-design descriptor. Each returns PT_OK or PT_EHIP.
 int cm_setup(const EngineDesc *D, const CoarseMesh &M, hipStream_t stream);
 int cm_cold(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
-            double *rows, double *th, hipStream_t stream);
+            double *rows, double *th, bool use_lds, hipStream_t stream);
 int cm_correct(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint, int Ne,
                hipStream_t stream);
 

@@ -22,7 +22,7 @@ def gpu_problem(cfg: dict):
     kw = {k: cfg[k] for k in ("nx", "ny", "n_steps", "n_slices")}
     for k in ("k0", "kmin", "pk", "c0", "cmin", "pc", "q", "t_final", "pnorm", "iterations",
               "cg_rtol", "max_iter", "bc", "precision", "precond", "storage", "propagator",
-              "coarse_iters"):
+              "coarse_iters", "tuning"):
         if k in cfg:
             kw[k] = cfg[k]
     return Problem(**kw)

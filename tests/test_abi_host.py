@@ -127,8 +127,36 @@ def test_struct_layout_matches_header():
     assert offs["q_t"] == 64 and offs["t_final"] == 72 and offs["n_steps"] == 80
     assert offs["cg_rtol"] == 96 and offs["max_iter"] == 104
     assert offs["dirichlet_mask"] == 128 and offs["propagator"] == 136
-    assert offs["coarse_iters"] == 140
-    assert ctypes.sizeof(PtProblem) == 144
+    assert offs["coarse_iters"] == 140 and offs["tuning"] == 144
+    assert ctypes.sizeof(PtProblem) == 152
+
+
+def test_tuning_layout_matches_header():
+    """pt_tuning: natural alignment, doubles at 8-byte offsets."""
+    T = _pt.PtTuning
+    offs = {name: getattr(T, name).offset for name, _ in T._fields_}
+    assert offs["wg_per_cu"] == 0 and offs["gk_weight"] == 32 and offs["lead_fine"] == 40
+    assert offs["verify"] == 64 and offs["inner_rtol"] == 72 and offs["gmg_tail"] == 80
+    assert offs["gmg_omega"] == 88 and offs["cm_lds"] == 96 and offs["phase_timers"] == 100
+    assert offs["wait_timeout_s"] == 104 and ctypes.sizeof(T) == 112
+
+
+def test_default_tuning_and_its_validation(lib):
+    d = _pt.default_tuning()
+    assert d["wg_per_cu"] == 1 and d["resident"] == -1 and d["verify"] == 1
+    assert d["phase_timers"] == 0 and d["tile_max"] == 4096 and d["gk_weight"] == 4.0
+    assert lib.pt_default_tuning(None) == _pt.PT_EINVAL
+    assert lib.pt_validate(ctypes.byref(base(tuning=dict(resident=0)).to_c())) == _pt.PT_OK
+    assert lib.pt_validate(ctypes.byref(base(tuning=dict(phase_timers=1)).to_c())) == _pt.PT_OK
+    for bad in (dict(wg_per_cu=0), dict(resident=2), dict(resident_npt_max=9),
+                dict(gk_weight=0.0), dict(tile_max=128), dict(ck_slots=0), dict(verify=2),
+                dict(inner_rtol=1.0), dict(gmg_omega=float("nan")), dict(phase_timers=-1),
+                dict(wait_timeout_s=-1.0), dict(cm_sweep_wgs=0)):
+        c = base(tuning=bad).to_c()
+        assert lib.pt_validate(ctypes.byref(c)) == _pt.PT_EINVAL, bad
+        assert lib.pt_workspace_bytes(ctypes.byref(c)) == 0, bad
+    with pytest.raises(ValueError):
+        base(tuning=dict(no_such_field=1)).to_c()
 
 
 def _batch(lib, probs, rho=None, grads=None, theta=0x3000, ws=0x10000000, nbytes=None,

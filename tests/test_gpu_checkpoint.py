@@ -64,11 +64,10 @@ def test_checkpoint_fp64_against_oracle(gpu, nx, ny, Nt, Ntau):
     assert max(e.values()) <= 1e-10
 
 
-def test_checkpoint_warm_and_few_slots(gpu, monkeypatch):
+def test_checkpoint_warm_and_few_slots(gpu):
     """Warm restart (guesses from the oracle's cold cycle), with fewer scratch
     slots than slices so that groups run several fine adjoint lanes each."""
-    monkeypatch.setenv("PT_CK_SLOTS", "3")
-    cfg = _cfg()
+    cfg = dict(_cfg(), tuning=dict(ck_slots=3))
     rho = density_uniform_noise(32, 32, 3)
     cold = run_oracle(cfg, rho)
     rho2 = np.clip(rho + 0.01 * density_uniform_noise(32, 32, 8, 0.0, 1.0), 0, 1)
@@ -82,12 +81,11 @@ def test_checkpoint_warm_and_few_slots(gpu, monkeypatch):
 
 
 @pytest.mark.parametrize("precond", [0, 1])
-def test_checkpoint_bitwise_equals_store_all(gpu, monkeypatch, precond):
+def test_checkpoint_bitwise_equals_store_all(gpu, precond):
     """Same fine-lane shape in both runs: the recomputed states are the stored
     ones, so lambda and dTheta/drho agree bit for bit."""
-    monkeypatch.setenv("PT_FINE_WGS", "4")
-    monkeypatch.setenv("PT_RESIDENT", "0")
-    cfg = _cfg(nx=48, ny=40, n_steps=60, n_slices=6, cg_rtol=1e-10, precond=precond)
+    cfg = _cfg(nx=48, ny=40, n_steps=60, n_slices=6, cg_rtol=1e-10, precond=precond,
+               tuning=dict(fine_wgs=4, resident=0))
     rho = density_uniform_noise(48, 40, 21)
     ck = run_gpu(cfg, rho, with_status=True)
     sa = run_gpu(dict(cfg, storage=0), rho, with_status=True)

@@ -75,9 +75,8 @@ def test_truncated_coarse_csimp_timevarying(gpu):
            density_uniform_noise(20, 20, 31, 0.5, 0.4))
 
 
-def test_truncated_coarse_streaming_engine(gpu, monkeypatch):
-    monkeypatch.setenv("PT_RESIDENT", "0")
-    _check(_cfg(nx=48, ny=40, n_steps=60, n_slices=6, coarse_iters=10),
+def test_truncated_coarse_streaming_engine(gpu):
+    _check(_cfg(nx=48, ny=40, n_steps=60, n_slices=6, coarse_iters=10, tuning=dict(resident=0)),
            density_uniform_noise(48, 40, 33))
 
 

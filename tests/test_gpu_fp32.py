@@ -53,19 +53,18 @@ def test_fp32_refine_ragged(gpu, nx, ny, Nt, Ntau):
     assert e["Theta"] <= 1e-6 and max(e.values()) <= 1e-5
 
 
-def test_fp32_refine_streaming_mode(gpu, monkeypatch):
+def test_fp32_refine_streaming_mode(gpu):
     """The streaming engine (vectors through HBM, FP32 storage) on the same problem."""
-    monkeypatch.setenv("PT_RESIDENT", "0")
-    cfg = _cfg(nx=40, ny=40, n_steps=32, n_slices=8)
+    cfg = _cfg(nx=40, ny=40, n_steps=32, n_slices=8, tuning=dict(resident=0))
     rho = density_uniform_noise(40, 40, 17)
     e = compare(run_gpu(cfg, rho), run_oracle(cfg, rho))
     assert e["Theta"] <= 1e-6 and max(e.values()) <= 1e-5
 
 
-def test_fp64_streaming_mode(gpu, monkeypatch):
+def test_fp64_streaming_mode(gpu):
     """The FP64 streaming engine meets the FP64 bar too."""
-    monkeypatch.setenv("PT_RESIDENT", "0")
-    cfg = _cfg(nx=40, ny=40, n_steps=32, n_slices=8, precision=0, cg_rtol=1e-13)
+    cfg = _cfg(nx=40, ny=40, n_steps=32, n_slices=8, precision=0, cg_rtol=1e-13,
+               tuning=dict(resident=0))
     rho = density_uniform_noise(40, 40, 17)
     e = compare(run_gpu(cfg, rho), run_oracle(cfg, rho))
     assert max(e.values()) <= 1e-10

@@ -6,8 +6,8 @@ FP64 bar (1e-10 at cg_rtol 1e-13). The FP32 inner solve with FP64 refinement
 must meet 1e-5, and 1e-6 on Theta. The tests cover:
 - the default split (levels above 4096 nodes smoothed by the whole group, the
   rest by one workgroup);
-- every level by the group (PT_GMG_TAIL=0);
-- every level by one workgroup (a large PT_GMG_TAIL);
+- every level by the group (tuning gmg_tail = 0);
+- every level by one workgroup (a large gmg_tail);
 - grids that stop coarsening early or do not coarsen at all (odd sides).
 
 Also checked: the multigrid solves need far fewer CG iterations than Jacobi
@@ -40,11 +40,11 @@ def _check(cfg, rho, bar, theta_bar=None):
     return g["status"]
 
 
-@pytest.mark.parametrize("tail", [None, "0", "100000"])
-def test_gmg_fp64_64(gpu, monkeypatch, tail):
-    if tail is not None:
-        monkeypatch.setenv("PT_GMG_TAIL", tail)
-    _check(_cfg(), density_uniform_noise(64, 64, 11), 1e-10)
+@pytest.mark.parametrize("tail", [None, 0, 100000])
+def test_gmg_fp64_64(gpu, tail):
+    # every level on the whole group (0), the default split, every level on one workgroup
+    cfg = _cfg() if tail is None else dict(_cfg(), tuning=dict(gmg_tail=tail))
+    _check(cfg, density_uniform_noise(64, 64, 11), 1e-10)
 
 
 @pytest.mark.parametrize("nx,ny,Nt,Ntau", [(48, 40, 30, 5), (37, 23, 24, 6), (128, 32, 32, 4)])

@@ -6,13 +6,14 @@ run of the PLT form (fine solves only) in both passes; under it that run is
 unchanged and reports no problem. The coarse solves (dtau = M dt, a stiffer
 system) need more iterations, so a pass with coarse solves under the same cap
 must report PT_ENOCONV from its status block, with every output still written
-and finite: the engine's coarse lanes (exact G) and the one-workgroup
-coarse-mesh solver.
+and finite: the engine's coarse lanes, with exact G and on the coarse mesh.
+Also here: call-order errors (PT_ESTATE), and the lane trace's optional
+per-round phase times.
 """
 import numpy as np
 import pytest
 
-from tests.gpu_helpers import gpu_problem
+from tests.gpu_helpers import gpu_problem, run_gpu
 from workloads import density_uniform_noise
 
 pytestmark = pytest.mark.gpu
@@ -105,3 +106,21 @@ def test_call_order_violations_report_estate(gpu, prop):
     cyc.adjoint(rho)
     cyc.sensitivities(rho)
     assert cyc.status()["status"] == 0
+
+
+def test_phase_timers_only_when_asked_for_and_results_unchanged(gpu):
+    """The lane trace carries per-round phase times only with the phase_timers
+    setting; the clock reads change no result (bitwise), and the always-on
+    part of the trace (rounds, iterations, step times) is there either way."""
+    cfg = _cfg()
+    rho = density_uniform_noise(32, 32, 5)
+    off = run_gpu(cfg, rho, with_status=True, with_trace=True)
+    on = run_gpu(dict(cfg, tuning=dict(phase_timers=1)), rho, with_status=True,
+                 with_trace=True)
+    for k in ("S", "uT", "utheta", "lam", "grad"):
+        assert np.array_equal(off[k], on[k]), k
+    assert all(r["barrier_us"] == 0 and r["work_us"] == 0 for r in off["trace"])
+    assert sum(r["barrier_us"] for r in on["trace"]) > 0
+    assert sum(r["work_us"] for r in on["trace"]) > 0
+    for tr in (off["trace"], on["trace"]):
+        assert all(r["rounds"] > 0 and r["step_end_us"] for r in tr)
