@@ -86,6 +86,9 @@ def parse():
                     help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (counter calibration)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="with --workload batch_fp32_64: run pt_autotune_batched on the batch "
+                         "(FP32+refine) and print the shape it picks (the source of BATCH_TUNING)")
     return ap.parse_args()
 
 
@@ -448,6 +451,50 @@ def sequential_reference(prob, rho, repeats=3) -> dict:
     return {"ms_per_cycle": ms, "Theta": float(cyc.Theta), "status": cyc.status()["status"]}
 
 
+def centre_trace(base, rho, Ntau=10) -> dict:
+    """The temperature at the domain centre over t (Fig. 3, Sec. 4.3): the
+    sequential method (one slice), and one cold Parareal iteration with N_tau
+    slices as vanilla Parareal returns it (the corrected coarse points u_n only)
+    and as the modified Parareal does (every fine state: the corrected coarse
+    points and, between them, the fine propagators' states F(u^0)). Errors are
+    against the sequential temperatures; the modified form's coarse points are
+    the vanilla ones (the same corrected states)."""
+    import dataclasses
+
+    import numpy as np
+
+    from paper_2411_19030_amd.cycle import Cycle
+    dev = rho.device
+    W = base.nx + 1
+    node = (base.ny // 2) * W + base.nx // 2
+    Nt = base.n_steps
+    M = Nt // Ntau
+    seq = Cycle(dataclasses.replace(base, n_slices=1, iterations=1), dev)
+    seq.forward(rho)
+    par = Cycle(dataclasses.replace(base, n_slices=Ntau, iterations=1), dev)
+    par.forward(rho)
+    ts = np.concatenate([[0.0], seq.S[:, node].cpu().numpy()])
+    tm = np.concatenate([[0.0], par.S[:, node].cpu().numpy()])
+    tv = par.uT[:, node].cpu().numpy()
+    coarse = np.arange(Ntau + 1) * M
+    fine = np.setdiff1d(np.arange(Nt + 1), coarse)
+    peak = float(np.max(np.abs(ts)))
+    st = [seq.status()["status"], par.status()["status"]]
+    del seq, par
+    r6 = lambda a: [float(f"{x:.6g}") for x in a]
+    return {"figure": "Fig. 3 (Sec. 4.3)", "node": [base.nx // 2, base.ny // 2],
+            "n_slices": Ntau, "iterations": 1, "guess": "cold (coarse sweep)",
+            "t_sequential_and_modified": r6(np.arange(Nt + 1) / Nt),
+            "t_vanilla": r6(coarse / Nt),
+            "sequential": r6(ts), "modified": r6(tm), "vanilla": r6(tv),
+            "max_err_vanilla_coarse_points": float(np.max(np.abs(tv - ts[coarse]))) / peak,
+            "max_err_modified_intermediate_points": float(np.max(np.abs(tm[fine] - ts[fine])))
+            / peak,
+            "errors_relative_to": "max |T_seq| at the node",
+            "vanilla_equals_modified_at_coarse_points": bool(np.array_equal(tv, tm[coarse])),
+            "status": st}
+
+
 def paper_sweep(slices=(5, 10, 20, 30), max_iters=8, repeats=1) -> dict:
     """The paper's preliminary experiment (Sec. 5.2-5.3) on its test case: for
     N_tau in {5, 10, 20, 30} and 1..8 Parareal iterations, cold guesses from the
@@ -498,6 +545,7 @@ def paper_sweep(slices=(5, 10, 20, 30), max_iters=8, repeats=1) -> dict:
                        "sensitivity_error", "ms_per_cycle", "speedup", "status"],
            "rows": []}
     del seq
+    out["fig3_centre_trace"] = centre_trace(base, rho)
     for prop in (0, 1):
         for Ntau in slices:
             for it in range(1, max_iters + 1):
@@ -604,20 +652,50 @@ def one_shot_chain(n_cycles=30, Ntau=30) -> dict:
             "summary": summary, "rows": rows}
 
 
-# Worker shapes of the 64-design batch chosen by pt_autotune_batched on the
-# MI355X (coordinate descent over fine/sweep workgroups and sweep workers).
-BATCH_TUNING = {"fine_wgs": 4, "sweep_wgs": 8, "sweep_groups": 8, "resident": 0, "grid": 0}
+# Worker shape of the 64-design batch (FP32+refine, cg_rtol 1e-7) picked by
+# pt_autotune_batched on one MI355X: `python bench.py --workload batch_fp32_64
+# --autotune` (coordinate descent over resident/streaming groups, fine and
+# sweep workgroups, sweep workers and the streaming tile; median of 3 warm
+# cycles per shape from the same saved guesses).
+BATCH_TUNING = {"fine_wgs": 4, "sweep_wgs": 8, "sweep_groups": 8, "resident": 0, "grid": 0,
+                "tile_max": 0}
 
 
-def batch_compare(rtol=1e-7, ref_rtol=1e-12, accuracy=1e-6) -> dict:
+def batch_autotune(rtol=1e-7) -> dict:
+    """pt_autotune_batched on the 64-design batch (FP32+refine): the shape it
+    picks, its warm-cycle time and the built-in shape's, and oracle-free checks
+    that the tuned shape ran cleanly."""
+    import torch
+
+    from paper_2411_19030_amd import Problem
+    from paper_2411_19030_amd.batched import BatchedCycle
+    from workloads import batch_designs
+
+    dev = torch.device("cuda:0")
+    ds = batch_designs()
+    rhos = [torch.tensor(d["rho"], device=dev) for d in ds]
+    probs = [Problem(nx=d["nx"], ny=d["ny"], n_steps=d["n_steps"], n_slices=d["n_slices"],
+                     pnorm=8, cg_rtol=rtol, max_iter=20000, precision=1) for d in ds]
+    cyc = BatchedCycle(probs, dev)
+    t0 = time.perf_counter()
+    best, ms, ms0 = cyc.autotune(rhos, progress=lambda shape, v: print(
+        "autotune", shape, f"{v:.1f} ms", file=sys.stderr, flush=True))
+    return {"workload": "batch_fp32_64", "tuned": best, "tuned_ms": ms, "default_ms": ms0,
+            "tuner_s": time.perf_counter() - t0}
+
+
+def batch_compare(rtol=1e-7, ref_rtol=1e-12, accuracy=1e-6, replays=5) -> dict:
     """The 64-design workload (sides 64..512, 16..64 slices of 16 steps, seeded
     densities): one cycle of every design. Forms, each timed on a warm cycle
     after a cold one:
-    * batched FP32 + FP64 refinement: all designs in one launch per pass;
+    * batched FP32 + FP64 refinement in the tuned shape: all designs in one
+      launch per pass; timed eagerly and as the replay of the warm cycle
+      captured in a HIP graph (median of `replays`; each replay is the next
+      warm cycle, from the guesses the previous one saved);
     * plain FP64: one design after another through the single-design calls;
     * reference: batched FP64 at cg_rtol 1e-12 (the accuracy yardstick).
     The objective accuracy of a form is max over designs of |Theta - Theta_ref| /
-    Theta_ref on the warm cycle."""
+    Theta_ref on the (first, eager) warm cycle."""
     import torch
 
     from paper_2411_19030_amd import Problem
@@ -641,19 +719,35 @@ def batch_compare(rtol=1e-7, ref_rtol=1e-12, accuracy=1e-6) -> dict:
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    def batched(prec, tol, tuning):
+    def batched(prec, tol, tuning, graph=False):
         cyc = BatchedCycle(probs(prec, tol), dev)
         cyc.tuning = tuning
         cyc.run(rhos, warm=False)
         t = timed(lambda: cyc.run(rhos, warm=True))
         th = cyc.Theta.cpu().numpy().copy()
         st = [s_["status"] for s_ in cyc.status()]
+        tg = None
+        if graph:
+            s = torch.cuda.Stream()
+            g = torch.cuda.CUDAGraph()
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=s):
+                cyc.run(rhos, warm=True)
+            g.replay()
+            torch.cuda.synchronize()
+            ts = sorted(timed(g.replay) for _ in range(replays))
+            tg = ts[len(ts) // 2]
+            st += [s_["status"] for s_ in cyc.status()]
+            del g
         del cyc
         torch.cuda.empty_cache()
-        return t, th, st
+        return t, th, st, tg
 
-    t_ref, th_ref, st_ref = batched(0, ref_rtol, BATCH_TUNING)
-    t32, th32, st32 = batched(1, rtol, BATCH_TUNING)
+    t_ref, th_ref, st_ref, _ = batched(0, ref_rtol, BATCH_TUNING)
+    print(f"batch: fp64 reference {t_ref:.2f} s", file=sys.stderr, flush=True)
+    t32, th32, st32, t32g = batched(1, rtol, BATCH_TUNING, graph=True)
+    print(f"batch: fp32+refine {t32:.2f} s, graph replay {t32g:.2f} s", file=sys.stderr,
+          flush=True)
     th64 = []
     t64 = 0.0
     st64 = []
@@ -665,6 +759,8 @@ def batch_compare(rtol=1e-7, ref_rtol=1e-12, accuracy=1e-6) -> dict:
         th64.append(float(cyc.Theta))
         st64.append(cyc.status()["status"])
         del cyc
+        if k % 16 == 15:
+            print(f"batch: plain fp64 designs 1..{k + 1}", file=sys.stderr, flush=True)
     import numpy as np
     th64 = np.array(th64)
     err32 = float(np.max(np.abs(th32 - th_ref) / th_ref))
@@ -676,13 +772,18 @@ def batch_compare(rtol=1e-7, ref_rtol=1e-12, accuracy=1e-6) -> dict:
         "accuracy_target": accuracy,
         "fp32_refine_batched": {"cg_rtol": rtol, "s_per_cycle": t32,
                                 "cell_updates_per_s": cells / t32, "max_Theta_rel_err": err32,
-                                "tuning": BATCH_TUNING, "status_ok": all(v == 0 for v in st32)},
+                                "tuning": BATCH_TUNING,
+                                "tuning_source": "pt_autotune_batched (bench.py --autotune)",
+                                "graph_replay_s_per_cycle": t32g,
+                                "graph_replay_cell_updates_per_s": cells / t32g,
+                                "status_ok": all(v == 0 for v in st32)},
         "fp64_plain_per_design": {"cg_rtol": rtol, "s_per_cycle": t64,
                                   "cell_updates_per_s": cells / t64, "max_Theta_rel_err": err64,
                                   "status_ok": all(v == 0 for v in st64)},
         "reference": {"form": "fp64 batched", "cg_rtol": ref_rtol, "s_per_cycle": t_ref,
                       "status_ok": all(v == 0 for v in st_ref)},
         "speedup_batched_fp32_refine_over_plain_fp64": t64 / t32,
+        "speedup_graph_replay_over_plain_fp64": t64 / t32g,
         "both_meet_accuracy": err32 <= accuracy and err64 <= accuracy,
     }
 
@@ -763,7 +864,7 @@ def main():
         print(json.dumps(large_run(args.workload, max(1, min(args.steps, 3)))))
         return
     if args.workload == "batch_fp32_64":
-        print(json.dumps(batch_compare()))
+        print(json.dumps(batch_autotune() if args.autotune else batch_compare()))
         return
     if args.workload == "paper_100":
         print(json.dumps(paper_sweep()))

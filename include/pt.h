@@ -375,7 +375,10 @@ int pt_batch_default_tuning(int n, pt_batch_tuning *out);
  *                solution kept in ws
  *   tuning       worker shapes, or NULL for pt_batch_default_tuning
  *   Theta_out    [n] device array: Theta of every design
- *   dTheta_drho  [n] HOST array of device pointers to [N_e] outputs
+ *   dTheta_drho  [n] HOST array of device pointers to [N_e] outputs, or NULL: the primal
+ *                pass only (Theta_out); the next warm call then restarts the adjoint
+ *                from the last full cycle's lambda, or from lambda = 0 after a cold
+ *                forward-only call
  * Outputs must not overlap ws. Device-side problems are reported per design
  * by pt_batched_status.
  */
@@ -399,11 +402,15 @@ int pt_batched_status(int n, const pt_problem *probs, const void *ws, hipStream_
  * timed cycle.
  *   best, best_ms   the fastest shape and its time
  *   default_ms      may be NULL: the time of the built-in shape, from the same
- *                   state (so best_ms <= default_ms) */
+ *                   state (so best_ms <= default_ms)
+ *   progress, user  may be NULL: called on the host after each shape is timed,
+ *                   with the shape, its time in ms (+inf if unusable) and user */
+typedef void (*pt_autotune_progress)(const pt_batch_tuning *shape, double ms, void *user);
 int pt_autotune_batched(int n, const pt_problem *probs, const double *const *rho,
                         double *Theta_out, double *const *dTheta_drho, void *ws,
                         size_t ws_bytes, hipStream_t stream, pt_batch_tuning *best,
-                        double *best_ms, double *default_ms);
+                        double *best_ms, double *default_ms, pt_autotune_progress progress,
+                        void *user);
 
 #ifdef __cplusplus
 }

@@ -167,7 +167,7 @@ def load_library(path: str = LIB_PATH):
     lib.pt_batched_status.restype = ctypes.c_int
     lib.pt_autotune_batched.argtypes = [ctypes.c_int, P, pp, vp, pp, vp, ctypes.c_size_t, vp, TP,
                                         ctypes.POINTER(ctypes.c_double),
-                                        ctypes.POINTER(ctypes.c_double)]
+                                        ctypes.POINTER(ctypes.c_double), AUTOTUNE_PROGRESS, vp]
     lib.pt_autotune_batched.restype = ctypes.c_int
     FP = ctypes.POINTER(PtFilter)
     lib.pt_filter_validate.argtypes = [FP]
@@ -476,12 +476,16 @@ def _ptr_array(tensors):
 
 
 def _check_batch(where, probs, rhos, Theta_out, grads, ws):
+    """grads None: a forward-only call (no gradient outputs)."""
     n = len(probs)
-    if len(rhos) != n or len(grads) != n:
-        raise ValueError(f"{where}: {n} problems, {len(rhos)} densities, {len(grads)} gradients")
+    if len(rhos) != n or (grads is not None and len(grads) != n):
+        raise ValueError(f"{where}: {n} problems, {len(rhos)} densities, "
+                         f"{None if grads is None else len(grads)} gradients")
     specs = [(Theta_out, "Theta_out", n)]
     for k, p in enumerate(probs):
-        specs += [(rhos[k], f"rho[{k}]", p.n_elem), (grads[k], f"dTheta_drho[{k}]", p.n_elem)]
+        specs += [(rhos[k], f"rho[{k}]", p.n_elem)]
+        if grads is not None:
+            specs += [(grads[k], f"dTheta_drho[{k}]", p.n_elem)]
     _check_tensors(where, specs, [(ws, "ws")])
 
 
@@ -498,12 +502,14 @@ def pt_batch_default_tuning(n: int) -> dict:
 
 def pt_parareal_batched(probs, rhos, warm: bool, tuning: Optional[dict], Theta_out, grads, ws,
                         stream=None, check: bool = True) -> int:
+    """grads None: the primal pass only (Theta_out)."""
     _check_batch("pt_parareal_batched", probs, rhos, Theta_out, grads, ws)
     arr = _probs_array(probs)
     t = PtBatchTuning.from_dict(tuning) if tuning is not None else None
     rc = load_library().pt_parareal_batched(
         len(probs), arr, _ptr_array(rhos), 1 if warm else 0,
-        ctypes.byref(t) if t is not None else None, _ptr(Theta_out), _ptr_array(grads),
+        ctypes.byref(t) if t is not None else None, _ptr(Theta_out),
+        _ptr_array(grads) if grads is not None else None,
         _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
     if check:
         _check(rc, "pt_parareal_batched")
@@ -518,16 +524,23 @@ def pt_batched_status(probs, ws, stream=None) -> list:
     return [{k: getattr(s, k) for k, _ in PtStats._fields_} for s in st]
 
 
-def pt_autotune_batched(probs, rhos, Theta_out, grads, ws, stream=None) -> tuple:
-    """(best shape, its ms, the built-in shape's ms), timed from one state."""
+AUTOTUNE_PROGRESS = ctypes.CFUNCTYPE(None, ctypes.POINTER(PtBatchTuning), ctypes.c_double,
+                                     ctypes.c_void_p)
+
+
+def pt_autotune_batched(probs, rhos, Theta_out, grads, ws, stream=None, progress=None) -> tuple:
+    """(best shape, its ms, the built-in shape's ms), timed from one state.
+    progress(shape dict, ms) is called after each shape is timed."""
     _check_batch("pt_autotune_batched", probs, rhos, Theta_out, grads, ws)
     arr = _probs_array(probs)
     t = PtBatchTuning()
     ms, ms0 = ctypes.c_double(), ctypes.c_double()
+    cb = AUTOTUNE_PROGRESS(lambda shape, v, _: progress(shape.contents.as_dict(), v)) \
+        if progress is not None else AUTOTUNE_PROGRESS()
     _check(load_library().pt_autotune_batched(
         len(probs), arr, _ptr_array(rhos), _ptr(Theta_out), _ptr_array(grads), _ptr(ws),
         ws.numel() * ws.element_size(), _stream(stream), ctypes.byref(t), ctypes.byref(ms),
-        ctypes.byref(ms0)), "pt_autotune_batched")
+        ctypes.byref(ms0), cb, None), "pt_autotune_batched")
     return t.as_dict(), ms.value, ms0.value
 
 

@@ -30,23 +30,29 @@ class BatchedCycle:
         self.tuning: Optional[dict] = None
         self.has_state = False
 
-    def run(self, rhos: Sequence[torch.Tensor], warm: Optional[bool] = None, stream=None):
-        """One cycle of every design; warm defaults to 'a previous cycle ran'."""
+    def run(self, rhos: Sequence[torch.Tensor], warm: Optional[bool] = None, stream=None,
+            forward_only: bool = False):
+        """One cycle of every design; warm defaults to 'a previous cycle ran'.
+        forward_only: the primal passes only (Theta; grads are left as they
+        were), e.g. for objective evaluations without gradients."""
         if warm is None:
             warm = self.has_state
         if warm and not self.has_state:
             raise RuntimeError("warm cycle requested before any cycle ran")
         _pt.pt_parareal_batched(self.probs, [r.contiguous() for r in rhos], warm, self.tuning,
-                                self.Theta, self.grads, self.ws, stream)
+                                self.Theta, None if forward_only else self.grads, self.ws,
+                                stream)
         self.has_state = True
         return self.Theta, self.grads
 
-    def autotune(self, rhos: Sequence[torch.Tensor], stream=None) -> tuple:
+    def autotune(self, rhos: Sequence[torch.Tensor], stream=None, progress=None) -> tuple:
         """Picks the launch shape by timing warm cycles of this batch
         (synchronous); returns (shape, its ms, the built-in shape's ms). The
-        workspace then holds the tuner's cold-cycle state for a warm cycle."""
+        workspace then holds the tuner's cold-cycle state for a warm cycle.
+        progress(shape, ms) is called after each shape is timed."""
         best, ms, ms0 = _pt.pt_autotune_batched(self.probs, [r.contiguous() for r in rhos],
-                                                self.Theta, self.grads, self.ws, stream)
+                                                self.Theta, self.grads, self.ws, stream,
+                                                progress)
         self.tuning = best
         self.has_state = True
         return best, ms, ms0
@@ -79,4 +85,11 @@ class BatchedOneShot:
         self.warm = warm
 
     def __call__(self, rhos: Sequence[torch.Tensor]) -> torch.Tensor:
+        """Theta of every design. Without a gradient to compute (torch.no_grad,
+        or no density requires grad) only the primal passes run."""
+        if not (torch.is_grad_enabled() and any(r.requires_grad for r in rhos)):
+            cyc = self.cycle
+            cyc.run([r.detach() for r in rhos], warm=self.warm and cyc.has_state,
+                    forward_only=True)
+            return cyc.Theta.clone()
         return _BatchedTO.apply(self, *rhos)

@@ -2139,7 +2139,9 @@ __global__ void k_sensitivities(const EngineDesc *__restrict__ D) {
 
 // Keeps a design's corrected u^{k+1} and lambda^{k+1} as its next guesses
 // (warm restart of Alg. 3); blockIdx.y = design.
-__global__ void k_save_guess(const EngineDesc *__restrict__ D) {
+// primal_only: a forward-only cycle keeps the lambda guess of the last full
+// cycle, or (zero_lambda, a cold forward-only cycle) sets it to 0.
+__global__ void k_save_guess(const EngineDesc *__restrict__ D, int primal_only, int zero_lambda) {
     const EngineDesc &E = D[blockIdx.y];
     const Consts &C = E.C;
     const Bufs &B = E.B;
@@ -2147,7 +2149,8 @@ __global__ void k_save_guess(const EngineDesc *__restrict__ D) {
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
          t += (size_t)gridDim.x * blockDim.x) {
         B.save_T[t] = B.out_T[t];
-        B.save_L[t] = B.out_L[t];
+        if (!primal_only) B.save_L[t] = B.out_L[t];
+        else if (zero_lambda) B.save_L[t] = 0.0;
     }
     if (blockIdx.x == 0)
         for (int k = threadIdx.x; k <= C.Ntau; k += blockDim.x) B.save_th[k] = B.out_th[k];

@@ -1692,15 +1692,16 @@ int batched_cycle(int n, const pt_problem *probs, const double *const *rho, int 
                   const pt_batch_tuning *tuning, double *Theta_out, double *const *dTheta_drho,
                   void *ws, size_t ws_bytes, hipStream_t stream, bool save_guess) {
     if (!valid_batch(n, probs)) return PT_EINVAL;
-    if (!rho || !Theta_out || !dTheta_drho || !ws || (warm != 0 && warm != 1)) return PT_EINVAL;
+    if (!rho || !Theta_out || !ws || (warm != 0 && warm != 1)) return PT_EINVAL;
+    const bool fwd_only = dTheta_drho == nullptr;  // primal pass only
     for (int k = 0; k < n; ++k)
-        if (!rho[k] || !dTheta_drho[k]) return PT_EINVAL;
+        if (!rho[k] || (!fwd_only && !dTheta_drho[k])) return PT_EINVAL;
     const pt_batch_tuning T = tuning ? *tuning : default_tuning(n);
     if (!valid_tuning(&T)) return PT_EINVAL;
     const BatchLayout Lay = batch_layout(n, probs);
     if (ws_bytes < Lay.total) return PT_ENOMEM;
     if (overlaps(Theta_out, sizeof(double) * n, ws, ws_bytes)) return PT_EINVAL;
-    for (int k = 0; k < n; ++k)
+    for (int k = 0; k < n && !fwd_only; ++k)
         if (overlaps(dTheta_drho[k], sizeof(double) * probs[k].nx * probs[k].ny, ws, ws_bytes))
             return PT_EINVAL;
 
@@ -1721,7 +1722,7 @@ int batched_cycle(int n, const pt_problem *probs, const double *const *rho, int 
         E.B.out_L = at<double>(ws, L.lam);
         E.B.Theta_out = Theta_out + k;
         E.B.Theta = Theta_out + k;
-        E.B.grad = dTheta_drho[k];
+        E.B.grad = fwd_only ? nullptr : dTheta_drho[k];
         E.B.save_T = at<double>(ws, L.gT);
         E.B.save_th = at<double>(ws, L.gth);
         E.B.save_L = at<double>(ws, L.gL);
@@ -1746,6 +1747,12 @@ int batched_cycle(int n, const pt_problem *probs, const double *const *rho, int 
     PT_TRY(run_batched_engine(hd, T, false, ws, Lay, stream));
     hipLaunchKernelGGL(k_finalize_fwd, dim3(64, n), dim3(256), 0, stream, D);
     PT_TRY(launch_check());
+    if (fwd_only) {
+        if (save_guess)
+            hipLaunchKernelGGL(k_save_guess, dim3(128, n), dim3(256), 0, stream, D, 1,
+                               warm ? 0 : 1);
+        return launch_check();
+    }
     // adjoint pass of every design in one launch
     for (int k = 0; k < n; ++k) {
         Bufs &B = hd[k].B;
@@ -1754,7 +1761,7 @@ int batched_cycle(int n, const pt_problem *probs, const double *const *rho, int 
     PT_TRY(run_batched_engine(hd, T, true, ws, Lay, stream));
     hipLaunchKernelGGL(k_finalize_adj, dim3(64, n), dim3(256), 0, stream, D);
     hipLaunchKernelGGL(k_sensitivities, dim3(128, n), dim3(256), 0, stream, D);
-    if (save_guess) hipLaunchKernelGGL(k_save_guess, dim3(128, n), dim3(256), 0, stream, D);
+    if (save_guess) hipLaunchKernelGGL(k_save_guess, dim3(128, n), dim3(256), 0, stream, D, 0, 0);
     return launch_check();
 }
 
@@ -1765,7 +1772,8 @@ extern "C" {
 int pt_autotune_batched(int n, const pt_problem *probs, const double *const *rho,
                         double *Theta_out, double *const *dTheta_drho, void *ws,
                         size_t ws_bytes, hipStream_t stream, pt_batch_tuning *best,
-                        double *best_ms, double *default_ms) {
+                        double *best_ms, double *default_ms, pt_autotune_progress progress,
+                        void *user) {
     if (!valid_batch(n, probs) || !best) return PT_EINVAL;
     if (capturing(stream)) return PT_EINVAL;
     const pt_batch_tuning dflt = default_tuning(n);
@@ -1786,7 +1794,7 @@ int pt_autotune_batched(int n, const pt_problem *probs, const double *const *rho
     constexpr int kRepeats = 3;
     // median of kRepeats warm cycles; a shape the batch cannot use, or any
     // device-side problem of a design, makes the shape unusable (ms = +inf)
-    auto time_shape = [&](const pt_batch_tuning &t, double &ms) -> int {
+    auto time_raw = [&](const pt_batch_tuning &t, double &ms) -> int {
         ms = INFINITY;
         if (!valid_tuning(&t)) return PT_OK;
         double ts[kRepeats];
@@ -1808,6 +1816,11 @@ int pt_autotune_batched(int n, const pt_problem *probs, const double *const *rho
         std::sort(ts, ts + kRepeats);
         ms = ts[kRepeats / 2];
         return PT_OK;
+    };
+    auto time_shape = [&](const pt_batch_tuning &t, double &ms) -> int {
+        const int rc = time_raw(t, ms);
+        if (rc == PT_OK && progress) progress(&t, ms, user);
+        return rc;
     };
     pt_batch_tuning cur = dflt;
     double best_t = INFINITY, t_dflt = INFINITY;

@@ -173,6 +173,15 @@ def _batch(lib, probs, rho=None, grads=None, theta=0x3000, ws=0x10000000, nbytes
     return lib.pt_parareal_batched(n, arr, rp, warm, t, theta, gp, ws, nbytes, None)
 
 
+def _batch_fwd(lib, probs, ws=0x10000000, nbytes=None):
+    arr = (PtProblem * len(probs))(*[p.to_c() for p in probs])
+    n = len(probs)
+    rp = (ctypes.c_void_p * n)(*[0x1000 + 0x100 * k for k in range(n)])
+    if nbytes is None:
+        nbytes = lib.pt_batched_workspace_bytes(n, arr)
+    return lib.pt_parareal_batched(n, arr, rp, 0, None, 0x3000, None, ws, nbytes, None)
+
+
 def test_batched_workspace_and_validation(lib):
     a, b = base(), base(nx=12, ny=6, n_steps=30, n_slices=5)
     arr = (PtProblem * 2)(a.to_c(), b.to_c())
@@ -193,6 +202,9 @@ def test_batched_argument_errors_before_any_device_work(lib):
     a, b = base(), base(nx=12, ny=6, n_steps=30, n_slices=5)
     assert _batch(lib, [a, b], rho=[0x1000, None]) == _pt.PT_EINVAL
     assert _batch(lib, [a, b], grads=[None, 0x9000]) == _pt.PT_EINVAL
+    # no gradient array at all: a forward-only call (still checked on the host)
+    assert _batch_fwd(lib, [a, b], ws=None) == _pt.PT_EINVAL
+    assert _batch_fwd(lib, [a, b], nbytes=64) == _pt.PT_ENOMEM
     assert _batch(lib, [a, b], theta=None) == _pt.PT_EINVAL
     assert _batch(lib, [a, b], ws=None) == _pt.PT_EINVAL
     assert _batch(lib, [a, b], warm=2) == _pt.PT_EINVAL

@@ -196,6 +196,41 @@ def test_batched_autograd(gpu):
             np.linalg.norm(o["grad"])
 
 
+def test_batched_forward_only_under_no_grad(gpu):
+    """Without a gradient to compute only the primal passes run: Theta equals
+    the full cycle's, no sensitivity is written, no adjoint solve is counted;
+    the next warm cycle with gradients still matches a warm cycle after a
+    full one on Theta (same primal guesses) and is a valid one-shot cycle."""
+    import torch
+
+    from paper_2411_19030_amd.batched import BatchedOneShot
+    shapes = [(16, 16, 32, 4), (24, 12, 30, 5)]
+    probs = _problems(shapes, cg_rtol=1e-13, max_iter=20000)
+    rhos_np = [density_uniform_noise(nx, ny, 80 + k) for k, (nx, ny, _, _) in enumerate(shapes)]
+    full = BatchedOneShot(probs, gpu, warm=False)
+    rhos = [torch.tensor(r, device=gpu, requires_grad=True) for r in rhos_np]
+    th_full = full(rhos).detach().cpu().numpy()
+    fwd = BatchedOneShot(probs, gpu, warm=False)
+    for g in fwd.cycle.grads:
+        g.fill_(7.0)
+    with torch.no_grad():
+        th = fwd(rhos).cpu().numpy()
+    assert np.array_equal(th, th_full)
+    assert all(bool((g == 7.0).all()) for g in fwd.cycle.grads)
+    st = fwd.cycle.status()
+    for k, (nx, ny, nt, ns) in enumerate(shapes):
+        assert st[k]["status"] == 0
+        # primal only: the fine solves of the forward pass (N_t steps)
+        assert st[k]["solves_fine"] == nt, st[k]
+    # a warm cycle with gradients after the forward-only one (lambda guess 0)
+    fwd.warm = True
+    thw = fwd(rhos)
+    thw.sum().backward()
+    for k in range(len(shapes)):
+        assert np.isfinite(rhos[k].grad.cpu().numpy()).all()
+    assert all(s["status"] == 0 for s in fwd.cycle.status())
+
+
 def test_batch_fp32_64_designs_full_size(gpu):
     """The 64-design workload in one call (default worker shapes): designs of
     side 64 against the oracle, every design finite with an OK status."""
@@ -243,10 +278,14 @@ def test_autotuned_shape_keeps_parity_and_beats_the_default(gpu):
     rhos_np = [density_uniform_noise(nx, ny, 300 + k) for k, (nx, ny, _, _) in enumerate(shapes)]
     rhos = [torch.tensor(r, device=gpu) for r in rhos_np]
     cyc = BatchedCycle(probs, gpu)
-    best, best_ms, default_ms = cyc.autotune(rhos)
+    seen = []
+    best, best_ms, default_ms = cyc.autotune(rhos, progress=lambda t, ms: seen.append((t, ms)))
     print("tuned", best, best_ms, "default", pt_batch_default_tuning(len(probs)), default_ms,
-          flush=True)
+          len(seen), "shapes", flush=True)
     assert 0.0 < best_ms <= default_ms
+    # the progress callback saw every timed shape: the built-in one first, the best among them
+    assert seen[0] == (pt_batch_default_tuning(len(probs)), default_ms)
+    assert (best, best_ms) in seen and min(ms for _, ms in seen) == best_ms
     th, gr = _run(cyc, rhos_np, True, gpu)
     assert all(s["status"] == 0 for s in cyc.status())
     for k, (nx, ny, nt, ns) in enumerate(shapes):
