@@ -105,8 +105,6 @@ typedef struct pt_tuning {
                                /* workgroup                                                (4096) */
     int32_t gmg_sweeps;        /* PT_GMG: smoothing pairs on the coarsest level            (16)  */
     double gmg_omega;          /* PT_GMG: smoother damping times 1/(Gershgorin bound)      (1.3) */
-    int32_t cm_lds;            /* PT_COARSE_MESH: 1: the cold coarse sweep keeps its        */
-                               /* vectors in LDS when they fit                               (1) */
     int32_t phase_timers;      /* 1: per-round phase times in the lane trace of FP64 launches */
                                /* without coarse-mesh lanes (slows the rounds)              (0) */
     double wait_timeout_s;     /* a device wait gives up after this long (PT_EHIP);        */

@@ -47,7 +47,7 @@ class PtTuning(ctypes.Structure):
         ("sweep_x0", ctypes.c_int32), ("verify", ctypes.c_int32),
         ("inner_rtol", ctypes.c_double), ("gmg_tail", ctypes.c_int32),
         ("gmg_sweeps", ctypes.c_int32), ("gmg_omega", ctypes.c_double),
-        ("cm_lds", ctypes.c_int32), ("phase_timers", ctypes.c_int32),
+        ("phase_timers", ctypes.c_int32),
         ("wait_timeout_s", ctypes.c_double),
     ]
 

@@ -20,8 +20,11 @@
 //    starts as soon as the batched step it reads is done and takes F_n only
 //    when it needs it (after its solve), so the sweep overlaps the fine lanes.
 //    Its outputs G(hat u_n) go to Gn[n], the primal theta chain to out_th and
-//    Gn_th.
-// After the launch, k_cm_correct forms the corrected fine states
+//    Gn_th. In a cold launch (LaunchInfo::cold, the lane alone) the same lane
+//    runs the cold sweep u^0_{n+1} = G(u^0_n) from u^0_0 = 0 (adjoint:
+//    v^0_{n-1} = G(v^0_n) from v^0_{N_tau} = 0) into Gk (and Gk_th), each solve
+//    from its input; k_cm_guess then prolongs it into the fine guesses.
+// After a correction launch, k_cm_correct forms the corrected fine states
 // F_n + P(Gn[n] - Gk[n]) and k_cm_sens the coarse-correction sensitivities.
 //
 // Every solve is Jacobi PCG in the single-reduction form of Chronopoulos and
@@ -134,6 +137,7 @@ __device__ __forceinline__ long long cm_lane(const EngineDesc *__restrict__ Ed, 
     const long long tmo = C.timeout_ticks;
     const bool adj = kind == CM_GK_ADJ || kind == CM_SWEEP_ADJ;
     const bool sweep = kind == CM_SWEEP_PRI || kind == CM_SWEEP_ADJ;
+    const bool cold = sweep && I.cold;  // the cold coarse sweep
     const int Nc = M.Nc, Wc = M.Wc, Hc = Wc + 1;
     const int ts = (Nc + g - 1) / g;
     const int a = min(rank * ts, Nc), b = min(a + ts, Nc);
@@ -150,9 +154,10 @@ __device__ __forceinline__ long long cm_lane(const EngineDesc *__restrict__ Ed, 
     const unsigned nbar0 = nbar;
     unsigned long long iters_all = 0;
     const int Nt = C.Ntau;
-    // a batched lane is one step of slice `slice`; the primal sweep runs
-    // n = 1 .. N_tau-1, the adjoint sweep n = N_tau-1 .. 1
-    const int nsteps = sweep ? Nt - 1 : 1;
+    // a batched lane is one step of slice `slice`; the primal correction sweep
+    // runs n = 1 .. N_tau-1, the adjoint one n = N_tau-1 .. 1; the cold sweeps
+    // n = 0 .. N_tau-1 and n = N_tau .. 1
+    const int nsteps = cold ? Nt : sweep ? Nt - 1 : 1;
     if (leader) {
         trec[TR_KIND] = kind;
         trec[TR_SLICE] = slice;
@@ -170,9 +175,13 @@ __device__ __forceinline__ long long cm_lane(const EngineDesc *__restrict__ Ed, 
     // the adjoint source factor Theta^{1-p}/N_e (Eq. 4.6)
     const double scale = adj ? pow_call(*B.Theta, 1.0 - C.p) / (double)C.Ne : 0.0;
 
-    // the sweep's first input R F_0 (primal) or R F_{N_tau} (adjoint)
+    // the correction sweep's first input R F_0 (primal) or R F_{N_tau}
+    // (adjoint); the cold sweep's is 0
     double theta = 0.0;
-    if (sweep) {
+    if (cold) {
+        for (int q = a + threadIdx.x; q < b; q += kThreads) stc(U + q, 0.0);
+        if (!barrier(false)) return -1;
+    } else if (sweep) {
         if (!waitf(FL_F, adj ? Nt : 0)) return -1;
         const double *F0 = adj ? B.FL + (size_t)Nt * C.Nn : cml_srow(C, B, C.M);
         for (int q = a + threadIdx.x; q < b; q += kThreads)
@@ -184,13 +193,15 @@ __device__ __forceinline__ long long cm_lane(const EngineDesc *__restrict__ Ed, 
         if (!barrier(false)) return -1;
     }
     for (int step = 0; step < nsteps; ++step) {
-        const int n = sweep ? (adj ? Nt - 1 - step : step + 1) : slice;
+        const int n = cold ? (adj ? Nt - step : step)
+                           : sweep ? (adj ? Nt - 1 - step : step + 1) : slice;
         const double *Tm = adj ? cml_srow(C, B, C.M * (n - 1) + 1) : nullptr;
         const double qn = adj ? 0.0 : B.qt[C.M * (n + 1)];
-        double *X = (sweep ? M.Gn : M.Gk) + (size_t)n * Nc;  // the step's output
+        double *X = (sweep && !cold ? M.Gn : M.Gk) + (size_t)n * Nc;  // the step's output
         const double *gk = M.Gk + (size_t)n * Nc;
-        const double *fin = (adj ? B.in_L : B.in_T) + (size_t)n * C.Nn;  // u^k_n
-        if (sweep && I.gk_lanes && !waitf(FL_GK, n)) return -1;
+        // u^k_n (no guess in the cold sweep)
+        const double *fin = cold ? nullptr : (adj ? B.in_L : B.in_T) + (size_t)n * C.Nn;
+        if (sweep && !cold && I.gk_lanes && !waitf(FL_GK, n)) return -1;
         double bnorm = 0.0, rn = 0.0, alpha = 0.0, beta = 0.0, gamma = 0.0;
         int iter = 0, restarts = 0;
         bool verify = false;
@@ -205,6 +216,9 @@ __device__ __forceinline__ long long cm_lane(const EngineDesc *__restrict__ Ed, 
                 if (id >= 0 && id < Nc && M.dinv[id] != 0.0) {
                     if (verify) {
                         x0 = ldc(X + id);
+                    } else if (cold) {
+                        u = ldc(U + id);
+                        x0 = u;
                     } else {
                         const double rk = fin[cml_fine(C, M, id)];
                         u = sweep ? ldc(U + id) : rk;
@@ -325,8 +339,11 @@ __device__ __forceinline__ long long cm_lane(const EngineDesc *__restrict__ Ed, 
             verify = true;  // the true residual of x decides
         }
         iters_all += iter;
-        // POST: the next input of a sweep, u = x + R F_n - G(R u^k_n)
-        if (sweep) {
+        // POST: the next input of a sweep, u = x + R F_n - G(R u^k_n), or x
+        // in the cold sweep
+        if (cold) {
+            for (int id = a + threadIdx.x; id < b; id += kThreads) stc(U + id, ldc(X + id));
+        } else if (sweep) {
             if (!waitf(FL_F, n)) return -1;
             const double *Fn = adj ? B.FL + (size_t)n * C.Nn : cml_srow(C, B, C.M * (n + 1));
             for (int id = a + threadIdx.x; id < b; id += kThreads)
@@ -349,7 +366,10 @@ __device__ __forceinline__ long long cm_lane(const EngineDesc *__restrict__ Ed, 
         if (!adj) {
             const double base = sweep ? theta : B.in_th[n];
             const double thG = pow_call(ipow(base, C.p) + th[0] * C.inv_NtauNe, C.inv_p);
-            if (sweep) {
+            if (cold) {
+                theta = thG;
+                if (leader) B.Gk_th[n] = thG;
+            } else if (sweep) {
                 theta = thG + B.F_th[n] - B.Gk_th[n];
                 if (leader) {
                     B.Gn_th[n] = thG;

@@ -10,27 +10,19 @@
 //     output P x, theta' = (theta^p + ||P x||_p^p / (N_tau N_e))^{1/p} (Alg. 1);
 //   G_adj^c(lambda, n): (C_c/dtau + K_c) x = C_c/dtau R lambda + P^T s(T_m),
 //     s the fine source of Eq. 4.6 at m = M(n-1)+1, output P x (Alg. 2).
-// The batched steps G(R u^k_n) and the sequential correction sweep run as
-// lanes of the engine launch that runs the fine propagators (the coarse-mesh
-// lanes of the engine). This file holds the coarse-mesh set-up (coefficients
-// and assembled stencils), the cold sweep u^0_{n+1} = G(u^0_n) that gives a
-// cold start its guesses, and the kernels after the launch: the corrected fine
-// states F_n + P(G(u^{k+1}_n) - G(u^k_n)) (Eq. 4.10 / Eq. 4.14 with both coarse
+// The batched steps G(R u^k_n), the cold sweep and the sequential correction
+// sweep run as lanes of the engine (the coarse-mesh lanes). This file holds
+// the coarse-mesh set-up (coefficients and assembled stencils) and the
+// kernels around the engine launches: the fine guesses of a cold start
+// (the cold sweep prolonged), the corrected fine states
+// F_n + P(G(u^{k+1}_n) - G(u^k_n)) (Eq. 4.10 / Eq. 4.14 with both coarse
 // outputs prolonged by the same linear P) and the sensitivity part of the
 // reversed correction, linear in the coarse output difference and summed per
 // fine element (Eq. 4.16).
-//
-// The cold sweep's solves are Jacobi-preconditioned CG (Hestenes-Stiefel form)
-// run by one workgroup of 1024 threads, with the true residual checked at the
-// end; reductions are in a fixed order. The solve's vectors sit in LDS when
-// they fit (about 3400 coarse nodes, e.g. the 51^2 mesh of a 100^2 design),
-// else in global memory, with the same arithmetic. It runs once, before the
-// first cycle of a cold start.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
-#include <cstdlib>
 
 #include "pt.h"
 #include "pt_internal.h"
@@ -38,19 +30,6 @@
 namespace pt {
 
 namespace {
-
-constexpr int kCT = kCoarseMeshThreads;
-constexpr int kCW = kCT / 64;
-
-__device__ __forceinline__ double cm_ipow(double x, int n) {
-    double r = 1.0, b = x;
-    while (n) {
-        if (n & 1) r *= b;
-        b *= b;
-        n >>= 1;
-    }
-    return r;
-}
 
 // Q1 rectangle element matrices, local nodes (0,0), (1,0), (1,1), (0,1):
 // K = (1/6)(hy/hx Kx + hx/hy Ky), C = hx hy/36 Cm with the integer patterns
@@ -143,23 +122,6 @@ __global__ void k_cm_stencil(const EngineDesc *__restrict__ D, CoarseMesh M) {
     }
 }
 
-// 9-point row I of a stencil array applied to a coarse vector.
-__device__ __forceinline__ double cm_row(const CoarseMesh &M, const double *S9, const double *x,
-                                         int I) {
-    const int J = I / M.Wc, i = I - J * M.Wc;
-    double s = 0.0;
-    for (int dj = -1; dj <= 1; ++dj) {
-        const int jj = J + dj;
-        if (jj < 0 || jj > M.nyc) continue;
-        for (int di = -1; di <= 1; ++di) {
-            const int ii = i + di;
-            if (ii < 0 || ii > M.nxc) continue;
-            s += S9[(size_t)((dj + 1) * 3 + di + 1) * M.Nc + I] * x[jj * M.Wc + ii];
-        }
-    }
-    return s;
-}
-
 // P x at fine node id (0 on fine Dirichlet nodes).
 __device__ __forceinline__ double cm_prolong(const Consts &C, const CoarseMesh &M,
                                              const unsigned char *mask, const double *x, int id) {
@@ -180,227 +142,8 @@ __device__ __forceinline__ double cm_prolong_diff(const Consts &C, const CoarseM
     return cm_prolong(C, M, mask, x, id) - cm_prolong(C, M, mask, y, id);
 }
 
-// (P^T s)_I for the fine adjoint source s_j = scale T_j^{p-1} (Eq. 4.6), with
-// the bilinear weights 1, 1/2, 1/4 of the fine nodes around coarse node I.
-__device__ __forceinline__ double cm_source(const Consts &C, const CoarseMesh &M,
-                                            const unsigned char *mask, const double *Tm,
-                                            double scale, int I) {
-    const int J = I / M.Wc, i = I - J * M.Wc;
-    double s = 0.0;
-    for (int dj = -1; dj <= 1; ++dj) {
-        const int fj = 2 * J + dj;
-        if (fj < 0 || fj > C.ny) continue;
-        for (int di = -1; di <= 1; ++di) {
-            const int fi = 2 * i + di;
-            if (fi < 0 || fi > C.nx) continue;
-            const int id = fj * C.W + fi;
-            if (mask[id]) continue;
-            const double w = (di == 0 ? 1.0 : 0.5) * (dj == 0 ? 1.0 : 0.5);
-            s += w * (scale * cm_ipow(Tm[id], C.p - 1));
-        }
-    }
-    return s;
-}
-
-// Sum of Q values over the workgroup in a fixed order (wave butterflies, then
-// the wave totals in wave order); every thread returns the same totals.
-// `red` holds 2 * Q * kCW doubles used alternately.
-template <int Q>
-__device__ void cm_reduce(double (&v)[Q], double *red, int &par) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    double *buf = red + par * Q * kCW;
-    if (l == 0)
-#pragma unroll
-        for (int q = 0; q < Q; ++q) buf[q * kCW + w] = v[q];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        double s = 0.0;
-        for (int k = 0; k < kCW; ++k) s += buf[q * kCW + k];
-        v[q] = s;
-    }
-    par ^= 1;
-}
-
-struct CmVecs {
-    double *r, *z, *p, *q, *b, *u;
-};
-
-__device__ __forceinline__ CmVecs cm_vecs(const CoarseMesh &M, int slot) {
-    double *base = M.vec + (size_t)slot * kCoarseMeshVecs * M.Nc;
-    CmVecs V;
-    V.r = base;
-    V.z = base + M.Nc;
-    V.p = base + 2 * (size_t)M.Nc;
-    V.q = base + 3 * (size_t)M.Nc;
-    V.b = base + 4 * (size_t)M.Nc;
-    V.u = base + 5 * (size_t)M.Nc;
-    return V;
-}
-
-// Solves (C_c/dtau + K_c) x = b on the coarse free nodes by Jacobi PCG from
-// x0, to ||b - A x|| <= rtol ||b|| checked on the true residual (at most three
-// restarts from it), x = 0 on Dirichlet nodes. rhs(I) and x0(I) are read once
-// per node before any write to x. Records the solve in the status block.
-template <typename Rhs, typename X0>
-__device__ void cm_pcg(const Consts &C, const CoarseMesh &M, Control *ctl, const CmVecs &V,
-                       double *x, Rhs rhs, X0 x0, double *red, int &par) {
-    const int Nc = M.Nc;
-    double bb[1] = {0.0};
-    for (int I = threadIdx.x; I < Nc; I += kCT) {
-        const bool d = M.dinv[I] == 0.0;
-        const double b = d ? 0.0 : rhs(I);
-        const double xv = d ? 0.0 : x0(I);
-        V.b[I] = b;
-        bb[0] += b * b;
-        V.q[I] = xv;  // staged: x may alias the inputs rhs/x0 read
-    }
-    __syncthreads();
-    for (int I = threadIdx.x; I < Nc; I += kCT) x[I] = V.q[I];
-    cm_reduce<1>(bb, red, par);  // its barrier also completes x
-    const double bnorm = sqrt(bb[0]);
-    int it = 0;
-    double rn = 0.0;
-    if (bnorm == 0.0) {
-        for (int I = threadIdx.x; I < Nc; I += kCT) x[I] = 0.0;
-        __syncthreads();
-    } else {
-        const double tol = C.rtol * bnorm;
-        for (int pass = 0;; ++pass) {
-            // true residual r = b - A x, z = D^{-1} r, p = z
-            double v[2] = {0.0, 0.0};
-            for (int I = threadIdx.x; I < Nc; I += kCT) {
-                const double r = V.b[I] - cm_row(M, M.A9, x, I);
-                const double z = M.dinv[I] * r;
-                V.r[I] = r;
-                V.p[I] = z;
-                v[0] += r * z;
-                v[1] += r * r;
-            }
-            cm_reduce<2>(v, red, par);
-            double rz = v[0];
-            rn = sqrt(v[1]);
-            if (rn <= tol || it >= C.max_iter || pass == 3) break;
-            for (;;) {
-                double w[1] = {0.0};
-                for (int I = threadIdx.x; I < Nc; I += kCT) {
-                    const double q = cm_row(M, M.A9, V.p, I);
-                    V.q[I] = q;
-                    w[0] += V.p[I] * q;
-                }
-                cm_reduce<1>(w, red, par);
-                const double alpha = rz / w[0];
-                double v2[2] = {0.0, 0.0};
-                for (int I = threadIdx.x; I < Nc; I += kCT) {
-                    x[I] += alpha * V.p[I];
-                    const double r = V.r[I] - alpha * V.q[I];
-                    const double z = M.dinv[I] * r;
-                    V.r[I] = r;
-                    V.z[I] = z;
-                    v2[0] += r * z;
-                    v2[1] += r * r;
-                }
-                cm_reduce<2>(v2, red, par);
-                const double beta = v2[0] / rz;
-                rz = v2[0];
-                ++it;
-                if (sqrt(v2[1]) <= tol || it >= C.max_iter) break;
-                for (int I = threadIdx.x; I < Nc; I += kCT) V.p[I] = V.z[I] + beta * V.p[I];
-                __syncthreads();
-            }
-        }
-    }
-    if (threadIdx.x == 0) {
-        const double relres = bnorm > 0.0 ? rn / bnorm : 0.0;
-        const bool conv = bnorm == 0.0 || rn <= C.rtol * bnorm;
-        atomicAdd(&ctl->iters_coarse, (unsigned long long)it);
-        atomicAdd(&ctl->solves_coarse, 1ull);
-        atomicMax(&ctl->max_iters, it);
-        atomicMax(&ctl->max_relres_bits, (unsigned long long)__double_as_longlong(relres));
-        if (!conv) atomicCAS(&ctl->status, 0, PT_ENOCONV);
-        if (!isfinite(relres)) atomicExch(&ctl->status, PT_EDOMAIN);
-    }
-    __syncthreads();
-}
-
-extern __shared__ double cm_lds[];
-
-// The solve slot's vectors in LDS (6 Nc doubles of dynamic LDS) instead of
-// global memory, for coarse meshes that fit: the same arithmetic, with the
-// per-iteration vector traffic off the CU's cache path.
-__device__ __forceinline__ CmVecs cm_vecs_lds(const CoarseMesh &M) {
-    CmVecs V;
-    V.r = cm_lds;
-    V.z = cm_lds + M.Nc;
-    V.p = cm_lds + 2 * (size_t)M.Nc;
-    V.q = cm_lds + 3 * (size_t)M.Nc;
-    V.b = cm_lds + 4 * (size_t)M.Nc;
-    V.u = cm_lds + 5 * (size_t)M.Nc;
-    return V;
-}
-
-// theta' = (theta^p + ||P x||_p^p / (N_tau N_e))^{1/p} (Alg. 1 with dtau, N_tau)
-__device__ double cm_theta(const Consts &C, const CoarseMesh &M, const Bufs &B, const double *x,
-                           double theta, double *red, int &par) {
-    double s[1] = {0.0};
-    for (int id = threadIdx.x; id < C.Nn; id += kCT)
-        s[0] += cm_ipow(cm_prolong(C, M, B.mask, x, id), C.p);
-    cm_reduce<1>(s, red, par);
-    return pow(cm_ipow(theta, C.p) + s[0] * C.inv_NtauNe, C.inv_p);
-}
-
 __device__ __forceinline__ double *crow(double *base, const CoarseMesh &M, int n) {
     return base + (size_t)n * M.Nc;
-}
-
-// The cold coarse sweep on one workgroup (vectors in LDS, else slot 0):
-// u^0_{n+1} = G(u^0_n) from u_0 = 0 (primal, with the theta chain into Gk_th)
-// or v^0_{n-1} = G(v^0_n) from v_{N_tau} = 0 (adjoint), outputs into Gk. Each
-// solve starts from its input.
-template <bool LDS>
-__global__ void __launch_bounds__(kCT) k_cm_cold(const EngineDesc *__restrict__ D, CoarseMesh M,
-                                                 int adjoint) {
-    __shared__ double red[2 * 2 * kCW];
-    int par = 0;
-    const Consts &C = D->C;
-    const Bufs &B = D->B;
-    if (B.ctl->status == kStatusOrder) return;  // adjoint with no forward before it
-    const CmVecs V = LDS ? cm_vecs_lds(M) : cm_vecs(M, 0);
-    const int Nt = C.Ntau;
-    double *u = V.u;
-    for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = 0.0;
-    __syncthreads();
-    if (!adjoint) {
-        double th = 0.0;
-        for (int n = 0; n < Nt; ++n) {
-            const double qn = B.qt[C.M * (n + 1)];
-            double *x = crow(M.Gk, M, n);
-            cm_pcg(
-                C, M, B.ctl, V, x, [&](int I) { return cm_row(M, M.C9, u, I) + qn * M.fc[I]; },
-                [&](int I) { return u[I]; }, red, par);
-            th = cm_theta(C, M, B, x, th, red, par);
-            if (threadIdx.x == 0) B.Gk_th[n] = th;
-            for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = x[I];
-            __syncthreads();
-        }
-    } else {
-        const double scale = pow(*B.Theta, 1.0 - C.p) / (double)C.Ne;
-        for (int n = Nt; n >= 1; --n) {
-            const double *Tm = cm_srow(C, B, C.M * (n - 1) + 1);
-            double *x = crow(M.Gk, M, n);
-            cm_pcg(
-                C, M, B.ctl, V, x,
-                [&](int I) {
-                    return cm_row(M, M.C9, u, I) + cm_source(C, M, B.mask, Tm, scale, I);
-                },
-                [&](int I) { return u[I]; }, red, par);
-            for (int I = threadIdx.x; I < M.Nc; I += kCT) u[I] = x[I];
-            __syncthreads();
-        }
-    }
 }
 
 // Fine guesses from the cold sweep: primal T[n] = P Gk[n-1], th[n] = Gk_th[n-1]
@@ -478,40 +221,6 @@ __global__ void k_cm_sens(const EngineDesc *__restrict__ D, CoarseMesh M) {
 
 int cm_check() { return hipGetLastError() == hipSuccess ? PT_OK : PT_EHIP; }
 
-// LDS-resident solve vectors when allowed and they fit the workgroup's LDS.
-size_t cm_lds_bytes(const CoarseMesh &M, bool use_lds) {
-    if (!use_lds) return 0;
-    int dev = 0, cap = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-        return 0;
-    const size_t need = sizeof(double) * kCoarseMeshVecs * (size_t)M.Nc;
-    const size_t fixed = sizeof(double) * 2 * 2 * kCW;  // the reduction buffer
-    return need + fixed <= (size_t)cap ? need : 0;
-}
-
-// Launches kernel K<true> with the vectors in LDS when they fit, else K<false>.
-template <template <bool> class K, typename... Args>
-int cm_launch(const CoarseMesh &M, bool use_lds, dim3 grid, hipStream_t stream, Args... args) {
-    const size_t lds = cm_lds_bytes(M, use_lds);
-    if (lds > 0) {
-        auto kern = K<true>::kernel();
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds) != hipSuccess)
-            return PT_EHIP;
-        hipLaunchKernelGGL(kern, grid, dim3(kCT), (unsigned)lds, stream, args...);
-    } else {
-        hipLaunchKernelGGL(K<false>::kernel(), grid, dim3(kCT), 0, stream, args...);
-    }
-    return cm_check();
-}
-
-template <bool LDS>
-struct ColdK {
-    static auto kernel() { return &k_cm_cold<LDS>; }
-};
-
 }  // namespace
 
 int cm_setup(const EngineDesc *D, const CoarseMesh &M, hipStream_t stream) {
@@ -520,10 +229,8 @@ int cm_setup(const EngineDesc *D, const CoarseMesh &M, hipStream_t stream) {
     return cm_check();
 }
 
-int cm_cold(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
-            double *rows, double *th, bool use_lds, hipStream_t stream) {
-    const int rc = cm_launch<ColdK>(M, use_lds, dim3(1), stream, D, M, adjoint ? 1 : 0);
-    if (rc != PT_OK) return rc;
+int cm_guess(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
+             double *rows, double *th, hipStream_t stream) {
     hipLaunchKernelGGL(k_cm_guess, dim3(std::min((Nn + 255) / 256, 1024), Ntau + 1), dim3(256),
                        0, stream, D, M, adjoint ? 1 : 0, rows, th);
     return cm_check();

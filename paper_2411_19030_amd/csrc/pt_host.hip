@@ -47,7 +47,6 @@ pt_tuning default_settings() {
     t.gmg_tail = 4096;
     t.gmg_sweeps = 16;
     t.gmg_omega = 1.3;
-    t.cm_lds = 1;
     t.phase_timers = 0;
     t.wait_timeout_s = 0.0;
     return t;
@@ -68,7 +67,7 @@ bool valid_settings(const pt_tuning &t) {
            t.ck_slots >= 1 && bool01(t.extrap) && bool01(t.sweep_x0) && bool01(t.verify) &&
            t.inner_rtol > 0.0 && t.inner_rtol < 1.0 && t.gmg_tail >= 0 && t.gmg_sweeps >= 1 &&
            t.gmg_sweeps <= 1000 && t.gmg_omega > 0.0 && isfinite(t.gmg_omega) &&
-           bool01(t.cm_lds) && bool01(t.phase_timers) && t.wait_timeout_s >= 0.0 &&
+           bool01(t.phase_timers) && t.wait_timeout_s >= 0.0 &&
            isfinite(t.wait_timeout_s);
 }
 
@@ -169,7 +168,7 @@ struct DesignLayout {
     size_t ck_stride;
     size_t Gk, Gn, Gk_th, Gn_th, F_th, Uprev, Uprev_th, Ubuf, Ubuf_th, acc, accG;
     // coarse-mesh propagators (PT_COARSE_MESH)
-    size_t cm_kE, cm_cE, cm_A9, cm_C9, cm_dinv, cm_fc, cm_Gk, cm_Gn, cm_vec;
+    size_t cm_kE, cm_cE, cm_A9, cm_C9, cm_dinv, cm_fc, cm_Gk, cm_Gn;
     // multi-design cycles keep the cycle's state here
     size_t S, uT, uth, lam, gT, gth, gL;
 };
@@ -218,7 +217,6 @@ void carve_design(Carver &c, const pt_problem *p, DesignLayout &L, bool batched)
         L.cm_fc = c.take(d * Nc);
         L.cm_Gk = c.take(d * Nt1 * Nc);
         L.cm_Gn = c.take(d * Nt1 * Nc);
-        L.cm_vec = c.take(d * kCoarseMeshVecs * Nc);
     }
     if (!batched) {
         L.Uprev = c.take(d * Nt1 * Nn);
@@ -462,7 +460,6 @@ CoarseMesh make_coarse_mesh(void *ws, const DesignLayout &L, const pt_problem *p
     M.fc = at<double>(ws, L.cm_fc);
     M.Gk = at<double>(ws, L.cm_Gk);
     M.Gn = at<double>(ws, L.cm_Gn);
-    M.vec = at<double>(ws, L.cm_vec);
     return M;
 }
 
@@ -1285,12 +1282,19 @@ int coarse_mesh_pass(const pt_problem *prob, std::vector<EngineDesc> &hd, Engine
         const double *in = it == 0 ? guess : Uprev;
         const double *in_th = it == 0 ? guess_theta : Uprev_th;
         if (cold0) {
+            // the cold coarse sweep: the sweep lane alone in a cold launch
             B.in_L = nullptr;
             B.in_T = nullptr;
             B.in_th = nullptr;
+            I.cold = 1;
             PT_TRY(upload_descs(hd, D, stream));
-            PT_TRY(cm_cold(D, M, C.Nn, Ntau, adjoint, Uprev, adjoint ? nullptr : Uprev_th,
-                           T.cm_lds != 0, stream));
+            std::vector<LanePlan> cp;
+            cp.push_back({adjoint ? CM_SWEEP_ADJ : CM_SWEEP_PRI, 1, 0, +1, 0.0, true, 0});
+            cp.back().fixed_nwg = T.cm_sweep_wgs;
+            PT_TRY(run_engine(E, D, cp, ws, Lay, T, stream, &M));
+            PT_TRY(cm_guess(D, M, C.Nn, Ntau, adjoint, Uprev, adjoint ? nullptr : Uprev_th,
+                            stream));
+            I.cold = 0;
             in = Uprev;
             in_th = Uprev_th;
         }

@@ -195,8 +195,6 @@ struct DesignPlan {
 
 // Coarse-spatial-mesh propagators (propagator PT_COARSE_MESH): the coarse
 // mesh has nx/2 x ny/2 elements; coarse node (I, J) is fine node (2I, 2J).
-constexpr int kCoarseMeshThreads = 1024;  // the cold sweep's workgroup
-constexpr int kCoarseMeshVecs = 6;        // r, z, p, q, b, u of its solves
 
 struct CoarseMesh {
     int nxc, nyc, Wc, Nc, Nec;  // elements per side, nodes per row, nodes, elements
@@ -206,7 +204,6 @@ struct CoarseMesh {
     double *dinv;               // [Nc] 1/diag of A (0 on Dirichlet nodes)
     double *fc;                 // [Nc] int N_I (0 on Dirichlet nodes)
     double *Gk, *Gn;            // [Ntau+1][Nc] coarse outputs G(R u^k_n), G(u^{k+1}_n)
-    double *vec;                // [kCoarseMeshVecs][Nc] the cold sweep's solve vectors
 };
 
 // Everything a workgroup needs about one design, read from device memory.
@@ -251,8 +248,9 @@ enum {
 // Host entry points of the coarse-mesh kernels (pt_cmesh.hip); D is the
 // uploaded single-design descriptor. Each returns PT_OK or PT_EHIP.
 int cm_setup(const EngineDesc *D, const CoarseMesh &M, hipStream_t stream);
-int cm_cold(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
-            double *rows, double *th, bool use_lds, hipStream_t stream);
+// fine guesses of a cold start from the cold sweep's outputs in M.Gk
+int cm_guess(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint,
+             double *rows, double *th, hipStream_t stream);
 int cm_correct(const EngineDesc *D, const CoarseMesh &M, int Nn, int Ntau, bool adjoint, int Ne,
                hipStream_t stream);
 

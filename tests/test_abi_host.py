@@ -137,7 +137,7 @@ def test_tuning_layout_matches_header():
     offs = {name: getattr(T, name).offset for name, _ in T._fields_}
     assert offs["wg_per_cu"] == 0 and offs["gk_weight"] == 32 and offs["lead_fine"] == 40
     assert offs["verify"] == 64 and offs["inner_rtol"] == 72 and offs["gmg_tail"] == 80
-    assert offs["gmg_omega"] == 88 and offs["cm_lds"] == 96 and offs["phase_timers"] == 100
+    assert offs["gmg_omega"] == 88 and offs["phase_timers"] == 96
     assert offs["wait_timeout_s"] == 104 and ctypes.sizeof(T) == 112
 
 

@@ -2,18 +2,17 @@
 against the oracle's (oracle/coarse_mesh.py), through the C ABI.
 
 Both sides solve the same coarse systems: the oracle directly, the library by
-Jacobi PCG to cg_rtol (the batched steps and the correction sweep as lanes of
-the engine launch, on groups of workgroups; the cold sweep on one workgroup).
-With cg_rtol 1e-13 for every solve each output must agree to 1e-10 (relative
-to the field's maximum), the bar of the other parity tests. Cases: cold starts
-on several grids (ragged tiles, N_tau = 1, an odd-index Dirichlet mask), warm
-starts and two iterations (the sweep's outputs then serve as G(u^k_n)), c-SIMP
-with the paper's time-varying load and p = 20, the cold sweep's vectors in LDS
-(small coarse meshes) and in global memory (forced here, the form of large
-ones), bitwise reproducibility, the status counters, N_tau iterations giving
-the sequential method, and the full 256 x 256 workload in the launch
-configuration the benchmark times (cold and warm cycles at its own cg_rtol
-1e-10, bar 1e-8 as in the other full-size tests).
+Jacobi PCG to cg_rtol in the engine's coarse-mesh lanes (the batched steps,
+the cold sweep and the correction sweep, on groups of workgroups). With
+cg_rtol 1e-13 for every solve each output must agree to 1e-10 (relative to the
+field's maximum), the bar of the other parity tests. Cases: cold starts on
+several grids (ragged tiles, N_tau = 1, an odd-index Dirichlet mask), warm
+starts and two iterations (the sweep's outputs then serve as G(u^k_n)),
+c-SIMP with the paper's time-varying load and p = 20, sweep groups of one and
+of many workgroups, bitwise reproducibility, the status counters, N_tau
+iterations giving the sequential method, and the full 256 x 256 workload in
+the launch configuration the benchmark times (cold and warm cycles at its own
+cg_rtol 1e-10, bar 1e-8 as in the other full-size tests).
 """
 import numpy as np
 import pytest
@@ -115,10 +114,12 @@ def test_coarse_mesh_full_size_256(gpu):
     _check(cfg, rho2, (cold["uT"], cold["utheta"], cold["lam"]), bar=1e-8)
 
 
-def test_coarse_mesh_global_memory_solver(gpu):
-    # the cold sweep's solve vectors in global memory (the form of coarse
-    # meshes too large for LDS) on a small case
-    cfg = _cfg(nx=24, ny=20, n_steps=30, n_slices=10, tuning=dict(cm_lds=0))
+@pytest.mark.parametrize("wgs", [1, 7, 64])
+def test_coarse_mesh_sweep_group_sizes(gpu, wgs):
+    # the coarse-mesh sweep lanes (cold and correction) on one workgroup, on a
+    # ragged split of the 143 coarse nodes, and on the most workgroups the
+    # planner gives a group of this grid (tiles of a few coarse nodes)
+    cfg = _cfg(nx=24, ny=20, n_steps=30, n_slices=10, tuning=dict(cm_sweep_wgs=wgs))
     rho = density_uniform_noise(24, 20, 44)
     _check(cfg, rho)
     _check(dict(cfg, iterations=2), rho)
