@@ -39,8 +39,8 @@ WORKLOAD = "plain_fp64_256"
 # WRITE_SIZE runs (each scaled by what the counter reads for a 1 GiB device
 # copy: x2.0 and x1.0), averaged over the forward and adjoint launches of a warm
 # cycle; valid only for the engine sources with this hash (see profiles/).
-TRAFFIC = {"sources_sha1": "ed70104b3096415b11e7a4c400b2b77bbcd135fd",
-           "bytes_per_launch": 0.5 * (28.66e9 + 28.68e9)}
+TRAFFIC = {"sources_sha1": "44e3a566aedc57eddd7d4398476b70737ea8b743",
+           "bytes_per_launch": 0.5 * (43.54e9 + 43.92e9)}
 
 
 def traffic_per_launch():
@@ -809,6 +809,7 @@ def large_run(name: str, steps: int) -> dict:
     cyc.run(rho)
     torch.cuda.synchronize()
     st_cold = cyc.status()
+    print(f"{name}: cold cycle done", file=sys.stderr, flush=True)
     gT, gth, gl = cyc.uT.clone(), cyc.utheta.clone(), cyc.lam.clone()
     stream = torch.cuda.current_stream()
     times = []
@@ -822,6 +823,7 @@ def large_run(name: str, steps: int) -> dict:
         ev[2].record(stream)
         torch.cuda.synchronize()
         times.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
+        print(f"{name}: warm cycle {sum(times[-1]):.0f} ms", file=sys.stderr, flush=True)
     st = cyc.status()
     cells = prob.n_elem * prob.n_steps
     ms = sum(a + b for a, b in times) / len(times)
