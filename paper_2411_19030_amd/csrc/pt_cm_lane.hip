@@ -111,7 +111,8 @@ __device__ __forceinline__ bool cml_reduce(double (&v)[Q], double *red, double *
     if (threadIdx.x == 0)
         for (int q = 0; q < Q; ++q) stc(part + ((size_t)par * kMaxGroup + rank) * 4 + q, v[q]);
     ++nbar;
-    if (!group_barrier(bar, nbar * (unsigned)g, ctl, tmo, release)) return false;
+    if (!group_barrier<false>(bar, (unsigned)g, nbar * (unsigned)g, ctl, tmo, release))
+        return false;
     group_sum<Q>(part + (size_t)par * kMaxGroup * 4, g, v, red);
     return true;
 }
@@ -167,7 +168,7 @@ __device__ __forceinline__ long long cm_lane(const EngineDesc *__restrict__ Ed, 
     }
     auto barrier = [&](bool rel) {
         ++nbar;
-        return group_barrier(bar, nbar * (unsigned)g, ctl, tmo, rel);
+        return group_barrier<false>(bar, (unsigned)g, nbar * (unsigned)g, ctl, tmo, rel);
     };
     auto waitf = [&](int fk, int n) {
         return wait_flag(B.flags, flag_index(fk, n), I.epoch, ctl, tmo);

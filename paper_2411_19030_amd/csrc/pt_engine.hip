@@ -114,34 +114,82 @@ __device__ __forceinline__ void lds_sync() {
     asm volatile("" ::: "memory");
 }
 
-// Group barrier. Every wave first waits for its own memory operations (the
-// device-coherent stores of this round) to complete; thread 0 then increments
-// the group counter and spins until all g workgroups have arrived. With
-// `release`, thread 0 also issues an agent-scope release fence first, which
-// publishes this workgroup's plain stores to other XCDs. Returns false on
-// timeout or when another workgroup aborted. Each group's counter has a cache
-// line of its own, and the spin reads the shared abort flag only every 64th
-// turn: the groups' polls then do not contend for one line.
-__device__ bool group_barrier(unsigned *cnt, unsigned target, Control *ctl, long long timeout,
-                              bool release) {
+// Group barrier of g workgroups. Every wave first waits for its own memory
+// operations (the device-coherent stores of this round) to complete; thread 0
+// then increments one of the group's counters, and the first wave spins until
+// the counters sum to all g workgroups' arrivals, reading them in one load of
+// up to eight lanes. Groups of kBarSplit or more workgroups spread their
+// arrivals over kBarParts counters (workgroup b on counter b % 8): device-scope
+// atomics on one address are performed one after another, which queued a large
+// group's arrivals on the round's critical path; smaller groups keep one
+// counter, where polling eight lines cost more than it saved. With `release`,
+// thread 0 also issues an agent-scope release fence first, which publishes
+// this workgroup's plain stores to other XCDs.
+// Returns false on timeout or when another workgroup aborted. Each counter has
+// a cache line of its own, and the spin reads the shared abort flag only every
+// 64th turn: the groups' polls then do not contend for one line.
+// SPLIT = false: always one counter. Every barrier of one group must count
+// its arrivals the same way: the engine instance with coarse-mesh lanes uses
+// one counter for all its groups (its registers are scarcer), the others
+// split by group size.
+constexpr int kBarSplit = 20;
+
+template <bool SPLIT = true>
+__device__ bool group_barrier(unsigned *cnt, unsigned g, unsigned target, Control *ctl,
+                              long long timeout, bool release) {
     __shared__ int s_ok;
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (release) __threadfence();
-        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (!SPLIT) {
+        // one counter: thread 0 arrives and spins
+        if (threadIdx.x == 0) {
+            if (release) __threadfence();
+            __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int ok = 1;
+            long long t0 = now_ticks();
+            unsigned spins = 0;
+            while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                if ((++spins & 63u) == 0 && (aborted(ctl) || now_ticks() - t0 > timeout)) {
+                    ok = 0;
+                    break;
+                }
+            }
+            s_ok = ok;
+        }
+    } else if (threadIdx.x < 64) {
+        // thread 0 arrives at counter b % parts; the first wave reads the
+        // counters in one load and sums them in scalar registers
+        const int lane = threadIdx.x;
+        const int parts = g >= (unsigned)kBarSplit ? kBarParts : 1;
+        if (lane == 0) {
+            if (release) __threadfence();
+            __hip_atomic_fetch_add(cnt + (blockIdx.x % parts) * kBarLine, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
         int ok = 1;
         long long t0 = now_ticks();
         unsigned spins = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        for (;;) {
+            const unsigned v = lane < parts ? __hip_atomic_load(cnt + lane * kBarLine,
+                                                                __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT)
+                                            : 0u;
+            unsigned sum = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+            if (parts > 1) {
+#pragma unroll
+                for (int k = 1; k < kBarParts; ++k)
+                    sum += (unsigned)__builtin_amdgcn_readlane((int)v, k);
+            }
+            if (sum >= target) break;
             __builtin_amdgcn_s_sleep(1);
             if ((++spins & 63u) == 0 && (aborted(ctl) || now_ticks() - t0 > timeout)) {
                 ok = 0;
                 break;
             }
         }
-        s_ok = ok;
+        if (lane == 0) s_ok = ok;
     }
     __syncthreads();
     asm volatile("" ::: "memory");
@@ -803,7 +851,8 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
                                                                __ATOMIC_RELAXED,
                                                                __HIP_MEMORY_SCOPE_AGENT));
             ++nbar;
-            ok = group_barrier(bar, nbar * (unsigned)g, ctl, S.timeout_ticks, false);
+            ok = group_barrier<!CMESH>(bar, (unsigned)g, nbar * (unsigned)g, ctl,
+                                       S.timeout_ticks, false);
             if (!ok) break;
             const int pos = ldc(S.qslot + gid);
             if (pos >= G.nlanes) break;
@@ -903,10 +952,12 @@ __global__ void __launch_bounds__(kThreads) k_engine(const EngineDesc *__restric
         auto barrier = [&](bool release) -> bool {
             ++nbar;
             if constexpr (!timers) {
-                return group_barrier(bar, nbar * (unsigned)g, ctl, tmo, release);
+                return group_barrier<!CMESH>(bar, (unsigned)g, nbar * (unsigned)g, ctl, tmo,
+                                             release);
             } else {
                 const long long t0 = now_ticks();
-                const bool r = group_barrier(bar, nbar * (unsigned)g, ctl, tmo, release);
+                const bool r = group_barrier<!CMESH>(bar, (unsigned)g, nbar * (unsigned)g, ctl,
+                                                     tmo, release);
                 const long long t1 = now_ticks();
                 if (timer) {
                     t_work += t0 - t_mark;

@@ -15,7 +15,9 @@ constexpr int kMaxGroup = 1024;     // workgroups per lane group (partials slots
 constexpr int kVecsPerLane = 10;    // x, p, r[2], w[2], s[2], tp, tq
 constexpr int kMaxFlags = 4 * 4096; // dependency flags per launch
 constexpr int kMaxLevels = 16;      // multigrid levels (level 0 = the element grid)
-constexpr int kBarStride = 64;      // words between group barrier counters (one 256-B line each)
+constexpr int kBarLine = 64;        // words per barrier counter (one 256-B line each)
+constexpr int kBarParts = 8;        // counters per group barrier (workgroup b arrives at b % 8)
+constexpr int kBarStride = kBarLine * kBarParts;  // words per group's barrier
 
 // Lane kinds: a lane is a sequence of linear solves executed by one group of
 // workgroups; lanes of one launch run concurrently and meet only through flags.
@@ -220,7 +222,7 @@ struct Launch {
     const int *wg_group;   // [grid] group of each workgroup (-1: idle)
     const Group *groups;   // [n_groups]
     const Lane *lanes;     // [n_lanes]
-    unsigned *bar;         // [kMaxGroups][kBarStride] group barrier counters, one line per group
+    unsigned *bar;         // [kMaxGroups][kBarParts][kBarLine] group barrier counters
     double *partials;      // [kMaxGroups][2][kMaxGroup][4]
     double *xch;           // resident-mode halo exchange [grid][2][2][3][xch_stride]
     int xch_stride;        // >= W + 1 of every design
