@@ -109,6 +109,16 @@ def test_explicit_mask(gpu):
     _check(compare(g, o))
 
 
+def test_no_dirichlet_node(gpu):
+    """No Dirichlet node (PT_BC_NONE): C/dt + K stays SPD through its mass
+    term, and the body heats up under the uniform source."""
+    cfg = _cfg(nx=20, ny=14, n_steps=24, n_slices=6, bc="none")
+    rho = density_uniform_noise(20, 14, 12)
+    o = run_oracle(cfg, rho)
+    g = run_gpu(cfg, rho)
+    _check(compare(g, o))
+
+
 def test_bitwise_deterministic(gpu):
     """Two runs give bitwise-equal outputs (fixed-order reductions, no races)."""
     cfg = _cfg(nx=40, ny=40, n_steps=32, n_slices=8, cg_rtol=1e-10)

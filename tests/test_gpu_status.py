@@ -124,3 +124,41 @@ def test_phase_timers_only_when_asked_for_and_results_unchanged(gpu):
     assert sum(r["work_us"] for r in on["trace"]) > 0
     for tr in (off["trace"], on["trace"]):
         assert all(r["rounds"] > 0 and r["step_end_us"] for r in tr)
+
+
+PT_EDOMAIN = -5
+
+
+@pytest.mark.parametrize("bad", [-0.25, float("nan")])
+def test_negative_or_nan_density_reports_edomain(gpu, bad):
+    """A density below 0 or not a number: the material law takes it as 0, so
+    every kernel runs as for that design, bit for bit, and both passes report
+    PT_EDOMAIN."""
+    rho = density_uniform_noise(32, 32, 7)
+    ref = rho.copy()
+    ref[100] = 0.0
+    r = rho.copy()
+    r[100] = bad
+    g0, f0, a0 = _passes(_cfg(), ref)
+    assert f0["status"] == a0["status"] == 0
+    g, sf, sa = _passes(_cfg(), r)
+    print(bad, sf, sa, flush=True)
+    assert sf["status"] == sa["status"] == PT_EDOMAIN
+    for k in ("S", "uT", "lam", "grad"):
+        assert np.array_equal(g[k], g0[k]), k
+    assert g["Theta"] == g0["Theta"]
+
+
+def test_zero_objective_reports_edomain(gpu):
+    """With no heat source T stays 0 (every solve sees b = 0 and returns x = 0
+    at once), so Theta = 0: the forward pass writes its outputs and reports
+    PT_EDOMAIN for the result. The adjoint source Theta^(1-p) (Eq. 4.6) is then
+    not defined; the adjoint pass reports PT_EDOMAIN too, its solves seeing a
+    non-finite right-hand side and ending at the iteration cap, which keeps
+    the test short."""
+    g, sf, sa = _passes(_cfg(q=0.0, max_iter=30), density_uniform_noise(32, 32, 3))
+    print(sf, sa, flush=True)
+    assert sf["status"] == PT_EDOMAIN and sf["max_cg_iters"] == 0
+    assert g["Theta"] == 0.0
+    assert np.all(g["S"] == 0.0) and np.all(g["uT"] == 0.0)
+    assert sa["status"] == PT_EDOMAIN
