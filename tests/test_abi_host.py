@@ -49,6 +49,8 @@ def base(**kw):
     dict(coarse_iters=5, propagator=1), dict(coarse_iters=5, precond=1),
     # the coarse spatial mesh halves even grids
     dict(propagator=2, nx=9), dict(propagator=2, ny=7), dict(propagator=2, coarse_iters=5),
+    # size limits: 16384 elements per side, 4000 slices
+    dict(nx=16385), dict(ny=16385), dict(n_steps=8002, n_slices=4001), dict(pnorm=-2),
 ])
 def test_validate_rejects(lib, kw):
     p = base(**kw)
@@ -69,6 +71,13 @@ def test_validate_accepts_and_sizes(lib):
     small = _pt.pt_workspace_bytes(p)
     big = _pt.pt_workspace_bytes(base(nx=64, ny=64))
     assert 0 < small < big
+    # the largest accepted grid and slice count size without overflow
+    edge = base(nx=16384, ny=16384, n_steps=8000, n_slices=4000)
+    assert _pt.pt_validate(edge) == _pt.PT_OK
+    nn = 16385 * 16385
+    # at least the slice-boundary states of the previous and the corrected
+    # iterate (two FP64 arrays of N_tau + 1 rows)
+    assert _pt.pt_workspace_bytes(edge) > 2 * 8 * nn * 4001
 
 
 def test_time_dependent_source_must_be_finite(lib):
