@@ -190,7 +190,7 @@ def test_batched_autograd(gpu):
     (w * th).sum().backward()
     for k, (nx, ny, nt, ns) in enumerate(shapes):
         o = _oracle(dict(nx=nx, ny=ny, n_steps=nt, n_slices=ns, pnorm=8), rhos_np[k])
-        assert abs(float(th[k]) - o["Theta"]) <= 1e-10 * o["Theta"]
+        assert abs(float(th[k].detach()) - o["Theta"]) <= 1e-10 * o["Theta"]
         g = rhos[k].grad.cpu().numpy()
         assert np.linalg.norm(g - float(w[k]) * o["grad"]) <= 1e-10 * abs(float(w[k])) * \
             np.linalg.norm(o["grad"])
