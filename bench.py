@@ -851,8 +851,9 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the pass would shard by time slices across GPUs, see the design notes)",
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the passes "
+              "would shard by time slices across GPUs, with the sequential sweeps handed on "
+              "from GPU to GPU)",
               file=sys.stderr)
         sys.exit(2)
     import torch
