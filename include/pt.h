@@ -109,6 +109,9 @@ typedef struct pt_tuning {
                                /* without coarse-mesh lanes (slows the rounds)              (0) */
     double wait_timeout_s;     /* a device wait gives up after this long (PT_EHIP);        */
                                /* 0: 20 s (60 s in batched launches)                         (0) */
+    int32_t gk_lag;            /* shared queue: the batched coarse step of slice n follows  */
+                               /* the fine lane of slice n + gk_lag along the sweep, so the */
+                               /* long fine lanes start earlier; -1: min(6, N_tau / 5)     (-1) */
 } pt_tuning;
 
 typedef struct pt_problem {

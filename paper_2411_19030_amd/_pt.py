@@ -48,7 +48,7 @@ class PtTuning(ctypes.Structure):
         ("inner_rtol", ctypes.c_double), ("gmg_tail", ctypes.c_int32),
         ("gmg_sweeps", ctypes.c_int32), ("gmg_omega", ctypes.c_double),
         ("phase_timers", ctypes.c_int32),
-        ("wait_timeout_s", ctypes.c_double),
+        ("wait_timeout_s", ctypes.c_double), ("gk_lag", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

@@ -49,6 +49,7 @@ pt_tuning default_settings() {
     t.gmg_omega = 1.3;
     t.phase_timers = 0;
     t.wait_timeout_s = 0.0;
+    t.gk_lag = -1;
     return t;
 }
 
@@ -68,7 +69,7 @@ bool valid_settings(const pt_tuning &t) {
            t.inner_rtol > 0.0 && t.inner_rtol < 1.0 && t.gmg_tail >= 0 && t.gmg_sweeps >= 1 &&
            t.gmg_sweeps <= 1000 && t.gmg_omega > 0.0 && isfinite(t.gmg_omega) &&
            bool01(t.phase_timers) && t.wait_timeout_s >= 0.0 &&
-           isfinite(t.wait_timeout_s);
+           isfinite(t.wait_timeout_s) && t.gk_lag >= -1 && t.gk_lag <= 4096;
 }
 
 
@@ -697,6 +698,7 @@ struct QueueArgs {
     int ngroups, nwg, tile;
     int kindA, nA, sA0, dirA;
     int kindB, nB, sB0, dirB;
+    int lagB;  // B's slice n goes after A's slice n + lagB along the sweep
 };
 
 struct PlanArgs {
@@ -745,11 +747,13 @@ __global__ void k_build_plan(PlanArgs P, Group *groups, Lane *lanes, int *wg_gro
     const QueueArgs &Q = P.Q;
     if (Q.ngroups > 0) {
         const int lane0 = lidx;
-        // merge the two slice sequences by position along the sweep
+        // merge the two slice sequences by position along the sweep, B lagging
+        // lagB slices behind A (both run in the same direction)
         int ia = 0, ib = 0;
         while (ia < Q.nA || ib < Q.nB) {
             const int sa = Q.sA0 + Q.dirA * ia, sb = Q.sB0 + Q.dirB * ib;
-            const bool takeA = ib >= Q.nB || (ia < Q.nA && Q.dirA * sa <= Q.dirA * sb);
+            const bool takeA =
+                ib >= Q.nB || (ia < Q.nA && Q.dirA * sa <= Q.dirA * sb + Q.lagB);
             lanes[lidx].kind = takeA ? Q.kindA : Q.kindB;
             lanes[lidx].slice = takeA ? sa : sb;
             lanes[lidx].design = 0;
@@ -985,6 +989,10 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
         Q.nB = plans[qb].count;
         Q.sB0 = plans[qb].slice0;
         Q.dirB = plans[qb].dir;
+        // a fine lane takes about as long as the sweep's next several steps:
+        // queued a few slices ahead of the batched coarse steps, the last fine
+        // lanes no longer hold up the sweep's last steps
+        Q.lagB = T.gk_lag >= 0 ? T.gk_lag : std::min(6, C.Ntau / 5);
     }
     for (size_t k = 0; k < plans.size(); ++k) {
         const auto &p = plans[k];

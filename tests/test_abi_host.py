@@ -147,20 +147,21 @@ def test_tuning_layout_matches_header():
     assert offs["wg_per_cu"] == 0 and offs["gk_weight"] == 32 and offs["lead_fine"] == 40
     assert offs["verify"] == 64 and offs["inner_rtol"] == 72 and offs["gmg_tail"] == 80
     assert offs["gmg_omega"] == 88 and offs["phase_timers"] == 96
-    assert offs["wait_timeout_s"] == 104 and ctypes.sizeof(T) == 112
+    assert offs["wait_timeout_s"] == 104 and offs["gk_lag"] == 112 and ctypes.sizeof(T) == 120
 
 
 def test_default_tuning_and_its_validation(lib):
     d = _pt.default_tuning()
     assert d["wg_per_cu"] == 1 and d["resident"] == -1 and d["verify"] == 1
     assert d["phase_timers"] == 0 and d["tile_max"] == 4096 and d["gk_weight"] == 4.0
+    assert d["gk_lag"] == -1
     assert lib.pt_default_tuning(None) == _pt.PT_EINVAL
     assert lib.pt_validate(ctypes.byref(base(tuning=dict(resident=0)).to_c())) == _pt.PT_OK
     assert lib.pt_validate(ctypes.byref(base(tuning=dict(phase_timers=1)).to_c())) == _pt.PT_OK
     for bad in (dict(wg_per_cu=0), dict(resident=2), dict(resident_npt_max=9),
                 dict(gk_weight=0.0), dict(tile_max=128), dict(ck_slots=0), dict(verify=2),
                 dict(inner_rtol=1.0), dict(gmg_omega=float("nan")), dict(phase_timers=-1),
-                dict(wait_timeout_s=-1.0), dict(cm_sweep_wgs=0)):
+                dict(wait_timeout_s=-1.0), dict(cm_sweep_wgs=0), dict(gk_lag=-2)):
         c = base(tuning=bad).to_c()
         assert lib.pt_validate(ctypes.byref(c)) == _pt.PT_EINVAL, bad
         assert lib.pt_workspace_bytes(ctypes.byref(c)) == 0, bad
