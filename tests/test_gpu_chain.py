@@ -70,7 +70,7 @@ def test_one_shot_chain_against_oracle(gpu, plt):
         if i == 0:
             obj.guess_T, obj.guess_theta = exact.guess_T, exact.guess_theta
             obj.guess_lambda = exact.guess_lambda
-        et = abs(float(th) - ref[i][0]) / ref[i][0]
+        et = abs(float(th.detach()) - ref[i][0]) / ref[i][0]
         g = x.grad.cpu().numpy()
         eg = float(np.linalg.norm(g - ref[i][1]) / np.linalg.norm(ref[i][1]))
         print("cycle", i, "plt" if plt else "parareal", et, eg, flush=True)

@@ -114,7 +114,7 @@ def test_chain_through_filter_and_objective(gpu):
     S, th = O.forward_sequential(d)
     _, g_rho = O.adjoint_sequential(d, S, th[-1])
     g_chi = O.filter_projection_backward(o_fil, g_rho, nx, ny, r, beta, eta)
-    et = abs(float(theta) - th[-1]) / th[-1]
+    et = abs(float(theta.detach()) - th[-1]) / th[-1]
     eg = float(np.linalg.norm(x.grad.cpu().numpy() - g_chi) / np.linalg.norm(g_chi))
     print(et, eg, flush=True)
     assert et <= 1e-10 and eg <= 1e-10
