@@ -39,8 +39,8 @@ WORKLOAD = "plain_fp64_256"
 # WRITE_SIZE runs (each scaled by what the counter reads for a 1 GiB device
 # copy: x2.0 and x1.0), averaged over the forward and adjoint launches of a warm
 # cycle; valid only for the engine sources with this hash (see profiles/).
-TRAFFIC = {"sources_sha1": "81893a544ea0a92a6ac17693e195a188f1b9645c",
-           "bytes_per_launch": 0.5 * (43.62e9 + 43.99e9)}
+TRAFFIC = {"sources_sha1": "5b6c87d5dec37de72213bcbd78e283b744a39966",
+           "bytes_per_launch": 0.5 * (44.45e9 + 44.97e9)}
 
 
 def traffic_per_launch():

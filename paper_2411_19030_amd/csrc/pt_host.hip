@@ -806,14 +806,15 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
     // per-round phase times: FP64 launches without coarse-mesh lanes only
     const bool timed = T.phase_timers != 0 && !C.fp32 && !cm;
     // sweep group: 40 workgroups. A resident sweep of full solves to a tight
-    // tolerance is the longest lane of the pass: it gets about 1200 nodes per
-    // workgroup within 40..56 (measured best at 256^2 and 100^2 with rtol
-    // 1e-10); shorter sweeps (truncated or loose solves) leave the fine lanes
-    // critical, and there more sweep workgroups only slow the fine lanes
+    // tolerance is the longest lane of the pass: it gets about 1000 nodes per
+    // workgroup within 40..64 (a quarter of the grid; measured best at 256^2
+    // and 100^2 with rtol 1e-10, the fine lanes queued ahead of the batched
+    // coarse steps); shorter sweeps (truncated or loose solves) leave the fine
+    // lanes critical, and there more sweep workgroups only slow the fine lanes
     const int sweep_wgs = T.sweep_wgs > 0 ? T.sweep_wgs : 40;
     const bool long_sweep = C.coarse_iters == 0 && C.rtol < 1e-9;
     const int sweep_wgs_res =
-        T.sweep_wgs > 0 ? T.sweep_wgs : long_sweep ? std::min(56, std::max(40, C.Nn / 1200)) : 40;
+        T.sweep_wgs > 0 ? T.sweep_wgs : long_sweep ? std::min(64, std::max(40, C.Nn / 1000)) : 40;
 
     const int NT = kThreads;
     const int res_npt_max = T.resident_npt_max;
