@@ -86,6 +86,10 @@ def parse():
                     help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (counter calibration)")
+    ap.add_argument("--lane-trace", action="store_true",
+                    help="with the headline workload or cmesh_fp64_256: print the lane trace "
+                         "of a warm cycle per pass (rounds, CG iterations and times per lane "
+                         "kind; per-round phase times on the headline) instead of the bench line")
     ap.add_argument("--autotune", action="store_true",
                     help="with --workload batch_fp32_64: run pt_autotune_batched on the batch "
                          "(FP32+refine) and print the shape it picks (the source of BATCH_TUNING)")
@@ -788,6 +792,82 @@ def batch_compare(rtol=1e-7, ref_rtol=1e-12, accuracy=1e-6, replays=5) -> dict:
     }
 
 
+def lane_trace(prob, rho, timers: bool) -> list:
+    """Lane trace of a warm cycle (guesses from the cold cycle), one record per
+    pass: per lane kind the lanes, group rounds, CG iterations, summed lane
+    time and time per round, with `timers` the per-round phase times (work,
+    barrier, partial sums) and the flag waits; the sweep's start and step
+    times; every fine lane's start and end. Times in microseconds from the
+    first lane's start (the 100 MHz device clock)."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2411_19030_amd._pt import pt_query_trace
+    from paper_2411_19030_amd.cycle import Cycle
+    if timers:
+        prob = dataclasses.replace(prob, tuning=dict(phase_timers=1))
+    cyc = Cycle(prob, rho.device)
+    cyc.run(rho)
+    torch.cuda.synchronize()
+    g = (cyc.uT.clone(), cyc.utheta.clone(), cyc.lam.clone())
+    cyc.run(rho, *g)
+    torch.cuda.synchronize()
+    out = []
+    for name, fn in (("forward", lambda: cyc.forward(rho, g[0], g[1])),
+                     ("adjoint", lambda: cyc.adjoint(rho, g[2]))):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        tr = pt_query_trace(prob, cyc.ws)
+        kinds = {}
+        for r in tr:
+            k = kinds.setdefault(r["kind"], dict(lanes=0, nwg=[], rounds=0, iters=0,
+                                                 lane_us=0.0, work=0.0, barrier=0.0,
+                                                 partial_sums=0.0, flag_wait_us=0.0,
+                                                 last_end_us=0.0))
+            end = r["step_end_us"][-1] if r["step_end_us"] else r["start_us"]
+            k["lanes"] += 1
+            if r["nwg"] not in k["nwg"]:
+                k["nwg"] = sorted(k["nwg"] + [r["nwg"]])
+            k["rounds"] += r["rounds"]
+            k["iters"] += r["iters"]
+            k["lane_us"] += end - r["start_us"]
+            k["work"] += r["work_us"]
+            k["barrier"] += r["barrier_us"]
+            k["partial_sums"] += r["reduce_us"]
+            k["flag_wait_us"] += r["flag_us"]
+            k["last_end_us"] = max(k["last_end_us"], end)
+        for k in kinds.values():
+            n = max(k["rounds"], 1)
+            k["us_per_round"] = round(k["lane_us"] / n, 2)
+            if timers:
+                k["per_round_us"] = {q: round(k[q] / n, 2) for q in ("work", "barrier",
+                                                                      "partial_sums")}
+            for q in ("work", "barrier", "partial_sums"):
+                del k[q]
+            if not timers:
+                del k["flag_wait_us"]
+            for q in ("lane_us", "last_end_us", "flag_wait_us"):
+                if q in k:
+                    k[q] = round(k[q])
+        rec = {"pass": name, "launch_ms": round(e0.elapsed_time(e1), 2), "kinds": kinds}
+        sw = [r for r in tr if "SWEEP" in r["kind"]]
+        if sw:
+            st = np.diff([sw[0]["start_us"]] + sw[0]["step_end_us"])
+            rec["sweep_start_us"] = round(sw[0]["start_us"])
+            rec["sweep_step_us"] = [round(float(x)) for x in st]
+        rec["fine_lanes_us"] = {str(r["slice"]): [round(r["start_us"]),
+                                                  round(r["step_end_us"][-1])]
+                                for r in sorted(tr, key=lambda r: r["start_us"])
+                                if r["kind"] in ("F_PRI", "F_ADJ") and r["step_end_us"]}
+        out.append(rec)
+    return out
+
+
 def large_run(name: str, steps: int) -> dict:
     """The large single design (2048 x 2048, 2048 steps in 128 slices, Gaussian-bump
     density; the same law at 512 x 512 with 512 steps in 32 slices): geometric
@@ -888,6 +968,22 @@ def main():
         print(json.dumps(plt_compare(prob, rho, None, None,
                                      precisions=(("fp64", 0, prob.cg_rtol),),
                                      repeats=max(1, args.steps))))
+        return
+    if args.lane_trace:
+        if args.workload not in (WORKLOAD, "cmesh_fp64_256"):
+            sys.exit("--lane-trace: the headline workload or cmesh_fp64_256")
+        w = workload(WORKLOAD)
+        cm = args.workload == "cmesh_fp64_256"
+        prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
+                       pnorm=w["p"], k0=w["k0"], kmin=w["kmin"], pk=w["pk"], c0=w["c0"],
+                       cmin=w["cmin"], pc=w["pc"], q=w["q"], t_final=w["t_final"], bc=w["bc"],
+                       iterations=1, cg_rtol=w["rtol"], max_iter=20000,
+                       propagator=2 if cm else 0)
+        rho = torch.tensor(workload_density(WORKLOAD), dtype=torch.float64,
+                           device=torch.device("cuda:0"))
+        # per-round phase times exist in FP64 launches without coarse-mesh lanes
+        for rec in lane_trace(prob, rho, timers=not cm):
+            print(json.dumps(rec), flush=True)
         return
     if args.workload == "cmesh_fp64_256":
         # the coarse-spatial-mesh cycle of the headline workload on its own
