@@ -936,6 +936,10 @@ def main():
               "from GPU to GPU)",
               file=sys.stderr)
         sys.exit(2)
+    if args.lane_trace and args.workload not in (WORKLOAD, "cmesh_fp64_256"):
+        print(f"bench.py: --lane-trace takes the headline workload or cmesh_fp64_256, "
+              f"not {args.workload}", file=sys.stderr)
+        sys.exit(2)
     import torch
 
     from paper_2411_19030_amd import Problem, load_library
@@ -943,6 +947,20 @@ def main():
     from workloads import workload, workload_density
 
     load_library()
+    if args.lane_trace:
+        w = workload(WORKLOAD)
+        cm = args.workload == "cmesh_fp64_256"
+        prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
+                       pnorm=w["p"], k0=w["k0"], kmin=w["kmin"], pk=w["pk"], c0=w["c0"],
+                       cmin=w["cmin"], pc=w["pc"], q=w["q"], t_final=w["t_final"], bc=w["bc"],
+                       iterations=1, cg_rtol=w["rtol"], max_iter=20000,
+                       propagator=2 if cm else 0)
+        rho = torch.tensor(workload_density(WORKLOAD), dtype=torch.float64,
+                           device=torch.device("cuda:0"))
+        # per-round phase times exist in FP64 launches without coarse-mesh lanes
+        for rec in lane_trace(prob, rho, timers=not cm):
+            print(json.dumps(rec), flush=True)
+        return
     if args.workload in ("large_2048", "large_law_512"):
         print(json.dumps(large_run(args.workload, max(1, min(args.steps, 3)))))
         return
@@ -968,22 +986,6 @@ def main():
         print(json.dumps(plt_compare(prob, rho, None, None,
                                      precisions=(("fp64", 0, prob.cg_rtol),),
                                      repeats=max(1, args.steps))))
-        return
-    if args.lane_trace:
-        if args.workload not in (WORKLOAD, "cmesh_fp64_256"):
-            sys.exit("--lane-trace: the headline workload or cmesh_fp64_256")
-        w = workload(WORKLOAD)
-        cm = args.workload == "cmesh_fp64_256"
-        prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
-                       pnorm=w["p"], k0=w["k0"], kmin=w["kmin"], pk=w["pk"], c0=w["c0"],
-                       cmin=w["cmin"], pc=w["pc"], q=w["q"], t_final=w["t_final"], bc=w["bc"],
-                       iterations=1, cg_rtol=w["rtol"], max_iter=20000,
-                       propagator=2 if cm else 0)
-        rho = torch.tensor(workload_density(WORKLOAD), dtype=torch.float64,
-                           device=torch.device("cuda:0"))
-        # per-round phase times exist in FP64 launches without coarse-mesh lanes
-        for rec in lane_trace(prob, rho, timers=not cm):
-            print(json.dumps(rec), flush=True)
         return
     if args.workload == "cmesh_fp64_256":
         # the coarse-spatial-mesh cycle of the headline workload on its own

@@ -20,6 +20,12 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in r.stderr
 
 
+def test_lane_trace_refuses_other_workloads_before_any_device_work():
+    r = _run("--workload", "plt_fp64_256", "--lane-trace")
+    assert r.returncode == 2
+    assert "--lane-trace" in r.stderr
+
+
 def test_help_lists_the_workloads():
     r = _run("--help")
     assert r.returncode == 0
