@@ -95,7 +95,8 @@ typedef struct pt_tuning {
                                /* from                                                       (1) */
     int32_t shared_queue;      /* 1: resident fine and batched coarse lanes share a queue   (1)  */
     int32_t tile_max;          /* largest streaming tile in nodes, >= 256                   (4096) */
-    int32_t ck_slots;          /* PT_CHECKPOINT: fine-lane groups (recompute slots), >= 1   (16) */
+    int32_t ck_slots;          /* PT_CHECKPOINT: fine-lane groups (recompute slots), >= 1;  */
+                               /* fewer if the grid cannot hold them beside the sweeps  (24) */
     int32_t extrap;            /* 1: fine steps start from 2 T_{j-1} - T_{j-2}               (0) */
     int32_t sweep_x0;          /* 1: a sweep step starts from G(u^k_n) + (u^{k+1}_n - u^k_n),  */
                                /* 0: from u^{k+1}_n                                          (1) */

@@ -39,7 +39,7 @@ pt_tuning default_settings() {
     t.lead_fine = 1;
     t.shared_queue = 1;
     t.tile_max = 4096;
-    t.ck_slots = 16;
+    t.ck_slots = 24;
     t.extrap = 0;
     t.sweep_x0 = 1;
     t.verify = 1;
@@ -911,6 +911,28 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
             }
             fixed += nwg[k] * ngroups[k];
             groups += ngroups[k];
+        }
+        if (C.ckpt) {
+            // checkpointed fine lanes: as many of their fixed groups (at most
+            // the recompute slots) as the grid holds beside the sweep groups,
+            // leaving the batched coarse steps, if any, a sweep group's worth
+            // of workgroups; fewer groups change no result (one group shape)
+            int nshare = 0;
+            for (const auto &p : plans)
+                if (!p.latency && p.fixed_nwg <= 0 && p.count > 0) ++nshare;
+            const int reserve = nshare > 0 ? std::max(nshare * kMinStreamWgs, sweep_wgs) : 0;
+            for (size_t k = 0; k < plans.size(); ++k) {
+                const auto &p = plans[k];
+                if (p.latency || p.fixed_nwg <= 0 || (p.kind != F_PRI && p.kind != F_ADJ))
+                    continue;
+                const int other = fixed - nwg[k] * ngroups[k];
+                const int fit = (grid - other - reserve) / nwg[k];
+                if (fit >= 1 && fit < ngroups[k]) {
+                    fixed -= nwg[k] * (ngroups[k] - fit);
+                    groups -= ngroups[k] - fit;
+                    ngroups[k] = fit;
+                }
+            }
         }
         const int rest = std::max(grid - fixed, 0);
         int budget = Lay.s.max_groups - groups;
