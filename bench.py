@@ -79,7 +79,8 @@ def parse():
                     help="skip the 64-design batch (batched FP32+refine vs plain FP64)")
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=[WORKLOAD, "batch_fp32_64", "large_2048", "large_law_512",
-                             "paper_100", "one_shot_chain", "plt_fp64_256", "cmesh_fp64_256"],
+                             "paper_100", "one_shot_chain", "plt_fp64_256", "cmesh_fp64_256",
+                             "diff_fp64_512"],
                     help="the headline workload (default), or one of the other workloads "
                          "measured on its own")
     ap.add_argument("--cpu-sample-only", type=int, default=0, metavar="WORKERS",
@@ -868,6 +869,54 @@ def lane_trace(prob, rho, timers: bool) -> list:
     return out
 
 
+def plain_run(name: str, steps: int, warmup: int) -> dict:
+    """A store-all FP64 Jacobi workload other than the headline (diff_fp64_512:
+    512 x 512, 1024 steps in 64 slices, the streaming engine): one cold cycle,
+    `warmup` untimed and `steps` timed warm cycles from its guesses, each timed
+    with HIP events on the stream (forward, then adjoint + sensitivities)."""
+    import torch
+
+    from paper_2411_19030_amd import Problem
+    from paper_2411_19030_amd.cycle import Cycle
+    from workloads import workload, workload_density
+
+    w = workload(name)
+    dev = torch.device("cuda:0")
+    prob = Problem(nx=w["nx"], ny=w["ny"], n_steps=w["n_steps"], n_slices=w["n_slices"],
+                   pnorm=w["p"], cg_rtol=w["rtol"], max_iter=20000)
+    cyc = Cycle(prob, dev)
+    rho = torch.tensor(workload_density(name), dtype=torch.float64, device=dev)
+    cyc.run(rho)
+    torch.cuda.synchronize()
+    gT, gth, gl = cyc.uT.clone(), cyc.utheta.clone(), cyc.lam.clone()
+    stream = torch.cuda.current_stream()
+    times = []
+    for i in range(warmup + steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        cyc.forward(rho, gT, gth)
+        ev[1].record(stream)
+        cyc.adjoint(rho, gl)
+        cyc.sensitivities(rho)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        if i >= warmup:
+            times.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
+    st = cyc.status()
+    cells = prob.n_elem * prob.n_steps
+    ms = sum(a + b for a, b in times) / len(times)
+    return {"metric": "fine-step cell-updates/s (fwd+adjoint+sens per cycle)",
+            "value": cells / (ms * 1e-3), "unit": "cell-updates/s", "n_gpus": 1,
+            "steps": steps, "warmup": warmup, "ms_per_step": ms, "higher_is_better": True,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": name, "nx": prob.nx, "ny": prob.ny, "n_steps": prob.n_steps,
+                       "n_slices": prob.n_slices, "cg_rtol": prob.cg_rtol},
+            "phase_ms": {"forward": sum(a for a, _ in times) / len(times),
+                         "adjoint_and_sensitivities": sum(b for _, b in times) / len(times)},
+            "status": st["status"], "cg_iterations": st["cg_iters_fine"] + st["cg_iters_coarse"],
+            "Theta": float(cyc.Theta)}
+
+
 def large_run(name: str, steps: int) -> dict:
     """The large single design (2048 x 2048, 2048 steps in 128 slices, Gaussian-bump
     density; the same law at 512 x 512 with 512 steps in 32 slices): geometric
@@ -960,6 +1009,10 @@ def main():
         # per-round phase times exist in FP64 launches without coarse-mesh lanes
         for rec in lane_trace(prob, rho, timers=not cm):
             print(json.dumps(rec), flush=True)
+        return
+    if args.workload == "diff_fp64_512":
+        print(json.dumps(plain_run(args.workload, max(1, min(args.steps, 5)),
+                                   max(0, min(args.warmup, 2)))))
         return
     if args.workload in ("large_2048", "large_law_512"):
         print(json.dumps(large_run(args.workload, max(1, min(args.steps, 3)))))

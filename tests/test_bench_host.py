@@ -30,7 +30,7 @@ def test_help_lists_the_workloads():
     r = _run("--help")
     assert r.returncode == 0
     for w in ("plain_fp64_256", "batch_fp32_64", "large_2048", "paper_100", "one_shot_chain",
-              "plt_fp64_256", "cmesh_fp64_256"):
+              "plt_fp64_256", "cmesh_fp64_256", "diff_fp64_512"):
         assert w in r.stdout
 
 
