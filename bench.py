@@ -39,8 +39,8 @@ WORKLOAD = "plain_fp64_256"
 # WRITE_SIZE runs (each scaled by what the counter reads for a 1 GiB device
 # copy: x2.0 and x1.0), averaged over the forward and adjoint launches of a warm
 # cycle; valid only for the engine sources with this hash (see profiles/).
-TRAFFIC = {"sources_sha1": "fbe07a9e0527c828917afb9ed88ac492d33cf150",
-           "bytes_per_launch": 0.5 * (44.45e9 + 44.99e9)}
+TRAFFIC = {"sources_sha1": "65d8a9b8ac3279a3b89c5c61efe59dc228c1cb48",
+           "bytes_per_launch": 0.5 * (44.44e9 + 45.00e9)}
 
 
 def traffic_per_launch():

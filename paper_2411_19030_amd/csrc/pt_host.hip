@@ -945,13 +945,14 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
             const double share = wsum > 0.0 ? rest * p.weight * p.count / wsum : 0.0;
             int q = p.queues > 0 ? std::min(p.queues, p.count)
                                  : std::min(p.count, std::max(1, (int)(share / kMinStreamWgs)));
-            if (p.queues <= 0 && has_sweep && !C.ckpt) {
+            if (p.queues <= 0 && has_sweep) {
                 // a sweep consumes these lanes' results slice by slice: run them
                 // in balanced waves on groups of about three tiles per
                 // workgroup, so results arrive in sweep order and a round
                 // streams few tiles (at 512^2: 7 fine groups in 9 waves and
                 // one coarse-step group, 37% faster than all lanes at once on
-                // groups of 4 workgroups)
+                // groups of 4 workgroups; checkpointed fine lanes keep their
+                // fixed groups, their batched coarse steps take one group)
                 const long long tile = std::max(256, std::min(T.tile_max, 4096));
                 const int target =
                     std::max(kMinStreamWgs, (int)((C.Nn + 3 * tile - 1) / (3 * tile)));
