@@ -39,8 +39,8 @@ WORKLOAD = "plain_fp64_256"
 # WRITE_SIZE runs (each scaled by what the counter reads for a 1 GiB device
 # copy: x2.0 and x1.0), averaged over the forward and adjoint launches of a warm
 # cycle; valid only for the engine sources with this hash (see profiles/).
-TRAFFIC = {"sources_sha1": "65d8a9b8ac3279a3b89c5c61efe59dc228c1cb48",
-           "bytes_per_launch": 0.5 * (44.44e9 + 45.00e9)}
+TRAFFIC = {"sources_sha1": "914e6666097f101ed76609b3fbc97b573fb68a26",
+           "bytes_per_launch": 0.5 * (44.44e9 + 44.98e9)}
 
 
 def traffic_per_launch():

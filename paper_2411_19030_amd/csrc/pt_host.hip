@@ -945,7 +945,7 @@ int run_engine(const EngineDesc &E, const EngineDesc *D, std::vector<LanePlan> &
             const double share = wsum > 0.0 ? rest * p.weight * p.count / wsum : 0.0;
             int q = p.queues > 0 ? std::min(p.queues, p.count)
                                  : std::min(p.count, std::max(1, (int)(share / kMinStreamWgs)));
-            if (p.queues <= 0 && has_sweep) {
+            if (p.queues <= 0 && has_sweep && p.count > 0) {
                 // a sweep consumes these lanes' results slice by slice: run them
                 // in balanced waves on groups of about three tiles per
                 // workgroup, so results arrive in sweep order and a round
